@@ -1,0 +1,146 @@
+/*
+ * csngf.h - C ABI of the MI355X (gfx950) Cross-Sim-NGF hot path.
+ *
+ * Given a fixed volume A and a moving volume B, the library scores candidate 3-D rotations
+ * of B.  For each rotation it resamples B, takes its normalized gradient field, and computes
+ * the masked squared-NGF cross similarity CSNGF(chi) at EVERY integer displacement chi
+ * (Sec. 3.1, Eq. (5)), using the six separable products of Eq. (6) correlated in the
+ * frequency domain against A's precomputed spectra (Eq. (7)-(8)), exact integer overlap
+ * counts N(chi), the minimum-overlap rule gamma (Sec. 3.2) and a per-rotation argmax.
+ * The overall best (score, rotation, displacement) is the alignment (Sec. 3.2, Fig. 1).
+ *
+ * Conventions shared by every call
+ *   - Volumes are float32, C order [nz][ny][nx] (x fastest); masks are uint8 (0 = outside)
+ *     in the same layout.  Each extent must be >= 3.
+ *   - Coordinates and 3x3 matrices use (x, y, z) order; matrices are row-major doubles.
+ *   - A rotation R maps an output voxel x on B's grid to the source point
+ *     p = R (x - c) + c in B, c = (n_B - 1) / 2 (inverse mapping: B^ = B o T_R, Sec. 3.2).
+ *     Entries are rounded to multiples of 2^-16 (ties to even) before use, and must satisfy
+ *     |R_ij| <= 2; the rounded matrix is what the results refer to.
+ *   - B^ is sampled by trilinear interpolation; a voxel of B^ is valid when p lies in the
+ *     closed box [0, n_B - 1] (and, with a mask on B, all 8 corners of its source cell are
+ *     inside the mask).  NGF (Eq. (1), eps from the params) uses central differences with
+ *     unit spacing; masks are eroded by the 7-point stencil so every counted voxel has all
+ *     six neighbours.
+ *   - A displacement chi = (chi_x, chi_y, chi_z) pairs A(x) with B^(x + chi); each component
+ *     lies in [-(n_A - 1), n_B - 1].  chi is valid when N(chi) >= 1 and
+ *     N(chi) >= gamma * min(|M_A|, |M_B^|).  The score is C(chi) = S(chi) / N(chi).
+ *   - Ties: the larger score wins; equal scores go to the smaller canonical index
+ *     (chi_z, chi_y, chi_x lexicographic, ascending); across rotations the smaller rotation
+ *     index wins.
+ *
+ * Errors: every call returns CSNGF_OK (0) or a negative code, leaves its outputs untouched
+ * on error, and records a message readable with csngf_last_error() on the same thread.
+ * No exception or abort crosses the ABI.  One host thread at a time may use a context;
+ * distinct contexts are independent.
+ */
+#ifndef CSNGF_H
+#define CSNGF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CSNGF_OK 0
+#define CSNGF_E_INVALID_ARG (-1)    /* NULL pointer, extent < 3, non-finite input, bad gamma/eps/R */
+#define CSNGF_E_UNSUPPORTED (-2)    /* FFT size not built (see csngf_supported_length), user mask on A */
+#define CSNGF_E_NO_DEVICE (-3)      /* no HIP device visible */
+#define CSNGF_E_OUT_OF_MEMORY (-4)  /* device allocation failed */
+#define CSNGF_E_DEVICE (-5)         /* HIP runtime error; message holds the HIP error text */
+#define CSNGF_E_NO_VALID_SHIFT (-6) /* no displacement met gamma for any rotation; best.score = -inf */
+
+/* params.flags: volumes, masks and map outputs are device pointers; the call is then
+ * stream-ordered on the context's stream and those buffers must stay alive until the
+ * stream has passed it.  Without the flag they are host pointers and calls are
+ * synchronous.  Rotation matrices and result structs are always host memory. */
+#define CSNGF_DEVICE_PTRS 1u
+
+typedef struct csngf_ctx csngf_ctx;
+
+typedef struct {
+  int32_t nx, ny, nz;
+} csngf_dims;
+
+typedef struct {
+  uint32_t struct_size; /* sizeof(csngf_params) */
+  float eps;            /* NGF regulariser, Eq. (1); default 1e-5 */
+  float gamma;          /* minimum overlap fraction in [0, 1], Sec. 3.2; default 0.5 */
+  int32_t pad[3];       /* FFT size (Px, Py, Pz); 0 = smallest supported >= n_A + n_B - 1 */
+  int32_t batch;        /* rotations in flight per launch sequence; 0 = automatic */
+  uint32_t flags;       /* CSNGF_DEVICE_PTRS */
+} csngf_params;
+
+typedef struct {
+  float score;      /* C at the argmax; -inf when no displacement is valid */
+  int32_t shift[3]; /* argmax displacement (chi_x, chi_y, chi_z) */
+  int64_t overlap;  /* N at the argmax (exact) */
+  int32_t valid;    /* 1 when some displacement met gamma */
+  int32_t reserved;
+} csngf_rot_result;
+
+typedef struct {
+  float score;      /* best C over all rotations; -inf when none is valid */
+  int32_t rot_index;/* index into the rotation array; -1 when none is valid */
+  int32_t shift[3];
+  int32_t reserved;
+  int64_t overlap;
+  double R[9];      /* the quantised matrix actually used */
+} csngf_best;
+
+typedef struct {
+  int32_t pad[3];          /* FFT size in use (Px, Py, Pz) */
+  int32_t batch;           /* rotation slots in flight */
+  int32_t map_dims[3];     /* W = n_A + n_B - 1 per axis (x, y, z) */
+  int32_t reserved;
+  int64_t count_a;         /* |M_A| after erosion */
+  int64_t spectra_bytes;   /* device bytes held for A's conjugate spectra */
+  int64_t workspace_bytes; /* device bytes held for rotation workspaces */
+} csngf_info;
+
+/* Fill *out with the defaults (eps 1e-5, gamma 0.5, automatic padding and batch). */
+int csngf_default_params(csngf_params* out);
+
+/* 1 when an FFT of length L is built into the library (L even, 8 <= L <= 512, only prime
+ * factors 2, 3, 5, 7, 11), else 0. */
+int csngf_supported_length(int32_t L);
+
+/* Precompute the fixed side for volume A (dims dA) against moving volumes of dims dB:
+ * NGF of A, its six weighted product fields (cross terms x2, Eq. (6)), their zero-padded
+ * 3-D FFTs, conjugated and kept resident on the device (Sec. 3.1, Eq. (7)-(8)).
+ * maskA must be NULL (full domain; eroded to the box [1, n_A - 2]) - a user mask on A
+ * returns CSNGF_E_UNSUPPORTED.  A is copied; the caller may free it on return.
+ * p may be NULL for the defaults.  On success *out owns all device memory. */
+int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims dB,
+                 const csngf_params* p, csngf_ctx** out);
+
+/* Use the given hipStream_t (e.g. PyTorch's current stream) for all later work; NULL
+ * restores the context's own stream.  The caller keeps ownership of the stream. */
+int csngf_set_stream(csngf_ctx* ctx, void* hip_stream);
+
+int csngf_get_info(const csngf_ctx* ctx, csngf_info* out);
+
+/* Score n rotations (R: n x 9 row-major doubles, host) of moving volume B (dims dB of the
+ * context; maskB NULL = full domain).  per_rot (host, n entries) may be NULL; best (host)
+ * may be NULL.  Returns CSNGF_E_NO_VALID_SHIFT when no rotation has a valid displacement
+ * (per_rot still filled).  n == 0 is valid: best->rot_index = -1. */
+int csngf_evaluate(csngf_ctx* ctx, const float* B, const uint8_t* maskB, const double* R,
+                   int32_t n, csngf_rot_result* per_rot, csngf_best* best);
+
+/* Full maps for one rotation (diagnosis and parity): C[Wz][Wy][Wx] float32 with -inf where
+ * chi is invalid, and optionally N[Wz][Wy][Wx] int64 (may be NULL).  Index i = chi + n_A - 1
+ * per axis.  Host or device pointers per params.flags. */
+int csngf_evaluate_map(csngf_ctx* ctx, const float* B, const uint8_t* maskB, const double* R9,
+                       float* C, int64_t* N);
+
+int csngf_destroy(csngf_ctx* ctx);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* csngf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CSNGF_H */

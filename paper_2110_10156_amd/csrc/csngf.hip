@@ -1,0 +1,926 @@
+// Host runtime and C ABI of the CSNGF hot path (see include/csngf.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "csngf.h"
+#include "csngf_debug.h"
+#include "csngf_kernels.hpp"
+
+using namespace csngf;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  const int code = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? CSNGF_E_OUT_OF_MEMORY
+                                                                               : CSNGF_E_DEVICE;
+  return fail(code, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(expr)                              \
+  do {                                            \
+    hipError_t e_ = (expr);                       \
+    if (e_ != hipSuccess) return hip_fail(e_, #expr); \
+  } while (0)
+
+#define LAUNCHCHK(what)                                   \
+  do {                                                    \
+    hipError_t e_ = hipGetLastError();                    \
+    if (e_ != hipSuccess) return hip_fail(e_, what);      \
+  } while (0)
+
+// ---------------------------------------------------------------- FFT plans
+bool factor_plan(int L, FftPlan& pl) {
+  if (L < 2 || L > kMaxLen) return false;
+  std::memset(&pl, 0, sizeof(pl));
+  int n = L, st = 0;
+  const int odd[] = {11, 7, 5, 3};
+  for (int r : odd)
+    while (n % r == 0) {
+      if (st >= kMaxStages) return false;
+      pl.radix[st++] = r;
+      n /= r;
+    }
+  while (n % 8 == 0) { pl.radix[st++] = 8; n /= 8; }
+  while (n % 4 == 0) { pl.radix[st++] = 4; n /= 4; }
+  while (n % 2 == 0) { pl.radix[st++] = 2; n /= 2; }
+  if (n != 1) return false;
+  pl.L = L;
+  pl.nst = st;
+  int ns = 1;
+  for (int s = 0; s < st; ++s) {
+    pl.ns[s] = ns;
+    ns *= pl.radix[s];
+  }
+  return true;
+}
+
+bool supported(int L) {
+  FftPlan pl;
+  return L >= 8 && L <= kMaxLen && (L % 2) == 0 && factor_plan(L, pl);
+}
+
+int smallest_supported_at_least(int need) {
+  for (int L = std::max(8, need); L <= kMaxLen; ++L)
+    if (supported(L)) return L;
+  return -1;
+}
+
+void twiddles(int L, std::vector<float2>& out) {
+  for (int j = 0; j < L; ++j) {
+    const double a = -2.0 * M_PI * (double)j / (double)L;
+    out.push_back(make_float2((float)std::cos(a), (float)std::sin(a)));
+  }
+}
+
+size_t a16(size_t b) { return (b + 15) & ~size_t(15); }
+
+size_t lds_fields(int Px, int nx) {
+  return a16(sizeof(float2) * Px) + a16(sizeof(float2) * Px * kRowsX) + a16(sizeof(float) * 3 * (kRowsX + 2) * nx) +
+         a16((size_t)3 * (kRowsX + 2) * nx);
+}
+size_t lds_pencil(int L) { return a16(sizeof(float2) * L) + a16(sizeof(float2) * L * kTileW); }
+size_t lds_final(int Px) { return a16(sizeof(float2) * Px) + a16(sizeof(float2) * Px * kRowsX); }
+
+constexpr size_t kLdsDefault = 64 * 1024;
+constexpr size_t kLdsMax = 160 * 1024;
+
+template <typename K>
+hipError_t allow_lds(K kernel, size_t bytes) {
+  if (bytes <= kLdsDefault) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bytes);
+}
+
+int quantise(const double* R, int* k, double* Rq) {
+  for (int i = 0; i < 9; ++i) {
+    const double v = R[i];
+    if (!std::isfinite(v) || std::fabs(v) > 2.0) return -1;
+    const double q = std::nearbyint(v * 65536.0);  // round half to even (default mode)
+    k[i] = (int)q;
+    if (Rq) Rq[i] = q / 65536.0;
+  }
+  return 0;
+}
+
+bool all_finite(const float* v, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(v[i])) return false;
+  return true;
+}
+
+enum KType { KT_FIELDS, KT_SAT, KT_YFWD, KT_ZPASS, KT_YINV, KT_FINAL, KT_MISC, KT_COUNT };
+const char* kTypeName[KT_COUNT] = {"fields_x", "overlap_sat", "y_forward", "z_mac_inverse",
+                                   "y_inverse", "x_c2r_argmax", "misc"};
+
+struct PendingEv {
+  int type;
+  hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct csngf_ctx {
+  int dev = 0;
+  hipStream_t own_stream = nullptr;
+  hipStream_t stream = nullptr;
+  int nA[3] = {0, 0, 0}, nB[3] = {0, 0, 0};  // x, y, z
+  int P[3] = {0, 0, 0};
+  int Wd[3] = {0, 0, 0};
+  int H = 0, Hp = 0, tiles = 0;
+  float eps = 1e-5f, gamma = 0.5f;
+  uint32_t flags = 0;
+  int batch = 1;
+  FftPlan plx{}, ply{}, plz{};
+  float2* d_tw = nullptr;
+  float2* d_spec = nullptr;
+  long long spec_bytes = 0;
+  long long count_a = 0;
+  float2* d_buf1 = nullptr;
+  float2* d_buf2 = nullptr;
+  long long buf1_slot = 0, buf2_slot = 0;
+  uint8_t* d_mask = nullptr;
+  long long mask_slot = 0;
+  int* d_sat = nullptr;
+  long long sat_slot = 0;
+  unsigned long long* d_keys = nullptr;
+  RotResultDev* d_res = nullptr;
+  int res_cap = 0;
+  int* d_rot = nullptr;
+  int rot_cap = 0;
+  float* d_B = nullptr;
+  uint8_t* d_mB = nullptr;
+  int* d_flag = nullptr;
+  RotResultDev* h_res = nullptr;
+  int h_res_cap = 0;
+  int* h_rot = nullptr;
+  int h_rot_cap = 0;
+  long long workspace_bytes = 0;
+  bool prof = false;
+  std::vector<PendingEv> pending;
+  std::vector<hipEvent_t> ev_pool;
+  long long stat_launches[KT_COUNT] = {0};
+  double stat_ms[KT_COUNT] = {0};
+};
+
+namespace {
+
+hipError_t ev_get(csngf_ctx* c, hipEvent_t* e) {
+  if (!c->ev_pool.empty()) {
+    *e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return hipSuccess;
+  }
+  return hipEventCreate(e);
+}
+
+// Record a start event (profiling) before a launch; returns the event or nullptr.
+hipEvent_t prof_begin(csngf_ctx* c) {
+  if (!c->prof) return nullptr;
+  hipEvent_t e = nullptr;
+  if (ev_get(c, &e) != hipSuccess) return nullptr;
+  hipEventRecord(e, c->stream);
+  return e;
+}
+
+void prof_end(csngf_ctx* c, int type, hipEvent_t start) {
+  if (!start) return;
+  hipEvent_t e = nullptr;
+  if (ev_get(c, &e) != hipSuccess) return;
+  hipEventRecord(e, c->stream);
+  c->pending.push_back({type, start, e});
+}
+
+void prof_fold(csngf_ctx* c) {
+  for (auto& p : c->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      c->stat_ms[p.type] += ms;
+      c->stat_launches[p.type] += 1;
+    }
+    c->ev_pool.push_back(p.a);
+    c->ev_pool.push_back(p.b);
+  }
+  c->pending.clear();
+}
+
+template <typename T>
+void dfree(T*& p) {
+  if (p) hipFree(p);
+  p = nullptr;
+}
+
+void release(csngf_ctx* c) {
+  if (!c) return;
+  hipSetDevice(c->dev);
+  if (c->stream) hipStreamSynchronize(c->stream);
+  dfree(c->d_tw);
+  dfree(c->d_spec);
+  dfree(c->d_buf1);
+  dfree(c->d_buf2);
+  dfree(c->d_mask);
+  dfree(c->d_sat);
+  dfree(c->d_keys);
+  dfree(c->d_res);
+  dfree(c->d_rot);
+  dfree(c->d_B);
+  dfree(c->d_mB);
+  dfree(c->d_flag);
+  if (c->h_res) hipHostFree(c->h_res);
+  if (c->h_rot) hipHostFree(c->h_rot);
+  for (auto& p : c->pending) {
+    hipEventDestroy(p.a);
+    hipEventDestroy(p.b);
+  }
+  for (auto e : c->ev_pool) hipEventDestroy(e);
+  if (c->own_stream) hipStreamDestroy(c->own_stream);
+  delete c;
+}
+
+int check_device() {
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n <= 0) {
+    (void)hipGetLastError();
+    return fail(CSNGF_E_NO_DEVICE, "no HIP device visible");
+  }
+  return CSNGF_OK;
+}
+
+int check_dims(const csngf_dims& d, const char* what) {
+  if (d.nx < 3 || d.ny < 3 || d.nz < 3)
+    return fail(CSNGF_E_INVALID_ARG, std::string(what) + ": every extent must be >= 3");
+  if (d.nx > kMaxLen || d.ny > kMaxLen || d.nz > kMaxLen)
+    return fail(CSNGF_E_UNSUPPORTED, std::string(what) + ": extent above 512");
+  return CSNGF_OK;
+}
+
+// Launch helpers -------------------------------------------------------------------------
+int lmax_class(int L) { return L <= 256 ? 256 : 512; }
+
+int launch_pencil(csngf_ctx* c, bool inv, const float2* in, float2* out, int n_in, int n_out, int out_off,
+                  const FftPlan& pl, long long in_g, long long out_g, int groups, long long in_s,
+                  long long out_s, int slots) {
+  const dim3 grid(c->tiles, groups, slots);
+  const size_t lds = lds_pencil(pl.L);
+  hipEvent_t ev = prof_begin(c);
+  if (!inv) {
+    if (lmax_class(pl.L) == 256)
+      hipLaunchKernelGGL((k_pencil<false, 256>), grid, dim3(kThreads), lds, c->stream, in, out, n_in, n_out, out_off,
+                         pl, c->d_tw, c->H, c->Hp, in_g, out_g, in_s, out_s);
+    else
+      hipLaunchKernelGGL((k_pencil<false, 512>), grid, dim3(kThreads), lds, c->stream, in, out, n_in, n_out, out_off,
+                         pl, c->d_tw, c->H, c->Hp, in_g, out_g, in_s, out_s);
+  } else {
+    if (lmax_class(pl.L) == 256)
+      hipLaunchKernelGGL((k_pencil<true, 256>), grid, dim3(kThreads), lds, c->stream, in, out, n_in, n_out, out_off,
+                         pl, c->d_tw, c->H, c->Hp, in_g, out_g, in_s, out_s);
+    else
+      hipLaunchKernelGGL((k_pencil<true, 512>), grid, dim3(kThreads), lds, c->stream, in, out, n_in, n_out, out_off,
+                         pl, c->d_tw, c->H, c->Hp, in_g, out_g, in_s, out_s);
+  }
+  prof_end(c, inv ? KT_YINV : KT_YFWD, ev);
+  LAUNCHCHK(inv ? "k_pencil<inverse>" : "k_pencil<forward>");
+  return CSNGF_OK;
+}
+
+int launch_fields(csngf_ctx* c, bool moving, const float* vol, const uint8_t* um, const int* n3, const int* rotq,
+                  float2* out, long long out_slot, uint8_t* mask_out, long long mask_slot, float* dbg, int slots) {
+  const dim3 grid((n3[1] + kRowsX - 1) / kRowsX, n3[2], slots);
+  const size_t lds = lds_fields(c->plx.L, n3[0]);
+  if (lds > kLdsMax) return fail(CSNGF_E_UNSUPPORTED, "x extent too large for the field stage");
+  hipEvent_t ev = prof_begin(c);
+  if (moving) {
+    HIPCHK(allow_lds(k_fields_x<true>, lds));
+    hipLaunchKernelGGL(k_fields_x<true>, grid, dim3(kThreads), lds, c->stream, vol, um, n3[0], n3[1], n3[2], rotq,
+                       c->eps, c->plx, c->d_tw, out, c->H, c->Hp, out_slot, mask_out, mask_slot, dbg);
+  } else {
+    HIPCHK(allow_lds(k_fields_x<false>, lds));
+    hipLaunchKernelGGL(k_fields_x<false>, grid, dim3(kThreads), lds, c->stream, vol, um, n3[0], n3[1], n3[2], rotq,
+                       c->eps, c->plx, c->d_tw, out, c->H, c->Hp, out_slot, mask_out, mask_slot, dbg);
+  }
+  prof_end(c, KT_FIELDS, ev);
+  LAUNCHCHK("k_fields_x");
+  return CSNGF_OK;
+}
+
+// One launch sequence over `slots` rotations whose Q16 tables start at rotq (device).
+int run_batch(csngf_ctx* c, const float* dB, const uint8_t* dmB, const int* rotq, int slots, RotResultDev* res,
+              float* cmap, long long* nmap) {
+  int rc;
+  hipEvent_t ev;
+  {
+    ev = prof_begin(c);
+    hipLaunchKernelGGL(k_fill_u64, dim3((slots + 63) / 64), dim3(64), 0, c->stream, c->d_keys, slots, 0ull);
+    prof_end(c, KT_MISC, ev);
+    LAUNCHCHK("k_fill_u64");
+  }
+  rc = launch_fields(c, true, dB, dmB, c->nB, rotq, c->d_buf1, c->buf1_slot, c->d_mask, c->mask_slot, nullptr, slots);
+  if (rc) return rc;
+  {
+    const int nx = c->nB[0], ny = c->nB[1], nz = c->nB[2];
+    ev = prof_begin(c);
+    const int rows = (nz + 1) * (ny + 1);
+    hipLaunchKernelGGL(k_sat_rows, dim3((rows + 3) / 4, slots), dim3(kThreads), 0, c->stream, c->d_mask, c->d_sat,
+                       nx, ny, nz, c->mask_slot, c->sat_slot);
+    hipLaunchKernelGGL(k_sat_cols, dim3((nz * nx + kThreads - 1) / kThreads, slots), dim3(kThreads), 0, c->stream,
+                       c->d_sat, nx, ny, nz, c->sat_slot, 0);
+    hipLaunchKernelGGL(k_sat_cols, dim3((ny * nx + kThreads - 1) / kThreads, slots), dim3(kThreads), 0, c->stream,
+                       c->d_sat, nx, ny, nz, c->sat_slot, 1);
+    prof_end(c, KT_SAT, ev);
+    LAUNCHCHK("k_sat");
+  }
+  // y forward: X1 [slot][f][z][y] -> X2 [slot][f][z][ky]
+  rc = launch_pencil(c, false, c->d_buf1, c->d_buf2, c->nB[1], c->P[1], 0, c->ply, (long long)c->nB[1] * c->Hp,
+                     (long long)c->P[1] * c->Hp, 6 * c->nB[2], c->buf1_slot, c->buf2_slot, slots);
+  if (rc) return rc;
+  {
+    const int nreal = c->P[1] * c->tiles * slots;
+    const int nb8 = (nreal + 7) / 8 * 8;
+    const size_t lds = lds_pencil(c->plz.L);
+    const int out_off = c->P[2] - (c->nA[2] - 1);
+    ev = prof_begin(c);
+    if (lmax_class(c->plz.L) == 256)
+      hipLaunchKernelGGL((k_zpass<256>), dim3(nb8), dim3(kThreads), lds, c->stream, c->d_buf2, c->d_spec, c->d_buf1,
+                         c->nB[2], c->P[1], c->H, c->Hp, c->Wd[2], out_off, c->plz, c->d_tw, c->buf2_slot,
+                         c->buf1_slot, c->tiles, slots, nreal);
+    else
+      hipLaunchKernelGGL((k_zpass<512>), dim3(nb8), dim3(kThreads), lds, c->stream, c->d_buf2, c->d_spec, c->d_buf1,
+                         c->nB[2], c->P[1], c->H, c->Hp, c->Wd[2], out_off, c->plz, c->d_tw, c->buf2_slot,
+                         c->buf1_slot, c->tiles, slots, nreal);
+    prof_end(c, KT_ZPASS, ev);
+    LAUNCHCHK("k_zpass");
+  }
+  // y inverse: Y3 [slot][zc][ky] -> Y4 [slot][zc][yc]
+  rc = launch_pencil(c, true, c->d_buf1, c->d_buf2, c->P[1], c->Wd[1], c->P[1] - (c->nA[1] - 1), c->ply,
+                     (long long)c->P[1] * c->Hp, (long long)c->Wd[1] * c->Hp, c->Wd[2], c->buf1_slot, c->buf2_slot,
+                     slots);
+  if (rc) return rc;
+  {
+    OverlapGeom g;
+    for (int i = 0; i < 3; ++i) {
+      g.nA[i] = c->nA[i];
+      g.nB[i] = c->nB[i];
+    }
+    const dim3 grid((c->Wd[1] + 2 * kRowsX - 1) / (2 * kRowsX), c->Wd[2], slots);
+    const size_t lds = lds_final(c->plx.L);
+    ev = prof_begin(c);
+    if (cmap) {
+      HIPCHK(allow_lds(k_final_x<true>, lds));
+      hipLaunchKernelGGL(k_final_x<true>, grid, dim3(kThreads), lds, c->stream, c->d_buf2, c->d_sat, c->d_keys, g,
+                         c->Wd[0], c->Wd[1], c->Wd[2], c->H, c->Hp, c->plx, c->d_tw, c->buf2_slot, c->sat_slot,
+                         c->count_a, c->gamma, cmap, nmap);
+    } else {
+      HIPCHK(allow_lds(k_final_x<false>, lds));
+      hipLaunchKernelGGL(k_final_x<false>, grid, dim3(kThreads), lds, c->stream, c->d_buf2, c->d_sat, c->d_keys, g,
+                         c->Wd[0], c->Wd[1], c->Wd[2], c->H, c->Hp, c->plx, c->d_tw, c->buf2_slot, c->sat_slot,
+                         c->count_a, c->gamma, cmap, nmap);
+    }
+    prof_end(c, KT_FINAL, ev);
+    LAUNCHCHK("k_final_x");
+    ev = prof_begin(c);
+    hipLaunchKernelGGL(k_finalize, dim3((slots + 63) / 64), dim3(64), 0, c->stream, c->d_keys, c->d_sat, g, c->Wd[0],
+                       c->Wd[1], c->sat_slot, slots, res);
+    prof_end(c, KT_MISC, ev);
+    LAUNCHCHK("k_finalize");
+  }
+  return CSNGF_OK;
+}
+
+template <typename T>
+int dalloc(T** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(p), bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return fail(CSNGF_E_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " +
+                                           hipGetErrorString(e));
+  }
+  return CSNGF_OK;
+}
+
+int ensure_rot_capacity(csngf_ctx* c, int n) {
+  if (n <= c->rot_cap && n <= c->h_rot_cap && n <= c->res_cap && n <= c->h_res_cap) return CSNGF_OK;
+  const int cap = std::max(n, 64);
+  dfree(c->d_rot);
+  dfree(c->d_res);
+  if (c->h_rot) hipHostFree(c->h_rot);
+  if (c->h_res) hipHostFree(c->h_res);
+  c->h_rot = nullptr;
+  c->h_res = nullptr;
+  c->rot_cap = c->res_cap = c->h_rot_cap = c->h_res_cap = 0;
+  int rc = dalloc(&c->d_rot, sizeof(int) * 9 * (size_t)cap);
+  if (rc) return rc;
+  rc = dalloc(&c->d_res, sizeof(RotResultDev) * (size_t)cap);
+  if (rc) return rc;
+  HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&c->h_rot), sizeof(int) * 9 * (size_t)cap));
+  HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&c->h_res), sizeof(RotResultDev) * (size_t)cap));
+  c->rot_cap = c->res_cap = c->h_rot_cap = c->h_res_cap = cap;
+  return CSNGF_OK;
+}
+
+// Stage the moving volume (and mask) on the device; device-pointer inputs are checked for
+// non-finite values by a kernel whose flag is read after the call's final synchronisation.
+int stage_moving(csngf_ctx* c, const float* B, const uint8_t* maskB, const float** dB, const uint8_t** dmB) {
+  const size_t nv = (size_t)c->nB[0] * c->nB[1] * c->nB[2];
+  if (c->flags & CSNGF_DEVICE_PTRS) {
+    *dB = B;
+    *dmB = maskB;
+    HIPCHK(hipMemsetAsync(c->d_flag, 0, sizeof(int), c->stream));
+    hipLaunchKernelGGL(k_check_finite, dim3(1024), dim3(256), 0, c->stream, B, (long long)nv, c->d_flag);
+    LAUNCHCHK("k_check_finite");
+    return CSNGF_OK;
+  }
+  if (!all_finite(B, nv)) return fail(CSNGF_E_INVALID_ARG, "moving volume B has a non-finite value");
+  if (!c->d_B) {
+    int rc = dalloc(&c->d_B, sizeof(float) * nv);
+    if (rc) return rc;
+  }
+  HIPCHK(hipMemcpyAsync(c->d_B, B, sizeof(float) * nv, hipMemcpyHostToDevice, c->stream));
+  *dB = c->d_B;
+  *dmB = nullptr;
+  if (maskB) {
+    if (!c->d_mB) {
+      int rc = dalloc(&c->d_mB, nv);
+      if (rc) return rc;
+    }
+    HIPCHK(hipMemcpyAsync(c->d_mB, maskB, nv, hipMemcpyHostToDevice, c->stream));
+    *dmB = c->d_mB;
+  }
+  return CSNGF_OK;
+}
+
+int read_flag(csngf_ctx* c, int* bad) {
+  *bad = 0;
+  if (!(c->flags & CSNGF_DEVICE_PTRS)) return CSNGF_OK;
+  HIPCHK(hipMemcpy(bad, c->d_flag, sizeof(int), hipMemcpyDeviceToHost));
+  return CSNGF_OK;
+}
+
+}  // namespace
+
+// =================================================================================== ABI
+extern "C" {
+
+const char* csngf_last_error(void) { return g_err.c_str(); }
+
+int csngf_default_params(csngf_params* out) {
+  if (!out) return fail(CSNGF_E_INVALID_ARG, "params is NULL");
+  std::memset(out, 0, sizeof(*out));
+  out->struct_size = sizeof(csngf_params);
+  out->eps = 1e-5f;
+  out->gamma = 0.5f;
+  return CSNGF_OK;
+}
+
+int csngf_supported_length(int32_t L) { return supported(L) ? 1 : 0; }
+
+int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims dB, const csngf_params* p,
+                 csngf_ctx** out) {
+  if (!out) return fail(CSNGF_E_INVALID_ARG, "out is NULL");
+  if (!A) return fail(CSNGF_E_INVALID_ARG, "fixed volume A is NULL");
+  csngf_params prm;
+  csngf_default_params(&prm);
+  if (p) {
+    if (p->struct_size != sizeof(csngf_params)) return fail(CSNGF_E_INVALID_ARG, "params.struct_size mismatch");
+    prm = *p;
+  }
+  int rc = check_dims(dA, "A");
+  if (rc) return rc;
+  rc = check_dims(dB, "B");
+  if (rc) return rc;
+  if (!(prm.eps > 0.f) || !std::isfinite(prm.eps)) return fail(CSNGF_E_INVALID_ARG, "eps must be finite and > 0");
+  if (!(prm.gamma >= 0.f && prm.gamma <= 1.f)) return fail(CSNGF_E_INVALID_ARG, "gamma must lie in [0, 1]");
+  if (prm.batch < 0) return fail(CSNGF_E_INVALID_ARG, "batch must be >= 0");
+  if (prm.flags & ~CSNGF_DEVICE_PTRS) return fail(CSNGF_E_INVALID_ARG, "unknown flag bits");
+  if (maskA) return fail(CSNGF_E_UNSUPPORTED, "a user mask on the fixed volume is not supported (pass NULL)");
+  const int nA[3] = {dA.nx, dA.ny, dA.nz}, nB[3] = {dB.nx, dB.ny, dB.nz};
+  int P[3];
+  for (int i = 0; i < 3; ++i) {
+    const int need = nA[i] + nB[i] - 1;
+    if (prm.pad[i] == 0) {
+      P[i] = smallest_supported_at_least(need);
+      if (P[i] < 0) return fail(CSNGF_E_UNSUPPORTED, "no supported FFT size >= n_A + n_B - 1 (max 512)");
+    } else {
+      if (prm.pad[i] < need) return fail(CSNGF_E_INVALID_ARG, "pad smaller than n_A + n_B - 1");
+      if (!supported(prm.pad[i])) return fail(CSNGF_E_UNSUPPORTED, "pad length not supported by the FFT");
+      P[i] = prm.pad[i];
+    }
+  }
+  const size_t nvA = (size_t)dA.nx * dA.ny * dA.nz;
+  if (!(prm.flags & CSNGF_DEVICE_PTRS) && !all_finite(A, nvA))
+    return fail(CSNGF_E_INVALID_ARG, "fixed volume A has a non-finite value");
+  rc = check_device();
+  if (rc) return rc;
+
+  csngf_ctx* c = new csngf_ctx();
+  auto bail = [&](int code) {
+    std::string keep = g_err;
+    release(c);
+    g_err = keep;
+    return code;
+  };
+  HIPCHK(hipGetDevice(&c->dev));
+  if (hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking) != hipSuccess)
+    return bail(hip_fail(hipGetLastError(), "hipStreamCreateWithFlags"));
+  c->stream = c->own_stream;
+  for (int i = 0; i < 3; ++i) {
+    c->nA[i] = nA[i];
+    c->nB[i] = nB[i];
+    c->P[i] = P[i];
+    c->Wd[i] = nA[i] + nB[i] - 1;
+  }
+  c->eps = prm.eps;
+  c->gamma = prm.gamma;
+  c->flags = prm.flags;
+  c->H = P[0] / 2 + 1;
+  c->Hp = (c->H + kTileW - 1) / kTileW * kTileW;
+  c->tiles = c->Hp / kTileW;
+  factor_plan(P[0], c->plx);
+  factor_plan(P[1], c->ply);
+  factor_plan(P[2], c->plz);
+  {
+    std::vector<float2> tw;
+    c->plx.tw_off = (int)tw.size();
+    twiddles(P[0], tw);
+    c->ply.tw_off = (int)tw.size();
+    twiddles(P[1], tw);
+    c->plz.tw_off = (int)tw.size();
+    twiddles(P[2], tw);
+    if ((rc = dalloc(&c->d_tw, sizeof(float2) * tw.size()))) return bail(rc);
+    if (hipMemcpy(c->d_tw, tw.data(), sizeof(float2) * tw.size(), hipMemcpyHostToDevice) != hipSuccess)
+      return bail(hip_fail(hipGetLastError(), "twiddle upload"));
+  }
+  const long long Hp = c->Hp;
+  c->count_a = (long long)(nA[0] - 2) * (nA[1] - 2) * (nA[2] - 2);
+  c->spec_bytes = (long long)sizeof(float2) * 6 * P[2] * P[1] * Hp;
+  if ((rc = dalloc(&c->d_spec, (size_t)c->spec_bytes))) return bail(rc);
+  if ((rc = dalloc(&c->d_flag, sizeof(int)))) return bail(rc);
+
+  // ---- fixed side: fields of A, y forward, z forward + conjugate store
+  {
+    const float* dA_ptr = A;
+    float* tmpA = nullptr;
+    if (!(prm.flags & CSNGF_DEVICE_PTRS)) {
+      if ((rc = dalloc(&tmpA, sizeof(float) * nvA))) return bail(rc);
+      if (hipMemcpy(tmpA, A, sizeof(float) * nvA, hipMemcpyHostToDevice) != hipSuccess) {
+        hipFree(tmpA);
+        return bail(hip_fail(hipGetLastError(), "upload of A"));
+      }
+      dA_ptr = tmpA;
+    }
+    float2 *x1 = nullptr, *x2 = nullptr;
+    const long long x1e = 6LL * nA[2] * nA[1] * Hp, x2e = 6LL * nA[2] * P[1] * Hp;
+    rc = dalloc(&x1, sizeof(float2) * x1e);
+    if (!rc) rc = dalloc(&x2, sizeof(float2) * x2e);
+    if (!rc && (prm.flags & CSNGF_DEVICE_PTRS)) {
+      HIPCHK(hipMemsetAsync(c->d_flag, 0, sizeof(int), c->stream));
+      hipLaunchKernelGGL(k_check_finite, dim3(1024), dim3(256), 0, c->stream, A, (long long)nvA, c->d_flag);
+    }
+    if (!rc) rc = launch_fields(c, false, dA_ptr, nullptr, nA, nullptr, x1, 0, nullptr, 0, nullptr, 1);
+    if (!rc)
+      rc = launch_pencil(c, false, x1, x2, nA[1], P[1], 0, c->ply, (long long)nA[1] * Hp, (long long)P[1] * Hp,
+                         6 * nA[2], 0, 0, 1);
+    if (!rc) {
+      const float scale = (float)(1.0 / ((double)P[0] * (double)P[1] * (double)P[2]));
+      const dim3 grid(c->tiles, P[1], 6);
+      const size_t lds = lds_pencil(P[2]);
+      if (lmax_class(P[2]) == 256)
+        hipLaunchKernelGGL((k_zstore<256>), grid, dim3(kThreads), lds, c->stream, x2, c->d_spec, nA[2], P[1], c->H,
+                           c->Hp, c->plz, c->d_tw, scale);
+      else
+        hipLaunchKernelGGL((k_zstore<512>), grid, dim3(kThreads), lds, c->stream, x2, c->d_spec, nA[2], P[1], c->H,
+                           c->Hp, c->plz, c->d_tw, scale);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) rc = hip_fail(e, "k_zstore");
+    }
+    hipError_t se = hipStreamSynchronize(c->stream);
+    if (!rc && se != hipSuccess) rc = hip_fail(se, "fixed-side precompute");
+    if (x1) hipFree(x1);
+    if (x2) hipFree(x2);
+    if (tmpA) hipFree(tmpA);
+    if (rc) return bail(rc);
+    int bad = 0;
+    if ((rc = read_flag(c, &bad))) return bail(rc);
+    if (bad) return bail(fail(CSNGF_E_INVALID_ARG, "fixed volume A has a non-finite value"));
+  }
+
+  // ---- rotation workspaces
+  {
+    const long long nvB = (long long)nB[0] * nB[1] * nB[2];
+    c->buf1_slot = std::max(6LL * nB[2] * nB[1], (long long)c->Wd[2] * P[1]) * Hp;
+    c->buf2_slot = std::max(6LL * nB[2] * P[1], (long long)c->Wd[2] * c->Wd[1]) * Hp;
+    c->mask_slot = (nvB + 255) / 256 * 256;
+    c->sat_slot = ((long long)(nB[0] + 1) * (nB[1] + 1) * (nB[2] + 1) + 63) / 64 * 64;
+    const long long per = sizeof(float2) * (c->buf1_slot + c->buf2_slot) + c->mask_slot + 4 * c->sat_slot;
+    int batch = prm.batch;
+    if (batch == 0) {
+      size_t fr = 0, tot = 0;
+      long long budget = 8LL << 30;
+      if (hipMemGetInfo(&fr, &tot) == hipSuccess) budget = std::min<long long>(budget, (long long)(fr / 4));
+      batch = (int)std::max(1LL, std::min(64LL, budget / per));
+    }
+    c->batch = batch;
+    if ((rc = dalloc(&c->d_buf1, sizeof(float2) * c->buf1_slot * batch))) return bail(rc);
+    if ((rc = dalloc(&c->d_buf2, sizeof(float2) * c->buf2_slot * batch))) return bail(rc);
+    if ((rc = dalloc(&c->d_mask, (size_t)c->mask_slot * batch))) return bail(rc);
+    if ((rc = dalloc(&c->d_sat, 4 * (size_t)c->sat_slot * batch))) return bail(rc);
+    if ((rc = dalloc(&c->d_keys, sizeof(unsigned long long) * batch))) return bail(rc);
+    c->workspace_bytes = per * batch;
+  }
+  *out = c;
+  return CSNGF_OK;
+}
+
+int csngf_set_stream(csngf_ctx* c, void* s) {
+  if (!c) return fail(CSNGF_E_INVALID_ARG, "ctx is NULL");
+  c->stream = s ? reinterpret_cast<hipStream_t>(s) : c->own_stream;
+  return CSNGF_OK;
+}
+
+int csngf_get_info(const csngf_ctx* c, csngf_info* o) {
+  if (!c || !o) return fail(CSNGF_E_INVALID_ARG, "NULL argument");
+  std::memset(o, 0, sizeof(*o));
+  for (int i = 0; i < 3; ++i) {
+    o->pad[i] = c->P[i];
+    o->map_dims[i] = c->Wd[i];
+  }
+  o->batch = c->batch;
+  o->count_a = c->count_a;
+  o->spectra_bytes = c->spec_bytes;
+  o->workspace_bytes = c->workspace_bytes;
+  return CSNGF_OK;
+}
+
+int csngf_evaluate(csngf_ctx* c, const float* B, const uint8_t* maskB, const double* R, int32_t n,
+                   csngf_rot_result* per_rot, csngf_best* best) {
+  if (!c) return fail(CSNGF_E_INVALID_ARG, "ctx is NULL");
+  if (!B) return fail(CSNGF_E_INVALID_ARG, "moving volume B is NULL");
+  if (n < 0) return fail(CSNGF_E_INVALID_ARG, "n must be >= 0");
+  if (n > 0 && !R) return fail(CSNGF_E_INVALID_ARG, "rotations are NULL");
+  if (n == 0) {
+    if (best) {
+      std::memset(best, 0, sizeof(*best));
+      best->score = -INFINITY;
+      best->rot_index = -1;
+    }
+    return CSNGF_OK;
+  }
+  std::vector<int> kq((size_t)n * 9);
+  for (int r = 0; r < n; ++r)
+    if (quantise(R + 9 * (size_t)r, &kq[9 * (size_t)r], nullptr))
+      return fail(CSNGF_E_INVALID_ARG, "rotation " + std::to_string(r) + " has a non-finite entry or |R_ij| > 2");
+  HIPCHK(hipSetDevice(c->dev));
+  int rc = ensure_rot_capacity(c, n);
+  if (rc) return rc;
+  const float* dB = nullptr;
+  const uint8_t* dmB = nullptr;
+  if ((rc = stage_moving(c, B, maskB, &dB, &dmB))) return rc;
+  std::memcpy(c->h_rot, kq.data(), sizeof(int) * 9 * (size_t)n);
+  HIPCHK(hipMemcpyAsync(c->d_rot, c->h_rot, sizeof(int) * 9 * (size_t)n, hipMemcpyHostToDevice, c->stream));
+  for (int base = 0; base < n; base += c->batch) {
+    const int m = std::min(c->batch, n - base);
+    if ((rc = run_batch(c, dB, dmB, c->d_rot + 9 * (size_t)base, m, c->d_res + base, nullptr, nullptr))) return rc;
+  }
+  HIPCHK(hipMemcpyAsync(c->h_res, c->d_res, sizeof(RotResultDev) * (size_t)n, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  int bad = 0;
+  if ((rc = read_flag(c, &bad))) return rc;
+  if (bad) return fail(CSNGF_E_INVALID_ARG, "moving volume B has a non-finite value");
+  int bi = -1;
+  for (int r = 0; r < n; ++r) {
+    const RotResultDev& x = c->h_res[r];
+    if (x.valid && (bi < 0 || x.score > c->h_res[bi].score)) bi = r;
+  }
+  if (per_rot) std::memcpy(per_rot, c->h_res, sizeof(csngf_rot_result) * (size_t)n);
+  if (best) {
+    std::memset(best, 0, sizeof(*best));
+    best->rot_index = bi;
+    if (bi < 0) {
+      best->score = -INFINITY;
+    } else {
+      const RotResultDev& x = c->h_res[bi];
+      best->score = x.score;
+      for (int i = 0; i < 3; ++i) best->shift[i] = x.shift[i];
+      best->overlap = x.overlap;
+      for (int i = 0; i < 9; ++i) best->R[i] = kq[9 * (size_t)bi + i] / 65536.0;
+    }
+  }
+  if (bi < 0) return fail(CSNGF_E_NO_VALID_SHIFT, "no displacement meets the minimum overlap for any rotation");
+  return CSNGF_OK;
+}
+
+int csngf_evaluate_map(csngf_ctx* c, const float* B, const uint8_t* maskB, const double* R9, float* C,
+                       int64_t* N) {
+  if (!c) return fail(CSNGF_E_INVALID_ARG, "ctx is NULL");
+  if (!B || !R9 || !C) return fail(CSNGF_E_INVALID_ARG, "NULL argument");
+  int kq[9];
+  if (quantise(R9, kq, nullptr)) return fail(CSNGF_E_INVALID_ARG, "rotation has a non-finite entry or |R_ij| > 2");
+  HIPCHK(hipSetDevice(c->dev));
+  int rc = ensure_rot_capacity(c, 1);
+  if (rc) return rc;
+  const float* dB = nullptr;
+  const uint8_t* dmB = nullptr;
+  if ((rc = stage_moving(c, B, maskB, &dB, &dmB))) return rc;
+  const long long nmap = (long long)c->Wd[0] * c->Wd[1] * c->Wd[2];
+  float* dC = C;
+  long long* dN = reinterpret_cast<long long*>(N);
+  float* tC = nullptr;
+  long long* tN = nullptr;
+  const bool host = !(c->flags & CSNGF_DEVICE_PTRS);
+  if (host) {
+    if ((rc = dalloc(&tC, sizeof(float) * nmap))) return rc;
+    dC = tC;
+    if (N) {
+      if ((rc = dalloc(&tN, sizeof(long long) * nmap))) {
+        hipFree(tC);
+        return rc;
+      }
+      dN = tN;
+    }
+  }
+  std::memcpy(c->h_rot, kq, sizeof(kq));
+  auto cleanup = [&]() {
+    if (tC) hipFree(tC);
+    if (tN) hipFree(tN);
+  };
+  if (hipMemcpyAsync(c->d_rot, c->h_rot, sizeof(kq), hipMemcpyHostToDevice, c->stream) != hipSuccess) {
+    cleanup();
+    return hip_fail(hipGetLastError(), "rotation upload");
+  }
+  rc = run_batch(c, dB, dmB, c->d_rot, 1, c->d_res, dC, dN);
+  hipError_t se = hipStreamSynchronize(c->stream);
+  if (!rc && se != hipSuccess) rc = hip_fail(se, "csngf_evaluate_map");
+  int bad = 0;
+  if (!rc) rc = read_flag(c, &bad);
+  if (!rc && bad) rc = fail(CSNGF_E_INVALID_ARG, "moving volume B has a non-finite value");
+  if (!rc && host) {
+    if (hipMemcpy(C, dC, sizeof(float) * nmap, hipMemcpyDeviceToHost) != hipSuccess)
+      rc = hip_fail(hipGetLastError(), "map download");
+    if (!rc && N && hipMemcpy(N, dN, sizeof(long long) * nmap, hipMemcpyDeviceToHost) != hipSuccess)
+      rc = hip_fail(hipGetLastError(), "overlap download");
+  }
+  cleanup();
+  return rc;
+}
+
+int csngf_destroy(csngf_ctx* c) {
+  if (!c) return fail(CSNGF_E_INVALID_ARG, "ctx is NULL");
+  release(c);
+  return CSNGF_OK;
+}
+
+// ---------------------------------------------------------------------------- debug / profile
+int csngf_debug_fft(const void* in, void* out, int32_t L, int32_t batch, int32_t inverse, void* stream) {
+  if (!in || !out || batch < 0) return fail(CSNGF_E_INVALID_ARG, "bad argument");
+  if (!supported(L)) return fail(CSNGF_E_UNSUPPORTED, "FFT length not supported");
+  int rc = check_device();
+  if (rc) return rc;
+  if (batch == 0) return CSNGF_OK;
+  FftPlan pl;
+  factor_plan(L, pl);
+  pl.tw_off = 0;
+  std::vector<float2> tw;
+  twiddles(L, tw);
+  float2* dtw = nullptr;
+  if ((rc = dalloc(&dtw, sizeof(float2) * L))) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(dtw, tw.data(), sizeof(float2) * L, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) {
+    const dim3 grid((batch + kTileW - 1) / kTileW);
+    const size_t lds = lds_pencil(L);
+    if (inverse)
+      hipLaunchKernelGGL(k_debug_fft<true>, grid, dim3(kThreads), lds, s, (const float2*)in, (float2*)out, batch, pl,
+                         dtw);
+    else
+      hipLaunchKernelGGL(k_debug_fft<false>, grid, dim3(kThreads), lds, s, (const float2*)in, (float2*)out, batch, pl,
+                         dtw);
+    e = hipGetLastError();
+  }
+  hipError_t se = hipStreamSynchronize(s);
+  hipFree(dtw);
+  if (e != hipSuccess) return hip_fail(e, "k_debug_fft");
+  if (se != hipSuccess) return hip_fail(se, "k_debug_fft sync");
+  return CSNGF_OK;
+}
+
+int csngf_debug_fields(const float* vol, const uint8_t* vmask, csngf_dims d, const double* R9, float eps, int32_t Px,
+                       float* prod6, uint8_t* mask, uint32_t flags) {
+  if (!vol || !prod6 || !mask) return fail(CSNGF_E_INVALID_ARG, "NULL argument");
+  int rc = check_dims(d, "volume");
+  if (rc) return rc;
+  if (!(eps > 0.f)) return fail(CSNGF_E_INVALID_ARG, "eps must be > 0");
+  if (Px == 0) Px = smallest_supported_at_least(2 * d.nx - 1);
+  if (Px < d.nx || !supported(Px)) return fail(CSNGF_E_UNSUPPORTED, "Px not supported");
+  int kq[9];
+  if (R9 && quantise(R9, kq, nullptr)) return fail(CSNGF_E_INVALID_ARG, "bad rotation");
+  if ((rc = check_device())) return rc;
+  const bool dev = flags & CSNGF_DEVICE_PTRS;
+  const size_t nv = (size_t)d.nx * d.ny * d.nz;
+  if (!dev && !all_finite(vol, nv)) return fail(CSNGF_E_INVALID_ARG, "non-finite volume");
+  csngf_ctx tmp;
+  tmp.stream = nullptr;
+  tmp.eps = eps;
+  factor_plan(Px, tmp.plx);
+  tmp.plx.tw_off = 0;
+  tmp.H = Px / 2 + 1;
+  tmp.Hp = (tmp.H + kTileW - 1) / kTileW * kTileW;
+  std::vector<float2> tw;
+  twiddles(Px, tw);
+  float* dvol = const_cast<float*>(vol);
+  uint8_t* dvm = const_cast<uint8_t*>(vmask);
+  float* dprod = prod6;
+  uint8_t* dmask = mask;
+  float2* x1 = nullptr;
+  int* drot = nullptr;
+  std::vector<void*> owned;
+  auto done = [&](int code) {
+    hipDeviceSynchronize();
+    for (void* p : owned) hipFree(p);
+    if (tmp.d_tw) hipFree(tmp.d_tw);
+    tmp.d_tw = nullptr;
+    return code;
+  };
+  const int n3[3] = {d.nx, d.ny, d.nz};
+  if ((rc = dalloc(&tmp.d_tw, sizeof(float2) * Px))) return done(rc);
+  if ((rc = dalloc(&x1, sizeof(float2) * 6 * (size_t)d.nz * d.ny * tmp.Hp))) return done(rc);
+  owned.push_back(x1);
+  if ((rc = dalloc(&drot, sizeof(kq)))) return done(rc);
+  owned.push_back(drot);
+  if (hipMemcpy(tmp.d_tw, tw.data(), sizeof(float2) * Px, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(drot, kq, sizeof(kq), hipMemcpyHostToDevice) != hipSuccess)
+    return done(hip_fail(hipGetLastError(), "upload"));
+  if (!dev) {
+    if ((rc = dalloc(&dvol, sizeof(float) * nv))) return done(rc);
+    owned.push_back(dvol);
+    if (hipMemcpy(dvol, vol, sizeof(float) * nv, hipMemcpyHostToDevice) != hipSuccess)
+      return done(hip_fail(hipGetLastError(), "upload"));
+    if (vmask) {
+      if ((rc = dalloc(&dvm, nv))) return done(rc);
+      owned.push_back(dvm);
+      if (hipMemcpy(dvm, vmask, nv, hipMemcpyHostToDevice) != hipSuccess)
+        return done(hip_fail(hipGetLastError(), "upload"));
+    }
+    if ((rc = dalloc(&dprod, sizeof(float) * 6 * nv))) return done(rc);
+    owned.push_back(dprod);
+    if ((rc = dalloc(&dmask, nv))) return done(rc);
+    owned.push_back(dmask);
+  }
+  rc = launch_fields(&tmp, R9 != nullptr, dvol, dvm, n3, drot, x1, 0, dmask, 0, dprod, 1);
+  if (rc) return done(rc);
+  if (hipDeviceSynchronize() != hipSuccess) return done(hip_fail(hipGetLastError(), "k_fields_x"));
+  if (!dev) {
+    if (hipMemcpy(prod6, dprod, sizeof(float) * 6 * nv, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(mask, dmask, nv, hipMemcpyDeviceToHost) != hipSuccess)
+      return done(hip_fail(hipGetLastError(), "download"));
+  }
+  return done(CSNGF_OK);
+}
+
+int csngf_profile_enable(csngf_ctx* c, int32_t enable) {
+  if (!c) return fail(CSNGF_E_INVALID_ARG, "ctx is NULL");
+  c->prof = enable != 0;
+  return CSNGF_OK;
+}
+
+int csngf_profile_read(csngf_ctx* c, csngf_kernel_stat* out, int32_t max, int32_t* count) {
+  if (!c) return fail(CSNGF_E_INVALID_ARG, "ctx is NULL");
+  HIPCHK(hipStreamSynchronize(c->stream));
+  prof_fold(c);
+  if (count) *count = KT_COUNT;
+  for (int i = 0; out && i < KT_COUNT && i < max; ++i) {
+    std::memset(&out[i], 0, sizeof(out[i]));
+    std::snprintf(out[i].name, sizeof(out[i].name), "%s", kTypeName[i]);
+    out[i].launches = c->stat_launches[i];
+    out[i].total_ms = c->stat_ms[i];
+  }
+  return CSNGF_OK;
+}
+
+int csngf_profile_reset(csngf_ctx* c) {
+  if (!c) return fail(CSNGF_E_INVALID_ARG, "ctx is NULL");
+  HIPCHK(hipStreamSynchronize(c->stream));
+  prof_fold(c);
+  for (int i = 0; i < KT_COUNT; ++i) {
+    c->stat_launches[i] = 0;
+    c->stat_ms[i] = 0;
+  }
+  return CSNGF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,221 @@
+// Mixed-radix complex FFT on LDS-staged pencils for gfx950.
+//
+// A workgroup holds W pencils of length L in LDS as buf[i * W + p] (pencil p fastest, so a
+// 64-lane wave touching consecutive p hits consecutive banks).  Each radix stage is an
+// in-place Stockham autosort step: every thread loads the R inputs of its butterflies
+// into registers, the group synchronises, then applies twiddles, the radix-R DFT and
+// writes the R outputs to their self-sorted places.  Stages follow a runtime plan
+// (radices and running products), so one kernel instance serves every supported length.
+//
+// Forward transforms use exp(-2 pi i j k / L); inverse ones use the conjugate and are
+// unnormalised (the caller folds 1/L into its data).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace csngf {
+
+constexpr int kMaxStages = 12;
+constexpr int kMaxLen = 512;
+
+struct FftPlan {
+  int L;                    // transform length
+  int nst;                  // number of stages
+  int radix[kMaxStages];    // radix of each stage
+  int ns[kMaxStages];       // product of the radices of all earlier stages
+  int tw_off;               // offset of this length's table W_L^j, j < L, in the table buffer
+};
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+// multiply by -i (forward) or +i (inverse)
+template <bool INV>
+__device__ __forceinline__ float2 rot_i(float2 a) {
+  return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+
+// ---------------------------------------------------------------- small DFTs
+template <bool INV>
+__device__ __forceinline__ void dft2(float2* x) {
+  float2 a = x[0], b = x[1];
+  x[0] = cadd(a, b);
+  x[1] = csub(a, b);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft4(float2* x) {
+  float2 t0 = cadd(x[0], x[2]), t1 = csub(x[0], x[2]);
+  float2 t2 = cadd(x[1], x[3]), t3 = rot_i<INV>(csub(x[1], x[3]));
+  x[0] = cadd(t0, t2);
+  x[2] = csub(t0, t2);
+  x[1] = cadd(t1, t3);
+  x[3] = csub(t1, t3);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft8(float2* x) {
+  constexpr float h = 0.70710678118654752f;
+  float2 a[4], b[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    a[k] = cadd(x[k], x[k + 4]);
+    b[k] = csub(x[k], x[k + 4]);
+  }
+  // b[k] *= W8^k  (W8 = exp(-i pi/4) forward, conjugate inverse)
+  b[1] = INV ? make_float2(h * (b[1].x - b[1].y), h * (b[1].x + b[1].y))
+             : make_float2(h * (b[1].x + b[1].y), h * (b[1].y - b[1].x));
+  b[2] = rot_i<INV>(b[2]);
+  b[3] = INV ? make_float2(-h * (b[3].x + b[3].y), h * (b[3].x - b[3].y))
+             : make_float2(h * (b[3].y - b[3].x), -h * (b[3].x + b[3].y));
+  dft4<INV>(a);
+  dft4<INV>(b);
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    x[2 * m] = a[m];
+    x[2 * m + 1] = b[m];
+  }
+}
+
+// cos(2 pi j / R) and sin(2 pi j / R) for j = 1 .. (R-1)/2
+template <int R> struct OddRoots;
+template <> struct OddRoots<3> {
+  static constexpr float c[1] = {-0.5f};
+  static constexpr float s[1] = {0.86602540378443871f};
+};
+template <> struct OddRoots<5> {
+  static constexpr float c[2] = {0.30901699437494745f, -0.80901699437494734f};
+  static constexpr float s[2] = {0.95105651629515353f, 0.58778525229247325f};
+};
+template <> struct OddRoots<7> {
+  static constexpr float c[3] = {0.62348980185873359f, -0.22252093395631434f, -0.90096886790241903f};
+  static constexpr float s[3] = {0.7818314824680298f, 0.97492791218182362f, 0.43388373911755823f};
+};
+template <> struct OddRoots<11> {
+  static constexpr float c[5] = {0.84125353283118121f, 0.41541501300188644f, -0.142314838273285f,
+                                 -0.65486073394528499f, -0.95949297361449737f};
+  static constexpr float s[5] = {0.54064081745559756f, 0.90963199535451833f, 0.9898214418809328f,
+                                 0.75574957435425827f, 0.28173255684142967f};
+};
+
+// Odd prime R: pair x_m with x_{R-m}; y_k = A_k -+ i B_k, y_{R-k} = A_k +- i B_k with
+// A_k = x_0 + sum_m (x_m + x_{R-m}) cos(2 pi k m / R), B_k = sum_m (x_m - x_{R-m}) sin(..).
+template <int R, bool INV>
+__device__ __forceinline__ void dft_odd(float2* x) {
+  constexpr int h = (R - 1) / 2;
+  float2 a[h + 1], b[h + 1];
+  float2 y0 = x[0];
+#pragma unroll
+  for (int m = 1; m <= h; ++m) {
+    a[m] = cadd(x[m], x[R - m]);
+    b[m] = csub(x[m], x[R - m]);
+    y0 = cadd(y0, a[m]);
+  }
+  float2 out[R];
+  out[0] = y0;
+#pragma unroll
+  for (int k = 1; k <= h; ++k) {
+    float2 A = x[0];
+    float2 B = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int m = 1; m <= h; ++m) {
+      const int j = (k * m) % R;
+      const float c = (j <= h) ? OddRoots<R>::c[j - 1] : OddRoots<R>::c[R - j - 1];
+      const float s = (j <= h) ? OddRoots<R>::s[j - 1] : -OddRoots<R>::s[R - j - 1];
+      A.x = fmaf(a[m].x, c, A.x);
+      A.y = fmaf(a[m].y, c, A.y);
+      B.x = fmaf(b[m].x, s, B.x);
+      B.y = fmaf(b[m].y, s, B.y);
+    }
+    if (!INV) {
+      out[k] = make_float2(A.x + B.y, A.y - B.x);
+      out[R - k] = make_float2(A.x - B.y, A.y + B.x);
+    } else {
+      out[k] = make_float2(A.x - B.y, A.y + B.x);
+      out[R - k] = make_float2(A.x + B.y, A.y - B.x);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < R; ++k) x[k] = out[k];
+}
+
+template <int R, bool INV>
+__device__ __forceinline__ void dft(float2* x) {
+  if constexpr (R == 2) dft2<INV>(x);
+  else if constexpr (R == 4) dft4<INV>(x);
+  else if constexpr (R == 8) dft8<INV>(x);
+  else dft_odd<R, INV>(x);
+}
+
+// ---------------------------------------------------------------- one Stockham stage
+// LW is the largest L * W this instance must handle; it bounds the butterflies per thread.
+template <int R, int W, int T, int LW, bool INV>
+__device__ __forceinline__ void fft_stage(float2* __restrict__ buf, const float2* __restrict__ tw,
+                                          int L, int ns) {
+  constexpr int NB = (LW / R + T - 1) / T;
+  const int lr = L / R;
+  const int nbf = lr * W;
+  const int twstep = L / (ns * R);
+  float2 v[NB][R];
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    const int bf = (int)threadIdx.x + u * T;
+    if (bf < nbf) {
+      const int p = bf % W, j = bf / W;
+#pragma unroll
+      for (int t = 0; t < R; ++t) v[u][t] = buf[(j + t * lr) * W + p];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    const int bf = (int)threadIdx.x + u * T;
+    if (bf < nbf) {
+      const int p = bf % W, j = bf / W;
+      const int k = j % ns, q = j / ns;
+      if (ns > 1) {
+#pragma unroll
+        for (int t = 1; t < R; ++t) {
+          float2 w = tw[t * k * twstep];
+          if (INV) w.y = -w.y;
+          v[u][t] = cmul(v[u][t], w);
+        }
+      }
+      dft<R, INV>(v[u]);
+      const int base = q * ns * R + k;
+#pragma unroll
+      for (int t = 0; t < R; ++t) buf[(base + t * ns) * W + p] = v[u][t];
+    }
+  }
+  __syncthreads();
+}
+
+// Whole transform.  Caller has synchronised after filling buf; on return buf holds the
+// result in natural order and the group is synchronised.
+template <int W, int T, int LW, bool INV>
+__device__ void fft_lds(float2* __restrict__ buf, const float2* __restrict__ tw, const FftPlan& pl) {
+  for (int s = 0; s < pl.nst; ++s) {
+    const int ns = pl.ns[s];
+    switch (pl.radix[s]) {
+      case 2: fft_stage<2, W, T, LW, INV>(buf, tw, pl.L, ns); break;
+      case 3: fft_stage<3, W, T, LW, INV>(buf, tw, pl.L, ns); break;
+      case 4: fft_stage<4, W, T, LW, INV>(buf, tw, pl.L, ns); break;
+      case 5: fft_stage<5, W, T, LW, INV>(buf, tw, pl.L, ns); break;
+      case 7: fft_stage<7, W, T, LW, INV>(buf, tw, pl.L, ns); break;
+      case 8: fft_stage<8, W, T, LW, INV>(buf, tw, pl.L, ns); break;
+      case 11: fft_stage<11, W, T, LW, INV>(buf, tw, pl.L, ns); break;
+      default: break;
+    }
+  }
+}
+
+// Copy this length's twiddle table into LDS (caller synchronises before use).
+__device__ __forceinline__ void load_twiddles(float2* __restrict__ dst, const float2* __restrict__ table,
+                                              const FftPlan& pl) {
+  for (int i = threadIdx.x; i < pl.L; i += blockDim.x) dst[i] = table[pl.tw_off + i];
+}
+
+}  // namespace csngf

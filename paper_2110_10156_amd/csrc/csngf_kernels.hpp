@@ -1,0 +1,568 @@
+// HIP kernels of the CSNGF hot path (gfx950).
+//
+// Data flow for one rotation slot (H = Px/2 + 1 half-spectrum bins along x, row pitch Hp):
+//   k_fields_x   B -> resample -> NGF -> mask -> 6 products -> x R2C    X1 [6][nz][ny][Hp]
+//   k_sat_*      eroded mask of B^ -> zero-bordered 3-D summed-area table (exact overlaps)
+//   k_pencil<F>  y forward, ny nonzero rows -> Py                        X2 [6][nz][Py][Hp]
+//   k_zpass      per field: z forward (nz nonzero -> Pz), multiply by A's conjugate spectrum,
+//                sum over fields; then z inverse of the sum              Y3 [Wz][Py][Hp]
+//   k_pencil<I>  y inverse, kept rows = displacement range               Y4 [Wz][Wy][Hp]
+//   k_final_x    x C2R -> S(chi); N(chi) from the SAT; gamma; C = S/N; per-slot argmax key
+// Fixed side (once per context): k_fields_x<direct>, k_pencil<F>, k_zstore (conjugate,
+// cross-term weight 2, 1/(Px Py Pz)).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "csngf_fft.hpp"
+
+namespace csngf {
+
+constexpr int kThreads = 256;
+constexpr int kTileW = 16;   // adjacent x-bins per pencil tile in the y/z passes
+constexpr int kRowsX = 8;    // rows per workgroup in the x passes
+
+struct RotResultDev {        // identical layout to csngf_rot_result
+  float score;
+  int32_t shift[3];
+  long long overlap;
+  int32_t valid;
+  int32_t reserved;
+};
+
+__device__ __forceinline__ float lerp_exact(float a, float b, float f) {
+  // a + f (b - a): returns a exactly when a == b, so constant regions stay constant
+  return fmaf(f, b - a, a);
+}
+
+// Trilinear sample of B at p = R (x - c) + c with R in Q16 fixed point.  Coordinates are
+// exact integers in units of 2^-17:  p_i 2^17 = sum_j k_ij (2 x_j - (n_j - 1)) + (n_i - 1) 2^16.
+// Returns false (value 0) when p leaves the closed box [0, n-1]^3 or, with a mask, when a
+// corner of the source cell lies outside the mask.
+__device__ __forceinline__ bool resample_q16(const float* __restrict__ B, const uint8_t* __restrict__ mB,
+                                             int nx, int ny, int nz, const int* __restrict__ k,
+                                             int x, int y, int z, float& out) {
+  const int dx = 2 * x - (nx - 1), dy = 2 * y - (ny - 1), dz = 2 * z - (nz - 1);
+  const int px = k[0] * dx + k[1] * dy + k[2] * dz + (nx - 1) * 65536;
+  const int py = k[3] * dx + k[4] * dy + k[5] * dz + (ny - 1) * 65536;
+  const int pz = k[6] * dx + k[7] * dy + k[8] * dz + (nz - 1) * 65536;
+  out = 0.f;
+  if (px < 0 || py < 0 || pz < 0 || px > ((nx - 1) << 17) || py > ((ny - 1) << 17) ||
+      pz > ((nz - 1) << 17))
+    return false;
+  int ix = px >> 17, iy = py >> 17, iz = pz >> 17;
+  const float q = 1.0f / 131072.0f;
+  float fx = (float)(px & 0x1FFFF) * q, fy = (float)(py & 0x1FFFF) * q, fz = (float)(pz & 0x1FFFF) * q;
+  if (ix == nx - 1) { ix = nx - 2; fx = 1.0f; }
+  if (iy == ny - 1) { iy = ny - 2; fy = 1.0f; }
+  if (iz == nz - 1) { iz = nz - 2; fz = 1.0f; }
+  const long sy = nx, sz = (long)nx * ny;
+  const long o = iz * sz + iy * sy + ix;
+  if (mB) {
+    if (!(mB[o] && mB[o + 1] && mB[o + sy] && mB[o + sy + 1] && mB[o + sz] && mB[o + sz + 1] &&
+          mB[o + sz + sy] && mB[o + sz + sy + 1]))
+      return false;
+  }
+  const float c00 = lerp_exact(B[o], B[o + 1], fx);
+  const float c10 = lerp_exact(B[o + sy], B[o + sy + 1], fx);
+  const float c01 = lerp_exact(B[o + sz], B[o + sz + 1], fx);
+  const float c11 = lerp_exact(B[o + sz + sy], B[o + sz + sy + 1], fx);
+  const float c0 = lerp_exact(c00, c10, fy);
+  const float c1 = lerp_exact(c01, c11, fy);
+  out = lerp_exact(c0, c1, fz);
+  return true;
+}
+
+__device__ __forceinline__ size_t align16(size_t b) { return (b + 15) & ~size_t(15); }
+
+// ------------------------------------------------------------------------------ x pass
+// One workgroup: slice z, rows y0 .. y0+kRowsX-1 of one rotation slot.  The halo (rows
+// y0-1 .. y0+kRowsX, slices z-1 .. z+1) is sampled into LDS, then for each of the 3 field
+// pairs (xx,yy), (zz,xy), (xz,yz) the products are packed as re/im of one complex row,
+// transformed along x (length Px, zero padded from nx) and split into two half spectra.
+template <bool MOVING>
+__global__ __launch_bounds__(kThreads) void k_fields_x(
+    const float* __restrict__ vol, const uint8_t* __restrict__ umask, int nx, int ny, int nz,
+    const int* __restrict__ rotq, float eps, FftPlan pl, const float2* __restrict__ twtab,
+    float2* __restrict__ out, int H, int Hp, long long out_slot_stride,
+    uint8_t* __restrict__ mask_out, long long mask_slot_stride, float* __restrict__ dbg_prod) {
+  constexpr int TY = kRowsX;
+  constexpr int HR = TY + 2;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int Px = pl.L;
+  float2* tw = reinterpret_cast<float2*>(smem);
+  float2* buf = reinterpret_cast<float2*>(smem + align16(sizeof(float2) * Px));
+  float* val = reinterpret_cast<float*>(smem + align16(sizeof(float2) * Px) + align16(sizeof(float2) * Px * TY));
+  uint8_t* ok = reinterpret_cast<uint8_t*>(reinterpret_cast<unsigned char*>(val) +
+                                           align16(sizeof(float) * 3 * HR * nx));
+  const int y0 = blockIdx.x * TY;
+  const int z = blockIdx.y;
+  const int slot = blockIdx.z;
+  const int* kq = MOVING ? rotq + 9 * slot : nullptr;
+  load_twiddles(tw, twtab, pl);
+
+  // 1. halo samples
+  const int nhalo = 3 * HR * nx;
+  for (int e = threadIdx.x; e < nhalo; e += kThreads) {
+    const int x = e % nx;
+    const int r = (e / nx) % HR;
+    const int pzl = e / (nx * HR);
+    const int yy = y0 + r - 1, zz = z + pzl - 1;
+    float v = 0.f;
+    bool good = false;
+    if (yy >= 0 && yy < ny && zz >= 0 && zz < nz) {
+      if (MOVING) {
+        good = resample_q16(vol, umask, nx, ny, nz, kq, x, yy, zz, v);
+      } else {
+        const long o = ((long)zz * ny + yy) * nx + x;
+        v = vol[o];
+        good = umask ? (umask[o] != 0) : true;
+      }
+    }
+    val[e] = v;
+    ok[e] = good ? 1 : 0;
+  }
+  __syncthreads();
+
+  const float eps2 = eps * eps;
+  for (int pair = 0; pair < 3; ++pair) {
+    // 2. products of this pair into the complex rows (re = first field, im = second)
+    for (int e = threadIdx.x; e < TY * Px; e += kThreads) {
+      const int x = e % Px;
+      const int r = e / Px;
+      float fa = 0.f, fb = 0.f;
+      if (x < nx) {
+        const int c = (1 * HR + r + 1) * nx + x;
+        const bool m = x >= 1 && x <= nx - 2 && ok[c] && ok[c - 1] && ok[c + 1] && ok[c - nx] &&
+                       ok[c + nx] && ok[c - HR * nx] && ok[c + HR * nx];
+        float n0 = 0.f, n1 = 0.f, n2 = 0.f;
+        if (m) {
+          const float gx = 0.5f * (val[c + 1] - val[c - 1]);
+          const float gy = 0.5f * (val[c + nx] - val[c - nx]);
+          const float gz = 0.5f * (val[c + HR * nx] - val[c - HR * nx]);
+          const float inv = 1.0f / sqrtf(gx * gx + gy * gy + gz * gz + eps2);
+          n0 = gx * inv;
+          n1 = gy * inv;
+          n2 = gz * inv;
+        }
+        if (pair == 0) { fa = n0 * n0; fb = n1 * n1; }
+        else if (pair == 1) { fa = n2 * n2; fb = n0 * n1; }
+        else { fa = n0 * n2; fb = n1 * n2; }
+        const int yy = y0 + r;
+        if (yy < ny) {
+          const long vox = ((long)z * ny + yy) * nx + x;
+          if (pair == 0 && mask_out) mask_out[slot * mask_slot_stride + vox] = m ? 1 : 0;
+          if (dbg_prod && slot == 0) {
+            const long nv = (long)nx * ny * nz;
+            dbg_prod[(2 * pair) * nv + vox] = fa;
+            dbg_prod[(2 * pair + 1) * nv + vox] = fb;
+          }
+        }
+      }
+      buf[x * TY + r] = make_float2(fa, fb);
+    }
+    __syncthreads();
+    fft_lds<TY, kThreads, kMaxLen * TY, false>(buf, tw, pl);
+    // 3. split the packed transform: Fa = (Z_k + conj Z_{P-k}) / 2, Fb = -i (Z_k - conj Z_{P-k}) / 2
+    for (int r = 0; r < TY; ++r) {
+      const int yy = y0 + r;
+      if (yy >= ny) break;
+      float2* oa = out + slot * out_slot_stride + (((long)(2 * pair) * nz + z) * ny + yy) * Hp;
+      float2* ob = out + slot * out_slot_stride + (((long)(2 * pair + 1) * nz + z) * ny + yy) * Hp;
+      for (int k = threadIdx.x; k < H; k += kThreads) {
+        const float2 zk = buf[k * TY + r];
+        const float2 zc = buf[((Px - k) % Px) * TY + r];
+        oa[k] = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y - zc.y));
+        ob[k] = make_float2(0.5f * (zk.y + zc.y), 0.5f * (zc.x - zk.x));
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------------------ y passes
+// Pencils along the middle axis.  Workgroup (x-tile, group g, slot): input rows i < n_in of
+// in[g], zero beyond; output row c takes transform row (c + out_off) mod L.
+template <bool INV, int LMAX>
+__global__ __launch_bounds__(kThreads) void k_pencil(
+    const float2* __restrict__ in, float2* __restrict__ out, int n_in, int n_out, int out_off,
+    FftPlan pl, const float2* __restrict__ twtab, int H, int Hp, long long in_gstride,
+    long long out_gstride, long long in_sstride, long long out_sstride) {
+  constexpr int W = kTileW;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int L = pl.L;
+  float2* tw = reinterpret_cast<float2*>(smem);
+  float2* buf = reinterpret_cast<float2*>(smem + align16(sizeof(float2) * L));
+  const int kx0 = blockIdx.x * W;
+  const float2* src = in + blockIdx.z * in_sstride + blockIdx.y * in_gstride + kx0;
+  float2* dst = out + blockIdx.z * out_sstride + blockIdx.y * out_gstride + kx0;
+  load_twiddles(tw, twtab, pl);
+  for (int e = threadIdx.x; e < L * W; e += kThreads) {
+    const int i = e / W, p = e % W;
+    float2 v = make_float2(0.f, 0.f);
+    if (i < n_in && kx0 + p < H) v = src[(long)i * Hp + p];
+    buf[e] = v;
+  }
+  __syncthreads();
+  fft_lds<W, kThreads, LMAX * W, INV>(buf, tw, pl);
+  for (int e = threadIdx.x; e < n_out * W; e += kThreads) {
+    const int c = e / W, p = e % W;
+    if (kx0 + p < H) {
+      const int j = (c + out_off) % L;
+      dst[(long)c * Hp + p] = buf[j * W + p];
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------ z pass
+// Workgroup (ky, x-tile, slot), ordered so that the slots of one tile run back to back on
+// one XCD and share that tile of A's spectra through its L2.
+template <int LMAX>
+__global__ __launch_bounds__(kThreads) void k_zpass(
+    const float2* __restrict__ X2, const float2* __restrict__ spec, float2* __restrict__ Y3,
+    int nz, int Py, int H, int Hp, int Wz, int out_off, FftPlan pl, const float2* __restrict__ twtab,
+    long long x2_sstride, long long y3_sstride, int ntiles, int nslots, int nreal) {
+  constexpr int W = kTileW;
+  constexpr int NE = (LMAX * W + kThreads - 1) / kThreads;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int Pz = pl.L;
+  float2* tw = reinterpret_cast<float2*>(smem);
+  float2* buf = reinterpret_cast<float2*>(smem + align16(sizeof(float2) * Pz));
+  // XCD-aware order: hardware deals block b to XCD b % 8; give each XCD a contiguous run.
+  const int nb8 = gridDim.x;
+  const int b = blockIdx.x;
+  const int logical = (b % 8) * (nb8 / 8) + b / 8;
+  if (logical >= nreal) return;
+  const int slot = logical % nslots;
+  const int rest = logical / nslots;
+  const int tile = rest % ntiles;
+  const int ky = rest / ntiles;
+  const int kx0 = tile * W;
+  load_twiddles(tw, twtab, pl);
+  float2 acc[NE];
+#pragma unroll
+  for (int u = 0; u < NE; ++u) acc[u] = make_float2(0.f, 0.f);
+  const long long fstride_x2 = (long long)nz * Py * Hp;
+  const long long fstride_sp = (long long)Pz * Py * Hp;
+  for (int f = 0; f < 6; ++f) {
+    const float2* src = X2 + slot * x2_sstride + f * fstride_x2 + (long long)ky * Hp + kx0;
+    for (int e = threadIdx.x; e < Pz * W; e += kThreads) {
+      const int i = e / W, p = e % W;
+      float2 v = make_float2(0.f, 0.f);
+      if (i < nz && kx0 + p < H) v = src[(long long)i * Py * Hp + p];
+      buf[e] = v;
+    }
+    __syncthreads();
+    fft_lds<W, kThreads, LMAX * W, false>(buf, tw, pl);
+    const float2* a = spec + f * fstride_sp + (long long)ky * Hp + kx0;
+#pragma unroll
+    for (int u = 0; u < NE; ++u) {
+      const int e = threadIdx.x + u * kThreads;
+      if (e < Pz * W) {
+        const int i = e / W, p = e % W;
+        if (kx0 + p < H) {
+          const float2 s = a[(long long)i * Py * Hp + p];
+          const float2 v = buf[e];
+          acc[u].x = fmaf(v.x, s.x, fmaf(-v.y, s.y, acc[u].x));
+          acc[u].y = fmaf(v.x, s.y, fmaf(v.y, s.x, acc[u].y));
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < NE; ++u) {
+    const int e = threadIdx.x + u * kThreads;
+    if (e < Pz * W) buf[e] = acc[u];
+  }
+  __syncthreads();
+  fft_lds<W, kThreads, LMAX * W, true>(buf, tw, pl);
+  float2* dst = Y3 + slot * y3_sstride + (long long)ky * Hp + kx0;
+  for (int e = threadIdx.x; e < Wz * W; e += kThreads) {
+    const int c = e / W, p = e % W;
+    if (kx0 + p < H) {
+      const int j = (c + out_off) % Pz;
+      dst[(long long)c * Py * Hp + p] = buf[j * W + p];
+    }
+  }
+}
+
+// Fixed side: z forward of A's fields, stored as w_f * scale * conj(.) in spec[f][kz][ky][kx].
+template <int LMAX>
+__global__ __launch_bounds__(kThreads) void k_zstore(
+    const float2* __restrict__ X2, float2* __restrict__ spec, int nz, int Py, int H, int Hp,
+    FftPlan pl, const float2* __restrict__ twtab, float scale) {
+  constexpr int W = kTileW;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int Pz = pl.L;
+  float2* tw = reinterpret_cast<float2*>(smem);
+  float2* buf = reinterpret_cast<float2*>(smem + align16(sizeof(float2) * Pz));
+  const int kx0 = blockIdx.x * W;
+  const int ky = blockIdx.y;
+  const int f = blockIdx.z;
+  load_twiddles(tw, twtab, pl);
+  const float2* src = X2 + (long long)f * nz * Py * Hp + (long long)ky * Hp + kx0;
+  for (int e = threadIdx.x; e < Pz * W; e += kThreads) {
+    const int i = e / W, p = e % W;
+    float2 v = make_float2(0.f, 0.f);
+    if (i < nz && kx0 + p < H) v = src[(long long)i * Py * Hp + p];
+    buf[e] = v;
+  }
+  __syncthreads();
+  fft_lds<W, kThreads, LMAX * W, false>(buf, tw, pl);
+  const float w = (f >= 3 ? 2.0f : 1.0f) * scale;
+  float2* dst = spec + (long long)f * Pz * Py * Hp + (long long)ky * Hp + kx0;
+  for (int e = threadIdx.x; e < Pz * W; e += kThreads) {
+    const int i = e / W, p = e % W;
+    if (kx0 + p < H) {
+      const float2 v = buf[e];
+      dst[(long long)i * Py * Hp + p] = make_float2(w * v.x, -w * v.y);
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------ overlap SAT
+// sat[slot][(nz+1)][(ny+1)][(nx+1)], zero on index 0 of every axis:
+// sat[z+1][y+1][x+1] = sum of mask over [0..z] x [0..y] x [0..x].
+// Step 1: one wave per row of the padded table, prefix over x (zero rows for index 0).
+__global__ __launch_bounds__(kThreads) void k_sat_rows(const uint8_t* __restrict__ mask, int* __restrict__ sat,
+                                                       int nx, int ny, int nz, long long mask_sstride,
+                                                       long long sat_sstride) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  const int slot = blockIdx.y;
+  const int rows = (nz + 1) * (ny + 1);
+  if (row >= rows) return;
+  const int zz = row / (ny + 1), yy = row % (ny + 1);
+  int* dst = sat + slot * sat_sstride + (long long)row * (nx + 1);
+  if (zz == 0 || yy == 0) {
+    for (int x = lane; x <= nx; x += 64) dst[x] = 0;
+    return;
+  }
+  const uint8_t* src = mask + slot * mask_sstride + ((long long)(zz - 1) * ny + (yy - 1)) * nx;
+  if (lane == 0) dst[0] = 0;
+  int carry = 0;
+  for (int x0 = 0; x0 < nx; x0 += 64) {
+    const int x = x0 + lane;
+    int v = (x < nx) ? (int)src[x] : 0;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int t = __shfl_up(v, d, 64);
+      if (lane >= d) v += t;
+    }
+    if (x < nx) dst[x + 1] = carry + v;
+    carry += __shfl(v, 63, 64);
+  }
+}
+
+// Step 2: prefix over y for every (z, x) column; step 3: prefix over z for every (y, x).
+__global__ __launch_bounds__(kThreads) void k_sat_cols(int* __restrict__ sat, int nx, int ny, int nz,
+                                                       long long sat_sstride, int along_z) {
+  const int slot = blockIdx.y;
+  const int t = blockIdx.x * kThreads + threadIdx.x;
+  const int X = nx + 1, Y = ny + 1;
+  int* s = sat + slot * sat_sstride;
+  if (!along_z) {
+    if (t >= nz * nx) return;
+    const int zz = 1 + t / nx, x = 1 + t % nx;
+    int* p = s + (long long)zz * Y * X + x;
+    int run = 0;
+    for (int yy = 1; yy <= ny; ++yy) {
+      run += p[(long long)yy * X];
+      p[(long long)yy * X] = run;
+    }
+  } else {
+    if (t >= ny * nx) return;
+    const int yy = 1 + t / nx, x = 1 + t % nx;
+    int* p = s + (long long)yy * X + x;
+    int run = 0;
+    for (int zz = 1; zz <= nz; ++zz) {
+      run += p[(long long)zz * Y * X];
+      p[(long long)zz * Y * X] = run;
+    }
+  }
+}
+
+struct OverlapGeom {
+  int nA[3];   // x, y, z
+  int nB[3];
+};
+
+// Exact N(chi) for a fixed side whose eroded mask is the box [1, nA-2]: count the moving
+// mask over the box shifted by chi and clipped to B's grid.
+__device__ __forceinline__ long long box_count(const int* __restrict__ s, const OverlapGeom& g,
+                                               int cx, int cy, int cz) {
+  const int X = g.nB[0] + 1, Y = g.nB[1] + 1;
+  const int lx = max(1 + cx, 0), hx = min(g.nA[0] - 2 + cx, g.nB[0] - 1);
+  const int ly = max(1 + cy, 0), hy = min(g.nA[1] - 2 + cy, g.nB[1] - 1);
+  const int lz = max(1 + cz, 0), hz = min(g.nA[2] - 2 + cz, g.nB[2] - 1);
+  if (lx > hx || ly > hy || lz > hz) return 0;
+  auto at = [&](int z, int y, int x) { return (long long)s[((long long)z * Y + y) * X + x]; };
+  return at(hz + 1, hy + 1, hx + 1) - at(lz, hy + 1, hx + 1) - at(hz + 1, ly, hx + 1) -
+         at(hz + 1, hy + 1, lx) + at(lz, ly, hx + 1) + at(lz, hy + 1, lx) + at(hz + 1, ly, lx) -
+         at(lz, ly, lx);
+}
+
+__device__ __forceinline__ unsigned int ordered_bits(float f) {
+  const unsigned int u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__device__ __forceinline__ long long threshold(long long count_a, long long count_b, float gamma) {
+  const long long m = count_a < count_b ? count_a : count_b;
+  const double t = ceil((double)gamma * (double)m);
+  const long long tt = (long long)t;
+  return tt > 1 ? tt : 1;
+}
+
+// ------------------------------------------------------------------------------ final x pass
+// Workgroup (row pair group, zc, slot): 8 packed complex pencils = 16 output rows (yc).
+// Two real rows with half spectra S1, S2 are recovered at once from Z = S1 + i S2 extended
+// by Hermitian symmetry: z = IFFT(Z), S1 row = Re z, S2 row = Im z.
+template <bool WRITE_MAP>
+__global__ __launch_bounds__(kThreads) void k_final_x(
+    const float2* __restrict__ Y4, const int* __restrict__ sat, unsigned long long* __restrict__ keys,
+    OverlapGeom g, int Wx, int Wy, int Wz, int H, int Hp, FftPlan pl, const float2* __restrict__ twtab,
+    long long y4_sstride, long long sat_sstride, long long count_a, float gamma,
+    float* __restrict__ cmap, long long* __restrict__ nmap) {
+  constexpr int WP = kRowsX;  // packed pencils
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ unsigned long long red[kThreads / 64];
+  const int Px = pl.L;
+  float2* tw = reinterpret_cast<float2*>(smem);
+  float2* buf = reinterpret_cast<float2*>(smem + align16(sizeof(float2) * Px));
+  const int yc0 = blockIdx.x * (2 * WP);
+  const int zc = blockIdx.y;
+  const int slot = blockIdx.z;
+  const int* s = sat + slot * sat_sstride;
+  load_twiddles(tw, twtab, pl);
+  const float2* rows = Y4 + slot * y4_sstride + ((long long)zc * Wy) * Hp;
+  const int half = Px / 2;
+  for (int e = threadIdx.x; e < WP * H; e += kThreads) {
+    const int p = e / H, k = e % H;
+    const int r0 = yc0 + 2 * p, r1 = r0 + 1;
+    const float2 a = (r0 < Wy) ? rows[(long long)r0 * Hp + k] : make_float2(0.f, 0.f);
+    const float2 c = (r1 < Wy) ? rows[(long long)r1 * Hp + k] : make_float2(0.f, 0.f);
+    if (k == 0 || k == half) {
+      buf[k * WP + p] = make_float2(a.x, c.x);
+    } else {
+      buf[k * WP + p] = make_float2(a.x - c.y, a.y + c.x);           // S1 + i S2
+      buf[(Px - k) * WP + p] = make_float2(a.x + c.y, c.x - a.y);    // conj(S1) + i conj(S2)
+    }
+  }
+  __syncthreads();
+  fft_lds<WP, kThreads, kMaxLen * WP, true>(buf, tw, pl);
+
+  const long long count_b = s[(long long)(g.nB[2] + 1) * (g.nB[1] + 1) * (g.nB[0] + 1) - 1];
+  const long long thr = threshold(count_a, count_b, gamma);
+  const int cz = zc - (g.nA[2] - 1);
+  unsigned long long best = 0ull;
+  for (int e = threadIdx.x; e < 2 * WP * Wx; e += kThreads) {
+    const int rr = e / Wx, cx = e % Wx;
+    const int yc = yc0 + rr;
+    if (yc >= Wy) continue;
+    const int p = rr >> 1;
+    const int chx = cx - (g.nA[0] - 1);
+    const int j = (chx + Px) % Px;
+    const float2 zv = buf[j * WP + p];
+    const float sv = (rr & 1) ? zv.y : zv.x;
+    const int cy = yc - (g.nA[1] - 1);
+    const long long n = box_count(s, g, chx, cy, cz);
+    const bool valid = n >= thr;
+    const float c = valid ? sv / (float)n : -INFINITY;
+    const unsigned int canon = (unsigned int)(((long long)zc * Wy + yc) * Wx + cx);
+    if (valid) {
+      const unsigned long long key = ((unsigned long long)ordered_bits(c) << 32) | (0xFFFFFFFFu - canon);
+      best = key > best ? key : best;
+    }
+    if (WRITE_MAP) {
+      const long long o = ((long long)zc * Wy + yc) * Wx + cx;
+      cmap[o] = c;
+      if (nmap) nmap[o] = n;
+    }
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const unsigned long long o = __shfl_xor(best, d, 64);
+    best = o > best ? o : best;
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long m = red[0];
+    for (int w = 1; w < kThreads / 64; ++w) m = red[w] > m ? red[w] : m;
+    if (m) atomicMax(keys + slot, m);
+  }
+}
+
+// Per-slot result from its key: score bits, canonical index -> displacement, exact N.
+__global__ void k_finalize(const unsigned long long* __restrict__ keys, const int* __restrict__ sat,
+                           OverlapGeom g, int Wx, int Wy, long long sat_sstride, int nslots,
+                           RotResultDev* __restrict__ res) {
+  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= nslots) return;
+  const unsigned long long key = keys[slot];
+  RotResultDev r;
+  r.reserved = 0;
+  if (key == 0ull) {
+    r.score = -INFINITY;
+    r.shift[0] = r.shift[1] = r.shift[2] = 0;
+    r.overlap = 0;
+    r.valid = 0;
+  } else {
+    const unsigned int hi = (unsigned int)(key >> 32);
+    const unsigned int u = (hi & 0x80000000u) ? (hi & 0x7FFFFFFFu) : ~hi;
+    const unsigned int canon = 0xFFFFFFFFu - (unsigned int)(key & 0xFFFFFFFFull);
+    const int cx = canon % Wx, cy = (canon / Wx) % Wy, cz = canon / (Wx * Wy);
+    r.score = __uint_as_float(u);
+    r.shift[0] = cx - (g.nA[0] - 1);
+    r.shift[1] = cy - (g.nA[1] - 1);
+    r.shift[2] = cz - (g.nA[2] - 1);
+    r.overlap = box_count(sat + slot * sat_sstride, g, r.shift[0], r.shift[1], r.shift[2]);
+    r.valid = 1;
+  }
+  res[slot] = r;
+}
+
+__global__ void k_fill_u64(unsigned long long* __restrict__ p, int n, unsigned long long v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_f32(float* __restrict__ p, long long n, float v) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_check_finite(const float* __restrict__ v, long long n, int* __restrict__ flag) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  int bad = 0;
+  for (; i < n; i += stride) bad |= !isfinite(v[i]);
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+
+// Batched C2C along a contiguous axis: in/out [batch][L]; 16 batch rows per workgroup.
+template <bool INV>
+__global__ __launch_bounds__(kThreads) void k_debug_fft(const float2* __restrict__ in, float2* __restrict__ out,
+                                                        int batch, FftPlan pl, const float2* __restrict__ twtab) {
+  constexpr int W = kTileW;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int L = pl.L;
+  float2* tw = reinterpret_cast<float2*>(smem);
+  float2* buf = reinterpret_cast<float2*>(smem + align16(sizeof(float2) * L));
+  const int b0 = blockIdx.x * W;
+  load_twiddles(tw, twtab, pl);
+  for (int e = threadIdx.x; e < L * W; e += kThreads) {
+    const int p = e / L, i = e % L;
+    buf[i * W + p] = (b0 + p < batch) ? in[(long long)(b0 + p) * L + i] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  fft_lds<W, kThreads, kMaxLen * W, INV>(buf, tw, pl);
+  for (int e = threadIdx.x; e < L * W; e += kThreads) {
+    const int p = e / L, i = e % L;
+    if (b0 + p < batch) out[(long long)(b0 + p) * L + i] = buf[i * W + p];
+  }
+}
+
+}  // namespace csngf

@@ -1,0 +1,121 @@
+"""The C-ABI library: it loads, exports every symbol the headers declare, and rejects bad
+arguments (no GPU needed for any of this)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2110_10156_amd import binding as bd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _gpu_present():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+def _declared_functions():
+    names = set()
+    for h in ("csngf.h", "csngf_debug.h"):
+        text = open(os.path.join(ROOT, "include", h)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b(csngf_[a-z_0-9]+)\s*\(", text))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    L = bd.lib()
+    declared = _declared_functions()
+    assert len(declared) >= 14
+    for name in declared:
+        assert hasattr(L, name), name
+        assert name in bd.SIGNATURES, name
+
+
+def test_struct_sizes_match_header_layout():
+    assert C.sizeof(bd.Params) == 32
+    assert C.sizeof(bd.RotResult) == 32
+    assert C.sizeof(bd.Best) == 32 + 72
+    assert C.sizeof(bd.Dims) == 12
+
+
+def test_default_params():
+    p = bd.default_params()
+    assert p.struct_size == C.sizeof(bd.Params)
+    assert abs(p.eps - 1e-5) < 1e-12 and p.gamma == 0.5
+    assert list(p.pad) == [0, 0, 0] and p.batch == 0 and p.flags == 0
+
+
+@pytest.mark.parametrize("L,ok", [(8, 1), (64, 1), (220, 1), (352, 1), (192, 1), (110, 1), (440, 1), (512, 1),
+                                  (6, 0), (13, 0), (26, 0), (514, 0), (1024, 0), (63, 0), (0, 0), (-4, 0)])
+def test_supported_lengths(L, ok):
+    assert bd.lib().csngf_supported_length(L) == ok
+
+
+def _create(A, dB, mask=None, params=None):
+    h = C.c_void_p()
+    rc = bd.lib().csngf_create(None if A is None else A.ctypes.data, bd.dims_of(A) if A is not None else bd.Dims(8, 8, 8),
+                               None if mask is None else mask.ctypes.data, dB,
+                               None if params is None else C.byref(params), C.byref(h))
+    return rc, h
+
+
+def test_create_rejects_bad_arguments_before_touching_a_device():
+    A = np.zeros((8, 8, 8), dtype=np.float32)
+    dB = bd.Dims(8, 8, 8)
+    assert _create(None, dB)[0] == bd.E_INVALID_ARG
+    assert b"NULL" in bd.lib().csngf_last_error()
+    assert _create(np.zeros((2, 8, 8), np.float32), dB)[0] == bd.E_INVALID_ARG
+    assert _create(A, bd.Dims(8, 2, 8))[0] == bd.E_INVALID_ARG
+    bad = A.copy()
+    bad[3, 3, 3] = np.nan
+    assert _create(bad, dB)[0] == bd.E_INVALID_ARG
+    assert b"non-finite" in bd.lib().csngf_last_error()
+    p = bd.default_params()
+    p.gamma = 1.5
+    assert _create(A, dB, params=p)[0] == bd.E_INVALID_ARG
+    p = bd.default_params()
+    p.eps = 0.0
+    assert _create(A, dB, params=p)[0] == bd.E_INVALID_ARG
+    p = bd.default_params()
+    p.struct_size = 4
+    assert _create(A, dB, params=p)[0] == bd.E_INVALID_ARG
+    p = bd.default_params()
+    p.pad[0] = 10  # < 8 + 8 - 1
+    assert _create(A, dB, params=p)[0] == bd.E_INVALID_ARG
+    p = bd.default_params()
+    p.pad[0] = 26  # 2 * 13: not built
+    assert _create(A, dB, params=p)[0] == bd.E_UNSUPPORTED
+    assert _create(A, dB, mask=np.ones(A.shape, np.uint8))[0] == bd.E_UNSUPPORTED
+    assert _create(np.zeros((8, 8, 600), np.float32), dB)[0] == bd.E_UNSUPPORTED
+
+
+def test_other_entry_points_reject_null():
+    L = bd.lib()
+    assert L.csngf_destroy(None) == bd.E_INVALID_ARG
+    assert L.csngf_evaluate(None, None, None, None, 0, None, None) == bd.E_INVALID_ARG
+    assert L.csngf_evaluate_map(None, None, None, None, None, None) == bd.E_INVALID_ARG
+    assert L.csngf_set_stream(None, None) == bd.E_INVALID_ARG
+    assert L.csngf_get_info(None, None) == bd.E_INVALID_ARG
+    assert L.csngf_profile_enable(None, 1) == bd.E_INVALID_ARG
+    assert L.csngf_default_params(None) == bd.E_INVALID_ARG
+    assert L.csngf_debug_fft(None, None, 64, 1, 0, None) == bd.E_INVALID_ARG
+    x = C.c_void_p(16)
+    assert L.csngf_debug_fft(x, x, 26, 1, 0, None) == bd.E_UNSUPPORTED
+
+
+@pytest.mark.skipif(_gpu_present(), reason="a GPU is visible")
+def test_no_device_is_reported():
+    A = np.random.default_rng(0).random((8, 8, 8)).astype(np.float32)
+    rc, h = _create(A, bd.Dims(8, 8, 8))
+    assert rc == bd.E_NO_DEVICE
+    assert b"device" in bd.lib().csngf_last_error()
+    with pytest.raises(bd.CsngfError) as ei:
+        bd.Context(A, (8, 8, 8))
+    assert ei.value.code == bd.E_NO_DEVICE

@@ -1,0 +1,296 @@
+"""Parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Bar: overlap counts N exact, validity sets identical, |C_gpu - C_oracle| <= 1e-4 on valid
+displacements (the FP32 tolerance of the hot path), per-rotation argmax identical unless the
+oracle's best and runner-up are within 2e-4 (then the GPU's pick must score within 2e-4 of
+the oracle's best), and the overall (rotation, displacement) identical.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2110_10156_amd import binding as bd
+from paper_2110_10156_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+CTOL = 1e-4
+TIE = 2e-4
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _rand_rot(rng, max_deg=40.0):
+    return synth.axis_angle_matrix(rng.normal(size=3), math.radians(rng.uniform(0, max_deg)))
+
+
+def _oracle_maps(A, B, R, mask_b=None, gamma=0.5, P=None):
+    fa = O.fixed_fields(A)
+    fb = O.moving_fields(B, O.quantize_rotation(R), mask_b)
+    S, N = O.correlation_maps_fft(fa, fb, P)
+    C, valid = O.normalise(S, N, int(fa.mask.sum()), int(fb.mask.sum()), gamma)
+    return C, N, valid
+
+
+def _compare_maps(Cg, Ng, Co, No, tag):
+    assert Cg.shape == Co.shape, tag
+    assert np.array_equal(Ng, No), f"{tag}: overlap counts differ at {np.argwhere(Ng != No)[:5]}"
+    vg, vo = np.isfinite(Cg), np.isfinite(Co)
+    assert np.array_equal(vg, vo), f"{tag}: validity differs"
+    if vo.any():
+        err = float(np.max(np.abs(Cg[vo].astype(np.float64) - Co[vo])))
+        _say(tag, "max|dC| =", err, "valid =", int(vo.sum()))
+        assert err <= CTOL, f"{tag}: max |dC| {err}"
+        go, gg = O.argmax_map(Co), int(np.argmax(np.where(vg, Cg, -np.inf)))
+        sorted_o = np.sort(Co[vo])[::-1]
+        gap = sorted_o[0] - sorted_o[1] if sorted_o.size > 1 else np.inf
+        if gap >= TIE:
+            assert gg == go[1], f"{tag}: argmax {gg} vs {go[1]}"
+        else:
+            assert Co.flat[gg] >= go[0] - TIE
+
+
+# ----------------------------------------------------------------------------- FFT engine
+FFT_LENGTHS = [8, 10, 12, 14, 16, 20, 22, 24, 28, 32, 40, 44, 48, 56, 64, 66, 88, 96, 110, 112, 128, 160, 176,
+               192, 198, 220, 240, 256, 264, 320, 330, 352, 384, 440, 448, 480, 512]
+
+
+@pytest.mark.parametrize("inverse", [False, True])
+def test_fft_engine_against_numpy(inverse):
+    import torch
+    rng = np.random.default_rng(1)
+    for L in FFT_LENGTHS:
+        _say("fft", L, "inverse" if inverse else "forward")
+        batch = 37
+        x = (rng.normal(size=(batch, L)) + 1j * rng.normal(size=(batch, L))).astype(np.complex64)
+        xd = torch.from_numpy(x).cuda()
+        yd = torch.empty_like(xd)
+        bd.debug_fft(xd, inverse=inverse, out=yd)
+        y = yd.cpu().numpy().astype(np.complex128)
+        ref = np.fft.ifft(x.astype(np.complex128), axis=1) * L if inverse else np.fft.fft(x.astype(np.complex128), axis=1)
+        # FP32 FFT bound: error ~ c * 2^-24 * log2(L) * ||x||_2 per row
+        norm = np.sqrt(np.sum(np.abs(x) ** 2, axis=1, keepdims=True))
+        err = np.max(np.abs(y - ref) / norm)
+        assert err < 4 * 2.0 ** -24 * math.log2(L), (L, err)
+    # delta -> constant, constant -> delta
+    for L in (64, 220, 352):
+        d = np.zeros((16, L), np.complex64)
+        d[:, 0] = 1
+        yd = bd.debug_fft(torch.from_numpy(d).cuda(), inverse=inverse).cpu().numpy()
+        assert np.max(np.abs(yd - 1)) < 1e-6
+        c = np.ones((16, L), np.complex64)
+        yc = bd.debug_fft(torch.from_numpy(c).cuda(), inverse=inverse).cpu().numpy()
+        e = np.zeros(L)
+        e[0] = L
+        assert np.max(np.abs(yc - e)) < 1e-4 * L
+
+
+# ----------------------------------------------------------------------------- field stage
+def _field_bound(vol, n_oracle_g, eps):
+    """Per-voxel error budget of FP32 products: resampled values carry a few ulps of |B|,
+    which the NGF divides by sqrt(|g|^2 + eps^2)."""
+    scale = float(np.max(np.abs(vol)))
+    return 1e-6 + 16 * 2.0 ** -24 * scale / np.sqrt(n_oracle_g + eps * eps)
+
+
+@pytest.mark.parametrize("which", ["fixed", "identity", "rotated", "masked"])
+def test_field_stage_against_oracle(which):
+    rng = np.random.default_rng(2)
+    pair = synth.config0()
+    eps = 1e-5
+    vol = pair.A if which == "fixed" else pair.B
+    R = None if which == "fixed" else (np.eye(3) if which == "identity" else _rand_rot(rng, 50))
+    mask = None
+    if which == "masked":
+        mask = (rng.random(vol.shape) > 0.02).astype(np.uint8)
+    _say("fields", which)
+    prod, m = bd.debug_fields(vol, R=R, mask=mask, eps=eps)
+    if R is None:
+        f = O.fixed_fields(vol, None, eps)
+        g = O.gradient(vol)
+    else:
+        Rq = O.quantize_rotation(R)
+        f = O.moving_fields(vol, Rq, None if mask is None else mask.astype(bool), eps)
+        Bh, _ = O.rotate_resample(vol, Rq, None if mask is None else mask.astype(bool))
+        g = O.gradient(Bh)
+    assert np.array_equal(m.astype(bool), f.mask), "eroded masks differ"
+    g2 = np.sum(g * g, axis=0)
+    bound = _field_bound(vol, g2, eps)
+    for i, (k, l) in enumerate(((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))):
+        ref = np.where(f.mask, f.n[k] * f.n[l], 0.0)
+        err = np.abs(prod[i] - ref)
+        assert np.all(err <= bound), (which, i, float(np.max(err - bound)))
+
+
+# ----------------------------------------------------------------------------- full maps
+def test_config0_maps_and_shift_recovery():
+    pair = synth.config0()
+    _say("config0 map")
+    with bd.Context(pair.A, pair.dims_b, pad=pair.pad) as ctx:
+        assert tuple(ctx.info().pad) == (64, 64, 64)
+        Cg, Ng = ctx.evaluate_map(pair.B, np.eye(3))
+        per, best = ctx.evaluate(pair.B, pair.rotations)
+    Co, No, _ = _oracle_maps(pair.A, pair.B, np.eye(3), P=pair.pad)
+    _compare_maps(Cg, Ng, Co, No, "config0")
+    assert best.rot_index == 0 and tuple(best.shift) == pair.true_shift
+    res, _ = O.evaluate(pair.A, pair.B, pair.rotations, P_xyz=pair.pad)
+    assert tuple(per[0].shift) == res[0].shift and per[0].overlap == res[0].overlap
+    assert abs(per[0].score - res[0].score) <= CTOL
+
+
+@pytest.mark.parametrize("case", range(6))
+def test_random_small_pairs_full_maps(case):
+    """Uneven shapes (ragged tiles), n_A != n_B, rotations, user masks on B, gamma 0.25/0.5,
+    automatic and explicit padding."""
+    rng = np.random.default_rng(50 + case)
+    sa = tuple(int(v) for v in rng.integers(5, 23, size=3))
+    sb = tuple(int(v) for v in rng.integers(5, 23, size=3))
+    from scipy.ndimage import gaussian_filter
+    A = gaussian_filter(rng.random(sa), 1.0).astype(np.float32)
+    B = gaussian_filter(rng.random(sb), 1.0).astype(np.float32)
+    gamma = (0.25, 0.5)[case % 2]
+    mask_b = (rng.random(sb) > 0.03).astype(np.uint8) if case >= 3 else None
+    R = np.eye(3) if case == 0 else _rand_rot(rng, 60)
+    _say("random", case, sa, sb, gamma, mask_b is not None)
+    pad = (0, 0, 0)
+    if case == 5:  # explicit padding well above n_A + n_B - 1
+        need = [sa[2] + sb[2] - 1, sa[1] + sb[1] - 1, sa[0] + sb[0] - 1]
+        pad = tuple(next(L for L in range(n + 7, 513) if bd.supported_length(L)) for n in need)
+    with bd.Context(A, bd.dims_of(B), gamma=gamma, pad=pad) as ctx:
+        P = tuple(ctx.info().pad)
+        Cg, Ng = ctx.evaluate_map(B, R, mask_b=mask_b)
+        per, best = ctx.evaluate(B, np.stack([R, np.eye(3)]), mask_b=mask_b)
+    Co, No, _ = _oracle_maps(A, B, R, None if mask_b is None else mask_b.astype(bool), gamma, P)
+    _compare_maps(Cg, Ng, Co, No, f"random{case}")
+    # the per-rotation result of evaluate() equals the map's argmax
+    if np.isfinite(Cg).any():
+        flat = int(np.argmax(np.where(np.isfinite(Cg), Cg, -np.inf)))
+        iz, iy, ix = np.unravel_index(flat, Cg.shape)
+        assert tuple(per[0].shift) == (ix - (sa[2] - 1), iy - (sa[1] - 1), iz - (sa[0] - 1))
+        assert per[0].score == Cg.flat[flat] and per[0].overlap == Ng.flat[flat]
+
+
+def test_padding_invariance_and_minimum_extent():
+    rng = np.random.default_rng(9)
+    A = rng.random((3, 4, 5)).astype(np.float32)
+    B = rng.random((4, 3, 3)).astype(np.float32)
+    _say("minimum extents")
+    with bd.Context(A, bd.dims_of(B), gamma=0.0) as c1, bd.Context(A, bd.dims_of(B), gamma=0.0, pad=(16, 12, 16)) as c2:
+        C1, N1 = c1.evaluate_map(B, np.eye(3))
+        C2, N2 = c2.evaluate_map(B, np.eye(3))
+    Co, No, _ = _oracle_maps(A, B, np.eye(3), gamma=0.0)
+    _compare_maps(C1, N1, Co, No, "min-extent")
+    assert np.array_equal(N1, N2)
+    v = np.isfinite(C1)
+    assert np.max(np.abs(C1[v] - C2[v])) <= CTOL
+
+
+def test_config1_rotations_against_oracle():
+    pair = synth.config1()
+    rots = pair.rotations
+    _say("config1 evaluate", len(rots))
+    with bd.Context(pair.A, pair.dims_b, pad=pair.pad) as ctx:
+        per, best = ctx.evaluate(pair.B, rots)
+        Cg, Ng = ctx.evaluate_map(pair.B, rots[pair.true_index])
+    assert best.rot_index == pair.true_index
+    assert tuple(best.shift) == pair.true_shift
+    Co, No, _ = _oracle_maps(pair.A, pair.B, rots[pair.true_index], P=pair.pad)
+    _compare_maps(Cg, Ng, Co, No, "config1-true")
+    sample = [0, 1, 2, 3, 5, 8, 13, 21, 34, 55, 89, pair.true_index]
+    res, _ = O.evaluate(pair.A, pair.B, rots[sample], P_xyz=pair.pad, keep_maps=True)
+    for idx, r in zip(sample, res):
+        g = per[idx]
+        assert bool(g.valid) == r.valid
+        if not r.valid:
+            continue
+        C = r.C
+        v = np.isfinite(C)
+        top = np.sort(C[v])[::-1]
+        if top[0] - top[1] >= TIE:
+            assert tuple(g.shift) == r.shift, (idx, tuple(g.shift), r.shift)
+            assert g.overlap == r.overlap
+        iz, iy, ix = (g.shift[2] + pair.A.shape[0] - 1, g.shift[1] + pair.A.shape[1] - 1,
+                      g.shift[0] + pair.A.shape[2] - 1)
+        assert abs(g.score - C[iz, iy, ix]) <= CTOL
+        assert g.overlap == r.N[iz, iy, ix]
+        assert C[iz, iy, ix] >= top[0] - TIE
+
+
+def test_sign_invariance_and_repeatability_bit_identical():
+    pair = synth.config0()
+    rng = np.random.default_rng(3)
+    R = _rand_rot(rng)
+    with bd.Context(pair.A, pair.dims_b) as ctx:
+        C1, N1 = ctx.evaluate_map(pair.B, R)
+        C2, N2 = ctx.evaluate_map(-pair.B, R)
+        C3, N3 = ctx.evaluate_map(pair.B, R)
+    assert np.array_equal(C1, C2) and np.array_equal(N1, N2)
+    assert np.array_equal(C1, C3) and np.array_equal(N1, N3)
+
+
+def test_batch_invariance_bit_identical():
+    pair = synth.config1(n_random=20)
+    with bd.Context(pair.A, pair.dims_b, batch=1) as c1, bd.Context(pair.A, pair.dims_b, batch=7) as c7:
+        p1, b1 = c1.evaluate(pair.B, pair.rotations)
+        p7, b7 = c7.evaluate(pair.B, pair.rotations)
+    for a, b in zip(p1, p7):
+        assert a.score == b.score and tuple(a.shift) == tuple(b.shift) and a.overlap == b.overlap
+    assert b1.rot_index == b7.rot_index == pair.true_index
+
+
+def test_edge_cases():
+    rng = np.random.default_rng(4)
+    A = rng.random((6, 6, 6)).astype(np.float32)
+    B = rng.random((6, 6, 6)).astype(np.float32)
+    with bd.Context(A, bd.dims_of(B)) as ctx:
+        per, best = ctx.evaluate(B, np.zeros((0, 3, 3)))
+        assert best.rot_index == -1
+        bad = B.copy()
+        bad[1, 2, 3] = np.inf
+        with pytest.raises(bd.CsngfError) as ei:
+            ctx.evaluate(bad, np.eye(3)[None])
+        assert ei.value.code == bd.E_INVALID_ARG
+        with pytest.raises(bd.CsngfError):
+            ctx.evaluate(B, np.full((1, 3, 3), np.nan))
+        # an empty mask on B leaves no valid displacement
+        per, best = ctx.evaluate(B, np.eye(3)[None], mask_b=np.zeros(B.shape, np.uint8))
+        assert best.rot_index == -1 and per[0].valid == 0 and math.isinf(best.score)
+        with pytest.raises(bd.CsngfError) as ei:
+            ctx.evaluate(B, np.eye(3)[None], mask_b=np.zeros(B.shape, np.uint8), allow_no_valid=False)
+        assert ei.value.code == bd.E_NO_VALID_SHIFT
+    # gamma = 1 with a rotation keeps only displacements covering the whole smaller mask
+    with bd.Context(A, bd.dims_of(B), gamma=1.0) as ctx:
+        R = _rand_rot(rng, 30)
+        Cg, Ng = ctx.evaluate_map(B, R)
+    Co, No, _ = _oracle_maps(A, B, R, gamma=1.0)
+    _compare_maps(Cg, Ng, Co, No, "gamma1")
+
+
+def test_device_pointer_path_with_torch_stream():
+    import torch
+    pair = synth.config0()
+    dev = torch.device("cuda:0")
+    A = torch.from_numpy(pair.A).to(dev)
+    B = torch.from_numpy(pair.B).to(dev)
+    s = torch.cuda.Stream()
+    with bd.Context(A, pair.dims_b, stream=s) as ctx:
+        per, best = ctx.evaluate(B, pair.rotations)
+        W = tuple(ctx.info().map_dims)
+        Cm = torch.empty((W[2], W[1], W[0]), dtype=torch.float32, device=dev)
+        Nm = torch.empty((W[2], W[1], W[0]), dtype=torch.int64, device=dev)
+        ctx.evaluate_map(B, np.eye(3), out=(Cm, Nm))
+        s.synchronize()
+        bad = B.clone()
+        bad[0, 0, 0] = float("nan")
+        with pytest.raises(bd.CsngfError):
+            ctx.evaluate(bad, pair.rotations)
+    with bd.Context(pair.A, pair.dims_b) as hctx:
+        Ch, Nh = hctx.evaluate_map(pair.B, np.eye(3))
+    assert np.array_equal(Cm.cpu().numpy(), Ch) and np.array_equal(Nm.cpu().numpy(), Nh)
+    assert tuple(best.shift) == pair.true_shift

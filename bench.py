@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""Throughput of the CSNGF hot path on one MI355X.
+
+A step is one csngf_evaluate call over a batch of rotations of the paper-scale pair
+(176x176x110 float32, ~3.4 Mvoxel, FFT size 352x352x220, 1000 random rotations): every
+rotation goes through resample -> NGF -> products -> forward FFT -> frequency MAC against
+A's resident spectra -> inverse FFT -> exact overlap -> normalise -> argmax.  Inputs are
+resident in HBM before the timed region.  Prints one JSON line.
+
+Roofline: per-kernel device time comes from HIP events the library records around every
+launch on its own stream during the timed steps; the dominant kernel's algorithmic bytes
+per launch (per-rotation bytes x rotations in the launch) divided by its mean launch time
+gives achieved GB/s against the 8 TB/s HBM peak.
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "rotations/s at 3.4 Mvoxel (full displacement map); p50/p99 alignment latency"
+
+
+def kernel_bytes(nA, nB, P):
+    """Algorithmic HBM bytes per rotation of each kernel family (complex64 = 8 B).
+
+    Pruned pencils: only nonzero input rows are read, H = Px/2 + 1 bins per row, only the
+    kept displacement rows are written; A's six conjugate spectra are read once per rotation.
+    """
+    nxA, nyA, nzA = nA
+    nxB, nyB, nzB = nB
+    Px, Py, Pz = P
+    H = Px // 2 + 1
+    Wx, Wy, Wz = (nA[i] + nB[i] - 1 for i in range(3))
+    vox = nxB * nyB * nzB
+    x1 = 6 * nzB * nyB * H * 8          # after the x pass
+    x2 = 6 * nzB * Py * H * 8           # after the y forward pass
+    spec = 6 * Pz * Py * H * 8          # A's conjugate spectra
+    y3 = Wz * Py * H * 8                # after the z inverse (kept rows)
+    y4 = Wz * Wy * H * 8                # after the y inverse (kept rows)
+    sat = 4 * (nxB + 1) * (nyB + 1) * (nzB + 1)
+    return {
+        "fields_x": 4 * vox + x1 + vox,              # B once, X1, eroded mask
+        "overlap_sat": vox + 5 * sat,                # mask in; table written, re-read, re-written twice
+        "y_forward": x1 + x2,
+        "z_mac_inverse": x2 + spec + y3,
+        "y_inverse": y3 + y4,
+        "x_c2r_argmax": y4,
+    }
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in ("csngf_kernels.hpp", "csngf_fft.hpp"):
+        with open(os.path.join(ROOT, "paper_2110_10156_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel, workload):
+    """Measured HBM bytes per launch from a committed rocprofv3 PMC summary, if it was taken
+    on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_pmc.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"source_hash:\s*([0-9a-f]+)", text)
+    b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    r = re.search(r"rotations_per_launch:\s*([0-9]+)", text)
+    if not (m and b and r) or m.group(1) != source_hash():
+        return None
+    return float(b.group(1)), int(r.group(1))
+
+
+def cpu_baseline(pair, n_rot):
+    from oracle import csngf_oracle as O
+    rots = pair.rotations[:n_rot]
+    t0 = time.perf_counter()
+    O.evaluate(pair.A, pair.B, rots, P_xyz=pair.pad)
+    dt = time.perf_counter() - t0
+    return {"value": n_rot / dt, "unit": "rotations/s", "cores": int(O.WORKERS), "kind": "oracle",
+            "sample": f"{n_rot} rotations of the 176x176x110 pair at FFT size 352x352x220 "
+                      f"(FP64 numpy/scipy, {dt:.1f} s; FFTs on {O.WORKERS} threads, the rest single-threaded)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--rotations", type=int, default=1000, help="rotations per step")
+    ap.add_argument("--batch", type=int, default=0, help="rotation slots in flight (0 = library default)")
+    ap.add_argument("--cpu-rotations", type=int, default=2, help="oracle sample size (0 = skip)")
+    ap.add_argument("--plain-rotations", type=int, default=64,
+                    help="rotations timed on the one-rotation-per-launch path (0 = skip)")
+    ap.add_argument("--no-profile", action="store_true", help="do not record per-kernel events")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build runs on a single MI355X "
+              f"(asked for --gpus {args.gpus}).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2110_10156_amd import binding as bd
+    from paper_2110_10156_amd import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    pair = synth.config2(n_random=args.rotations)
+    rots = pair.rotations[:args.rotations]
+    A = torch.from_numpy(pair.A).to(dev)
+    B = torch.from_numpy(pair.B).to(dev)
+    torch.cuda.synchronize()
+
+    ctx = bd.Context(A, pair.dims_b, pad=pair.pad, batch=args.batch)
+    info = ctx.info()
+    slots = info.batch
+    print(f"[bench] ctx ready: P={tuple(info.pad)} slots={slots} "
+          f"spectra {info.spectra_bytes / 2**20:.0f} MiB workspace {info.workspace_bytes / 2**30:.2f} GiB",
+          file=sys.stderr, flush=True)
+    for i in range(args.warmup):
+        ctx.evaluate(B, rots)
+        print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    if not args.no_profile:
+        ctx.profile_reset()
+        ctx.profile_enable(True)
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ts = time.perf_counter()
+        per, best = ctx.evaluate(B, rots)     # synchronous: returns with results on the host
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    print(f"[bench] timed {args.steps} steps", file=sys.stderr, flush=True)
+    stats = {}
+    if not args.no_profile:
+        stats = ctx.profile_read()
+        ctx.profile_enable(False)
+    elapsed = t1 - t0
+    value = args.steps * len(rots) / elapsed
+
+    roofline = None
+    kb = kernel_bytes(pair.dims_a, pair.dims_b, tuple(info.pad))
+    if stats:
+        dom = max((k for k in kb if stats.get(k, (0, 0))[0] > 0), key=lambda k: stats[k][1])
+        launches, ms = stats[dom]
+        per_launch_rot = len(rots) * args.steps / launches
+        alg = kb[dom] * per_launch_rot
+        avg_s = ms / launches / 1e3
+        achieved = alg / avg_s / 1e9
+        tr = read_traffic(dom, "176x176x110")
+        traffic = None
+        if tr is not None:
+            traffic = tr[0] / tr[1] * per_launch_rot
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
+                    "avg_launch_ms": round(avg_s * 1e3, 4), "rotations_per_launch": per_launch_rot,
+                    "alg_bytes_per_launch": alg,
+                    "kernels_ms_per_rotation": {k: round(v[1] / (len(rots) * args.steps), 5)
+                                                for k, v in stats.items() if v[0]}}
+        print(f"[bench] kernel ms/rotation: {roofline['kernels_ms_per_rotation']}", file=sys.stderr, flush=True)
+
+    plain = None
+    if args.plain_rotations > 0:
+        with bd.Context(A, pair.dims_b, pad=pair.pad, batch=1) as pctx:
+            pr = rots[:args.plain_rotations]
+            pctx.evaluate(B, pr[:4])
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            pctx.evaluate(B, pr)
+            torch.cuda.synchronize()
+            plain = len(pr) / (time.perf_counter() - ts)
+        print(f"[bench] plain path {plain:.1f} rot/s", file=sys.stderr, flush=True)
+
+    cpu = None
+    if args.cpu_rotations > 0:
+        cpu = cpu_baseline(pair, args.cpu_rotations)
+        print(f"[bench] oracle {cpu['value']:.3f} rot/s", file=sys.stderr, flush=True)
+
+    lat_ms = np.array(lat) * 1e3
+    yard = sum(kernel_bytes(pair.dims_a, pair.dims_b, tuple(info.pad)).values())
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "rotations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "176x176x110 float32 pair (3.4 Mvoxel), 4-class shell phantom, "
+                               f"{len(rots)} random rotations per step, FFT 352x352x220, full displacement map",
+                   "rotations_per_step": len(rots), "fft_size": list(info.pad), "slots": slots},
+        "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 3),
+                       "p99": round(float(np.percentile(lat_ms, 99)), 3),
+                       "what": f"one csngf_evaluate call of {len(rots)} rotations, host to host"},
+        "plain_rotations_per_s": None if plain is None else round(plain, 2),
+        "path_bytes_per_rotation": yard,
+        "path_hbm_frac": round(yard * value / (HBM_PEAK_GBS * 1e9), 4),
+        "best": {"rot_index": best.rot_index, "shift": list(best.shift), "score": best.score},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -45,6 +45,14 @@ from dataclasses import dataclass
 import numpy as np
 import scipy.fft as sfft
 
+import os
+
+# FFT worker threads: the CPU cores this process may use, at most 16.
+try:
+    WORKERS = max(1, min(16, len(os.sched_getaffinity(0))))
+except AttributeError:  # pragma: no cover
+    WORKERS = max(1, min(16, os.cpu_count() or 1))
+
 EPS_DEFAULT = 1e-5     # Sec. 2, after Eq. (1)
 GAMMA_DEFAULT = 0.5    # Sec. 3.2
 Q16 = 65536.0          # rotation-entry quantum (reading: fixed-point coordinates)
@@ -239,11 +247,11 @@ def correlation_maps_fft(fa: Fields, fb: Fields, P_xyz=None):
     for (k, l), w in zip(_PAIRS, _WEIGHTS):
         a = ma * fa.n[k] * fa.n[l]
         b = mb * fb.n[k] * fb.n[l]
-        term = w * np.conj(sfft.rfftn(a, s=P, workers=-1)) * sfft.rfftn(b, s=P, workers=-1)
+        term = w * np.conj(sfft.rfftn(a, s=P, workers=WORKERS)) * sfft.rfftn(b, s=P, workers=WORKERS)
         acc = term if acc is None else acc + term
-    S_circ = sfft.irfftn(acc, s=P, workers=-1)
-    N_prod = np.conj(sfft.rfftn(ma, s=P, workers=-1)) * sfft.rfftn(mb, s=P, workers=-1)
-    N_circ = sfft.irfftn(N_prod, s=P, workers=-1)
+    S_circ = sfft.irfftn(acc, s=P, workers=WORKERS)
+    N_prod = np.conj(sfft.rfftn(ma, s=P, workers=WORKERS)) * sfft.rfftn(mb, s=P, workers=WORKERS)
+    N_circ = sfft.irfftn(N_prod, s=P, workers=WORKERS)
     S = _linear_from_circular(S_circ, sa, sb, P)
     Nf = _linear_from_circular(N_circ, sa, sb, P)
     N = np.rint(Nf)

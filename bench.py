@@ -102,6 +102,8 @@ def main():
     ap.add_argument("--plain-rotations", type=int, default=64,
                     help="rotations timed on the one-rotation-per-launch path (0 = skip)")
     ap.add_argument("--no-profile", action="store_true", help="do not record per-kernel events")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -120,6 +122,15 @@ def main():
     A = torch.from_numpy(pair.A).to(dev)
     B = torch.from_numpy(pair.B).to(dev)
     torch.cuda.synchronize()
+
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib * 2**20 // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        print(f"[bench] calibration copy of {args.calib_copy_mib} MiB done", file=sys.stderr, flush=True)
 
     ctx = bd.Context(A, pair.dims_b, pad=pair.pad, batch=args.batch)
     info = ctx.info()

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "csngf.h"
@@ -89,11 +90,31 @@ void twiddles(int L, std::vector<float2>& out) {
 size_t a16(size_t b) { return (b + 15) & ~size_t(15); }
 
 size_t lds_fields(int Px, int nx) {
-  return a16(sizeof(float2) * Px) + a16(sizeof(float2) * Px * kRowsX) + a16(sizeof(float) * 3 * (kRowsX + 2) * nx) +
+  return a16(sizeof(float2) * Px) + a16(sizeof(float2) * Px * (kRowsX + 1)) + a16(sizeof(float) * 3 * (kRowsX + 2) * nx) +
          a16((size_t)3 * (kRowsX + 2) * nx);
 }
 size_t lds_pencil(int L) { return a16(sizeof(float2) * L) + a16(sizeof(float2) * L * kTileW); }
-size_t lds_final(int Px) { return a16(sizeof(float2) * Px) + a16(sizeof(float2) * Px * kRowsX); }
+size_t lds_final(int Px, int nxB) {
+  return a16(sizeof(float2) * Px) + a16(sizeof(float2) * Px * (kRowsX + 1)) + a16(sizeof(int) * 2 * kRowsX * (nxB + 1));
+}
+
+// Call fn with std::integral_constant<int, L> for lengths that have a compile-time instance
+// (kFastLengths) and std::integral_constant<int, 0> (run-time plan) otherwise.
+template <typename Fn>
+void with_len(int L, Fn&& fn) {
+  switch (L) {
+#define CSNGF_CASE(N)                          \
+  case N:                                      \
+    fn(std::integral_constant<int, N>{});      \
+    return;
+    CSNGF_CASE(16) CSNGF_CASE(32) CSNGF_CASE(64) CSNGF_CASE(96) CSNGF_CASE(128) CSNGF_CASE(192)
+    CSNGF_CASE(220) CSNGF_CASE(256) CSNGF_CASE(352)
+#undef CSNGF_CASE
+    default:
+      fn(std::integral_constant<int, 0>{});
+      return;
+  }
+}
 
 constexpr size_t kLdsDefault = 64 * 1024;
 constexpr size_t kLdsMax = 160 * 1024;
@@ -269,7 +290,6 @@ int check_dims(const csngf_dims& d, const char* what) {
 }
 
 // Launch helpers -------------------------------------------------------------------------
-int lmax_class(int L) { return L <= 256 ? 256 : 512; }
 
 int launch_pencil(csngf_ctx* c, bool inv, const float2* in, float2* out, int n_in, int n_out, int out_off,
                   const FftPlan& pl, long long in_g, long long out_g, int groups, long long in_s,
@@ -277,21 +297,15 @@ int launch_pencil(csngf_ctx* c, bool inv, const float2* in, float2* out, int n_i
   const dim3 grid(c->tiles, groups, slots);
   const size_t lds = lds_pencil(pl.L);
   hipEvent_t ev = prof_begin(c);
-  if (!inv) {
-    if (lmax_class(pl.L) == 256)
-      hipLaunchKernelGGL((k_pencil<false, 256>), grid, dim3(kThreads), lds, c->stream, in, out, n_in, n_out, out_off,
+  with_len(pl.L, [&](auto lc) {
+    constexpr int LC = decltype(lc)::value;
+    if (!inv)
+      hipLaunchKernelGGL((k_pencil<false, LC>), grid, dim3(kThreads), lds, c->stream, in, out, n_in, n_out, out_off,
                          pl, c->d_tw, c->H, c->Hp, in_g, out_g, in_s, out_s);
     else
-      hipLaunchKernelGGL((k_pencil<false, 512>), grid, dim3(kThreads), lds, c->stream, in, out, n_in, n_out, out_off,
+      hipLaunchKernelGGL((k_pencil<true, LC>), grid, dim3(kThreads), lds, c->stream, in, out, n_in, n_out, out_off,
                          pl, c->d_tw, c->H, c->Hp, in_g, out_g, in_s, out_s);
-  } else {
-    if (lmax_class(pl.L) == 256)
-      hipLaunchKernelGGL((k_pencil<true, 256>), grid, dim3(kThreads), lds, c->stream, in, out, n_in, n_out, out_off,
-                         pl, c->d_tw, c->H, c->Hp, in_g, out_g, in_s, out_s);
-    else
-      hipLaunchKernelGGL((k_pencil<true, 512>), grid, dim3(kThreads), lds, c->stream, in, out, n_in, n_out, out_off,
-                         pl, c->d_tw, c->H, c->Hp, in_g, out_g, in_s, out_s);
-  }
+  });
   prof_end(c, inv ? KT_YINV : KT_YFWD, ev);
   LAUNCHCHK(inv ? "k_pencil<inverse>" : "k_pencil<forward>");
   return CSNGF_OK;
@@ -302,17 +316,24 @@ int launch_fields(csngf_ctx* c, bool moving, const float* vol, const uint8_t* um
   const dim3 grid((n3[1] + kRowsX - 1) / kRowsX, n3[2], slots);
   const size_t lds = lds_fields(c->plx.L, n3[0]);
   if (lds > kLdsMax) return fail(CSNGF_E_UNSUPPORTED, "x extent too large for the field stage");
+  hipError_t ae = hipSuccess;
   hipEvent_t ev = prof_begin(c);
-  if (moving) {
-    HIPCHK(allow_lds(k_fields_x<true>, lds));
-    hipLaunchKernelGGL(k_fields_x<true>, grid, dim3(kThreads), lds, c->stream, vol, um, n3[0], n3[1], n3[2], rotq,
-                       c->eps, c->plx, c->d_tw, out, c->H, c->Hp, out_slot, mask_out, mask_slot, dbg);
-  } else {
-    HIPCHK(allow_lds(k_fields_x<false>, lds));
-    hipLaunchKernelGGL(k_fields_x<false>, grid, dim3(kThreads), lds, c->stream, vol, um, n3[0], n3[1], n3[2], rotq,
-                       c->eps, c->plx, c->d_tw, out, c->H, c->Hp, out_slot, mask_out, mask_slot, dbg);
-  }
+  with_len(c->plx.L, [&](auto lc) {
+    constexpr int LC = decltype(lc)::value;
+    if (moving) {
+      ae = allow_lds(k_fields_x<true, LC>, lds);
+      if (ae == hipSuccess)
+        hipLaunchKernelGGL((k_fields_x<true, LC>), grid, dim3(kThreads), lds, c->stream, vol, um, n3[0], n3[1], n3[2],
+                           rotq, c->eps, c->plx, c->d_tw, out, c->H, c->Hp, out_slot, mask_out, mask_slot, dbg);
+    } else {
+      ae = allow_lds(k_fields_x<false, LC>, lds);
+      if (ae == hipSuccess)
+        hipLaunchKernelGGL((k_fields_x<false, LC>), grid, dim3(kThreads), lds, c->stream, vol, um, n3[0], n3[1], n3[2],
+                           rotq, c->eps, c->plx, c->d_tw, out, c->H, c->Hp, out_slot, mask_out, mask_slot, dbg);
+    }
+  });
   prof_end(c, KT_FIELDS, ev);
+  if (ae != hipSuccess) return hip_fail(ae, "hipFuncSetAttribute(k_fields_x)");
   LAUNCHCHK("k_fields_x");
   return CSNGF_OK;
 }
@@ -353,14 +374,12 @@ int run_batch(csngf_ctx* c, const float* dB, const uint8_t* dmB, const int* rotq
     const size_t lds = lds_pencil(c->plz.L);
     const int out_off = c->P[2] - (c->nA[2] - 1);
     ev = prof_begin(c);
-    if (lmax_class(c->plz.L) == 256)
-      hipLaunchKernelGGL((k_zpass<256>), dim3(nb8), dim3(kThreads), lds, c->stream, c->d_buf2, c->d_spec, c->d_buf1,
+    with_len(c->plz.L, [&](auto lc) {
+      constexpr int LC = decltype(lc)::value;
+      hipLaunchKernelGGL((k_zpass<LC>), dim3(nb8), dim3(kThreads), lds, c->stream, c->d_buf2, c->d_spec, c->d_buf1,
                          c->nB[2], c->P[1], c->H, c->Hp, c->Wd[2], out_off, c->plz, c->d_tw, c->buf2_slot,
                          c->buf1_slot, c->tiles, slots, nreal);
-    else
-      hipLaunchKernelGGL((k_zpass<512>), dim3(nb8), dim3(kThreads), lds, c->stream, c->d_buf2, c->d_spec, c->d_buf1,
-                         c->nB[2], c->P[1], c->H, c->Hp, c->Wd[2], out_off, c->plz, c->d_tw, c->buf2_slot,
-                         c->buf1_slot, c->tiles, slots, nreal);
+    });
     prof_end(c, KT_ZPASS, ev);
     LAUNCHCHK("k_zpass");
   }
@@ -376,19 +395,26 @@ int run_batch(csngf_ctx* c, const float* dB, const uint8_t* dmB, const int* rotq
       g.nB[i] = c->nB[i];
     }
     const dim3 grid((c->Wd[1] + 2 * kRowsX - 1) / (2 * kRowsX), c->Wd[2], slots);
-    const size_t lds = lds_final(c->plx.L);
+    const size_t lds = lds_final(c->plx.L, c->nB[0]);
+    hipError_t ae = hipSuccess;
     ev = prof_begin(c);
-    if (cmap) {
-      HIPCHK(allow_lds(k_final_x<true>, lds));
-      hipLaunchKernelGGL(k_final_x<true>, grid, dim3(kThreads), lds, c->stream, c->d_buf2, c->d_sat, c->d_keys, g,
-                         c->Wd[0], c->Wd[1], c->Wd[2], c->H, c->Hp, c->plx, c->d_tw, c->buf2_slot, c->sat_slot,
-                         c->count_a, c->gamma, cmap, nmap);
-    } else {
-      HIPCHK(allow_lds(k_final_x<false>, lds));
-      hipLaunchKernelGGL(k_final_x<false>, grid, dim3(kThreads), lds, c->stream, c->d_buf2, c->d_sat, c->d_keys, g,
-                         c->Wd[0], c->Wd[1], c->Wd[2], c->H, c->Hp, c->plx, c->d_tw, c->buf2_slot, c->sat_slot,
-                         c->count_a, c->gamma, cmap, nmap);
-    }
+    with_len(c->plx.L, [&](auto lc) {
+      constexpr int LC = decltype(lc)::value;
+      if (cmap) {
+        ae = allow_lds(k_final_x<true, LC>, lds);
+        if (ae == hipSuccess)
+          hipLaunchKernelGGL((k_final_x<true, LC>), grid, dim3(kThreads), lds, c->stream, c->d_buf2, c->d_sat,
+                             c->d_keys, g, c->Wd[0], c->Wd[1], c->Wd[2], c->H, c->Hp, c->plx, c->d_tw, c->buf2_slot,
+                             c->sat_slot, c->count_a, c->gamma, cmap, nmap);
+      } else {
+        ae = allow_lds(k_final_x<false, LC>, lds);
+        if (ae == hipSuccess)
+          hipLaunchKernelGGL((k_final_x<false, LC>), grid, dim3(kThreads), lds, c->stream, c->d_buf2, c->d_sat,
+                             c->d_keys, g, c->Wd[0], c->Wd[1], c->Wd[2], c->H, c->Hp, c->plx, c->d_tw, c->buf2_slot,
+                             c->sat_slot, c->count_a, c->gamma, cmap, nmap);
+      }
+    });
+    if (ae != hipSuccess) return hip_fail(ae, "hipFuncSetAttribute(k_final_x)");
     prof_end(c, KT_FINAL, ev);
     LAUNCHCHK("k_final_x");
     ev = prof_begin(c);
@@ -600,12 +626,11 @@ int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims
       const float scale = (float)(1.0 / ((double)P[0] * (double)P[1] * (double)P[2]));
       const dim3 grid(c->tiles, P[1], 6);
       const size_t lds = lds_pencil(P[2]);
-      if (lmax_class(P[2]) == 256)
-        hipLaunchKernelGGL((k_zstore<256>), grid, dim3(kThreads), lds, c->stream, x2, c->d_spec, nA[2], P[1], c->H,
+      with_len(P[2], [&](auto lc) {
+        constexpr int LC = decltype(lc)::value;
+        hipLaunchKernelGGL((k_zstore<LC>), grid, dim3(kThreads), lds, c->stream, x2, c->d_spec, nA[2], P[1], c->H,
                            c->Hp, c->plz, c->d_tw, scale);
-      else
-        hipLaunchKernelGGL((k_zstore<512>), grid, dim3(kThreads), lds, c->stream, x2, c->d_spec, nA[2], P[1], c->H,
-                           c->Hp, c->plz, c->d_tw, scale);
+      });
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) rc = hip_fail(e, "k_zstore");
     }
@@ -804,12 +829,15 @@ int csngf_debug_fft(const void* in, void* out, int32_t L, int32_t batch, int32_t
   if (e == hipSuccess) {
     const dim3 grid((batch + kTileW - 1) / kTileW);
     const size_t lds = lds_pencil(L);
-    if (inverse)
-      hipLaunchKernelGGL(k_debug_fft<true>, grid, dim3(kThreads), lds, s, (const float2*)in, (float2*)out, batch, pl,
-                         dtw);
-    else
-      hipLaunchKernelGGL(k_debug_fft<false>, grid, dim3(kThreads), lds, s, (const float2*)in, (float2*)out, batch, pl,
-                         dtw);
+    with_len(L, [&](auto lc) {
+      constexpr int LC = decltype(lc)::value;
+      if (inverse)
+        hipLaunchKernelGGL((k_debug_fft<true, LC>), grid, dim3(kThreads), lds, s, (const float2*)in, (float2*)out,
+                           batch, pl, dtw);
+      else
+        hipLaunchKernelGGL((k_debug_fft<false, LC>), grid, dim3(kThreads), lds, s, (const float2*)in, (float2*)out,
+                           batch, pl, dtw);
+    });
     e = hipGetLastError();
   }
   hipError_t se = hipStreamSynchronize(s);

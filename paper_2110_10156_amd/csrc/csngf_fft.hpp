@@ -193,24 +193,227 @@ __device__ __forceinline__ void fft_stage(float2* __restrict__ buf, const float2
   __syncthreads();
 }
 
-// Whole transform.  Caller has synchronised after filling buf; on return buf holds the
-// result in natural order and the group is synchronised.
-template <int W, int T, int LW, bool INV>
+// ---------------------------------------------------------------- compile-time plans
+struct CPlan {
+  int nst;
+  int r[kMaxStages];
+  int ns[kMaxStages];
+};
+
+// Same factorisation as the host plan: odd radices first (11, 7, 5, 3), then 8, 4, 2.
+constexpr CPlan make_cplan(int L) {
+  CPlan p{0, {0}, {0}};
+  int n = L;
+  const int odd[4] = {11, 7, 5, 3};
+  for (int i = 0; i < 4; ++i)
+    while (n % odd[i] == 0) { p.r[p.nst++] = odd[i]; n /= odd[i]; }
+  while (n % 8 == 0) { p.r[p.nst++] = 8; n /= 8; }
+  while (n % 4 == 0) { p.r[p.nst++] = 4; n /= 4; }
+  while (n % 2 == 0) { p.r[p.nst++] = 2; n /= 2; }
+  int ns = 1;
+  for (int s = 0; s < p.nst; ++s) { p.ns[s] = ns; ns *= p.r[s]; }
+  return p;
+}
+
+// One stage with everything known at compile time (exact butterflies per thread, no
+// run-time division).
+template <int L, int R, int NS, int W, int T, bool INV>
+__device__ __forceinline__ void fft_stage_fixed(float2* __restrict__ buf, const float2* __restrict__ tw) {
+  constexpr int LR = L / R;
+  constexpr int NBF = LR * W;
+  constexpr int NB = (NBF + T - 1) / T;
+  constexpr int TWSTEP = L / (NS * R);
+  float2 v[NB][R];
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    const int bf = (int)threadIdx.x + u * T;
+    if (NBF % T == 0 || bf < NBF) {
+      const int p = bf % W, j = bf / W;
+#pragma unroll
+      for (int t = 0; t < R; ++t) v[u][t] = buf[(j + t * LR) * W + p];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    const int bf = (int)threadIdx.x + u * T;
+    if (NBF % T == 0 || bf < NBF) {
+      const int p = bf % W, j = bf / W;
+      const int k = j % NS, q = j / NS;
+      if constexpr (NS > 1) {
+#pragma unroll
+        for (int t = 1; t < R; ++t) {
+          float2 w = tw[t * k * TWSTEP];
+          if (INV) w.y = -w.y;
+          v[u][t] = cmul(v[u][t], w);
+        }
+      }
+      dft<R, INV>(v[u]);
+      const int base = q * NS * R + k;
+#pragma unroll
+      for (int t = 0; t < R; ++t) buf[(base + t * NS) * W + p] = v[u][t];
+    }
+  }
+  __syncthreads();
+}
+
+template <int L, int S, int W, int T, bool INV>
+__device__ __forceinline__ void fft_fixed(float2* __restrict__ buf, const float2* __restrict__ tw) {
+  constexpr CPlan P = make_cplan(L);
+  if constexpr (S < P.nst) {
+    fft_stage_fixed<L, P.r[S], P.ns[S], W, T, INV>(buf, tw);
+    fft_fixed<L, S + 1, W, T, INV>(buf, tw);
+  }
+}
+
+// Whole transform.  LC > 0: the length is LC, planned at compile time.  LC == 0: run-time
+// plan pl (any supported length up to kMaxLen).  Caller has synchronised after filling buf;
+// on return buf holds the result in natural order and the group is synchronised.
+template <int W, int T, int LC, bool INV>
 __device__ void fft_lds(float2* __restrict__ buf, const float2* __restrict__ tw, const FftPlan& pl) {
-  for (int s = 0; s < pl.nst; ++s) {
-    const int ns = pl.ns[s];
-    switch (pl.radix[s]) {
-      case 2: fft_stage<2, W, T, LW, INV>(buf, tw, pl.L, ns); break;
-      case 3: fft_stage<3, W, T, LW, INV>(buf, tw, pl.L, ns); break;
-      case 4: fft_stage<4, W, T, LW, INV>(buf, tw, pl.L, ns); break;
-      case 5: fft_stage<5, W, T, LW, INV>(buf, tw, pl.L, ns); break;
-      case 7: fft_stage<7, W, T, LW, INV>(buf, tw, pl.L, ns); break;
-      case 8: fft_stage<8, W, T, LW, INV>(buf, tw, pl.L, ns); break;
-      case 11: fft_stage<11, W, T, LW, INV>(buf, tw, pl.L, ns); break;
-      default: break;
+  if constexpr (LC > 0) {
+    fft_fixed<LC, 0, W, T, INV>(buf, tw);
+  } else {
+    constexpr int LW = kMaxLen * W;
+    for (int s = 0; s < pl.nst; ++s) {
+      const int ns = pl.ns[s];
+      switch (pl.radix[s]) {
+        case 2: fft_stage<2, W, T, LW, INV>(buf, tw, pl.L, ns); break;
+        case 3: fft_stage<3, W, T, LW, INV>(buf, tw, pl.L, ns); break;
+        case 4: fft_stage<4, W, T, LW, INV>(buf, tw, pl.L, ns); break;
+        case 5: fft_stage<5, W, T, LW, INV>(buf, tw, pl.L, ns); break;
+        case 7: fft_stage<7, W, T, LW, INV>(buf, tw, pl.L, ns); break;
+        case 8: fft_stage<8, W, T, LW, INV>(buf, tw, pl.L, ns); break;
+        case 11: fft_stage<11, W, T, LW, INV>(buf, tw, pl.L, ns); break;
+        default: break;
+      }
     }
   }
 }
+
+// ---------------------------------------------------------------- transform with fused I/O
+// Fixed-length transform of W pencils whose first stage takes its inputs from a producer
+// and whose last stage hands its outputs to a consumer, so that neither passes through LDS:
+//   ld(i, p)            -> float2   input element i of pencil p           (IN_LDS = false)
+//   st(k, p, v, slot)              output element k of pencil p; slot is a compile-time
+//                                  index (butterfly * R + t) unique per thread (OUT_LDS = false)
+// With IN_LDS the first stage reads buf in natural order instead; with OUT_LDS the last
+// stage writes buf in natural order instead.  buf must not be in use by other threads on
+// entry (caller synchronises).  On return the group is NOT synchronised after the last
+// stage; callers reusing buf (or reading it with OUT_LDS) must __syncthreads() first.
+template <int L, int R, int NS, int W, int WS, int T, bool INV, bool FROM_LD, bool TO_ST, typename LD, typename ST>
+__device__ __forceinline__ void fft_stage_io(float2* __restrict__ buf, const float2* __restrict__ tw, LD& ld, ST& st) {
+  constexpr int LR = L / R;
+  constexpr int NBF = LR * W;
+  constexpr int NB = (NBF + T - 1) / T;
+  constexpr int TWSTEP = L / (NS * R);
+  float2 v[NB][R];
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    const int bf = (int)threadIdx.x + u * T;
+    if (NBF % T == 0 || bf < NBF) {
+      const int p = bf % W, j = bf / W;
+#pragma unroll
+      for (int t = 0; t < R; ++t) v[u][t] = FROM_LD ? ld(j + t * LR, p) : buf[(j + t * LR) * WS + p];
+    }
+  }
+  if constexpr (!FROM_LD && !TO_ST) __syncthreads();
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    const int bf = (int)threadIdx.x + u * T;
+    if (NBF % T == 0 || bf < NBF) {
+      const int p = bf % W, j = bf / W;
+      const int k = j % NS, q = j / NS;
+      if constexpr (NS > 1) {
+#pragma unroll
+        for (int t = 1; t < R; ++t) {
+          float2 w = tw[t * k * TWSTEP];
+          if (INV) w.y = -w.y;
+          v[u][t] = cmul(v[u][t], w);
+        }
+      }
+      dft<R, INV>(v[u]);
+      const int base = q * NS * R + k;
+#pragma unroll
+      for (int t = 0; t < R; ++t) {
+        if constexpr (TO_ST) st(base + t * NS, p, v[u][t], u * R + t);
+        else buf[(base + t * NS) * WS + p] = v[u][t];
+      }
+    }
+  }
+  if constexpr (!TO_ST) __syncthreads();
+}
+
+template <int L, int S, int W, int WS, int T, bool INV, bool IN_LDS, bool OUT_LDS, typename LD, typename ST>
+__device__ __forceinline__ void fft_io_stages(float2* __restrict__ buf, const float2* __restrict__ tw, LD& ld, ST& st) {
+  constexpr CPlan P = make_cplan(L);
+  if constexpr (S < P.nst) {
+    constexpr bool first = (S == 0), last = (S + 1 == P.nst);
+    fft_stage_io<L, P.r[S], P.ns[S], W, WS, T, INV, first && !IN_LDS, last && !OUT_LDS>(buf, tw, ld, st);
+    fft_io_stages<L, S + 1, W, WS, T, INV, IN_LDS, OUT_LDS>(buf, tw, ld, st);
+  }
+}
+
+// Call f(k, p, slot) for every output element a thread owns in the last stage of a
+// fixed-length plan (same ownership and slot numbering as the consumer of fft_io).
+template <int L, int W, int T, typename F>
+__device__ __forceinline__ void for_each_last_slot(F&& f) {
+  constexpr CPlan P = make_cplan(L);
+  constexpr int R = P.r[P.nst - 1], NS = P.ns[P.nst - 1];
+  constexpr int NBF = (L / R) * W, NB = (NBF + T - 1) / T;
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    const int bf = (int)threadIdx.x + u * T;
+    if (NBF % T == 0 || bf < NBF) {
+      const int p = bf % W, j = bf / W;
+      const int k = j % NS, q = j / NS;
+      const int base = q * NS * R + k;
+#pragma unroll
+      for (int t = 0; t < R; ++t) f(base + t * NS, p, u * R + t);
+    }
+  }
+}
+
+// Number of consumer slots per thread in the last stage of a fixed-length plan.
+template <int L, int W, int T>
+constexpr int last_slots() {
+  constexpr CPlan P = make_cplan(L);
+  constexpr int R = P.r[P.nst - 1];
+  return ((L / R) * W + T - 1) / T * R;
+}
+
+// Consumer slots per thread for fft_io: the last stage's outputs (LC > 0) or the strided
+// loop over the whole tile of the run-time path (LC == 0).
+template <int LC, int W, int T>
+constexpr int consumer_slots() {
+  if constexpr (LC > 0) return last_slots<LC, W, T>();
+  else return (kMaxLen * W + T - 1) / T;
+}
+
+// LC > 0: compile-time plan with fused I/O.  LC == 0: run-time plan: the producer fills buf,
+// the LDS transform runs, and the consumer reads buf (slot = position in the thread's loop).
+template <int LC, int W, int T, bool INV, bool IN_LDS, bool OUT_LDS, int WS = W, typename LD, typename ST>
+__device__ __forceinline__ void fft_io(float2* __restrict__ buf, const float2* __restrict__ tw, const FftPlan& pl,
+                                       LD&& ld, ST&& st) {
+  static_assert(LC > 0 || WS == W, "padded rows need a compile-time plan");
+  if constexpr (LC > 0) {
+    fft_io_stages<LC, 0, W, WS, T, INV, IN_LDS, OUT_LDS>(buf, tw, ld, st);
+  } else {
+    const int L = pl.L;
+    if constexpr (!IN_LDS) {
+      for (int e = threadIdx.x; e < L * W; e += T) buf[e] = ld(e / W, e % W);
+    }
+    __syncthreads();
+    fft_lds<W, T, 0, INV>(buf, tw, pl);
+    if constexpr (!OUT_LDS) {
+      int slot = 0;
+      for (int e = threadIdx.x; e < L * W; e += T, ++slot) st(e / W, e % W, buf[e], slot);
+    }
+  }
+}
+
+// Lengths with a compile-time instance; every other supported length uses the run-time plan.
+constexpr int kFastLengths[] = {16, 32, 64, 96, 128, 192, 220, 256, 352};
 
 // Copy this length's twiddle table into LDS (caller synchronises before use).
 __device__ __forceinline__ void load_twiddles(float2* __restrict__ dst, const float2* __restrict__ table,

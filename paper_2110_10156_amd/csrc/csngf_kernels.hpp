@@ -77,22 +77,27 @@ __device__ __forceinline__ size_t align16(size_t b) { return (b + 15) & ~size_t(
 
 // ------------------------------------------------------------------------------ x pass
 // One workgroup: slice z, rows y0 .. y0+kRowsX-1 of one rotation slot.  The halo (rows
-// y0-1 .. y0+kRowsX, slices z-1 .. z+1) is sampled into LDS, then for each of the 3 field
-// pairs (xx,yy), (zz,xy), (xz,yz) the products are packed as re/im of one complex row,
-// transformed along x (length Px, zero padded from nx) and split into two half spectra.
-template <bool MOVING>
+// y0-1 .. y0+kRowsX, slices z-1 .. z+1) is sampled into LDS; then for each of the 3 field
+// pairs (xx,yy), (zz,xy), (xz,yz) the first FFT stage computes mask, NGF and the pair's
+// products straight from the halo (re = first field, im = second), the transform runs
+// along x (length Px, zero padded from nx) and the result is split into two half spectra.
+template <int LC>
+constexpr int xrow_stride() { return LC > 0 ? kRowsX + 1 : kRowsX; }
+
+template <bool MOVING, int LC>
 __global__ __launch_bounds__(kThreads) void k_fields_x(
     const float* __restrict__ vol, const uint8_t* __restrict__ umask, int nx, int ny, int nz,
     const int* __restrict__ rotq, float eps, FftPlan pl, const float2* __restrict__ twtab,
     float2* __restrict__ out, int H, int Hp, long long out_slot_stride,
     uint8_t* __restrict__ mask_out, long long mask_slot_stride, float* __restrict__ dbg_prod) {
   constexpr int TY = kRowsX;
+  constexpr int WS = xrow_stride<LC>();
   constexpr int HR = TY + 2;
   extern __shared__ __align__(16) unsigned char smem[];
   const int Px = pl.L;
   float2* tw = reinterpret_cast<float2*>(smem);
   float2* buf = reinterpret_cast<float2*>(smem + align16(sizeof(float2) * Px));
-  float* val = reinterpret_cast<float*>(smem + align16(sizeof(float2) * Px) + align16(sizeof(float2) * Px * TY));
+  float* val = reinterpret_cast<float*>(smem + align16(sizeof(float2) * Px) + align16(sizeof(float2) * Px * (TY + 1)));
   uint8_t* ok = reinterpret_cast<uint8_t*>(reinterpret_cast<unsigned char*>(val) +
                                            align16(sizeof(float) * 3 * HR * nx));
   const int y0 = blockIdx.x * TY;
@@ -101,80 +106,92 @@ __global__ __launch_bounds__(kThreads) void k_fields_x(
   const int* kq = MOVING ? rotq + 9 * slot : nullptr;
   load_twiddles(tw, twtab, pl);
 
-  // 1. halo samples
+  // 1. halo samples, HU per thread in flight
+  constexpr int HU = 4;
   const int nhalo = 3 * HR * nx;
-  for (int e = threadIdx.x; e < nhalo; e += kThreads) {
-    const int x = e % nx;
-    const int r = (e / nx) % HR;
-    const int pzl = e / (nx * HR);
-    const int yy = y0 + r - 1, zz = z + pzl - 1;
-    float v = 0.f;
-    bool good = false;
-    if (yy >= 0 && yy < ny && zz >= 0 && zz < nz) {
-      if (MOVING) {
-        good = resample_q16(vol, umask, nx, ny, nz, kq, x, yy, zz, v);
-      } else {
-        const long o = ((long)zz * ny + yy) * nx + x;
-        v = vol[o];
-        good = umask ? (umask[o] != 0) : true;
+  for (int base = 0; base < nhalo; base += HU * kThreads) {
+    float v[HU];
+    bool good[HU];
+#pragma unroll
+    for (int u = 0; u < HU; ++u) {
+      const int e = base + u * kThreads + (int)threadIdx.x;
+      v[u] = 0.f;
+      good[u] = false;
+      if (e < nhalo) {
+        const int x = e % nx;
+        const int r = (e / nx) % HR;
+        const int pzl = e / (nx * HR);
+        const int yy = y0 + r - 1, zz = z + pzl - 1;
+        if (yy >= 0 && yy < ny && zz >= 0 && zz < nz) {
+          if (MOVING) {
+            good[u] = resample_q16(vol, umask, nx, ny, nz, kq, x, yy, zz, v[u]);
+          } else {
+            const long o = ((long)zz * ny + yy) * nx + x;
+            v[u] = vol[o];
+            good[u] = umask ? (umask[o] != 0) : true;
+          }
+        }
       }
     }
-    val[e] = v;
-    ok[e] = good ? 1 : 0;
+#pragma unroll
+    for (int u = 0; u < HU; ++u) {
+      const int e = base + u * kThreads + (int)threadIdx.x;
+      if (e < nhalo) {
+        val[e] = v[u];
+        ok[e] = good[u] ? 1 : 0;
+      }
+    }
   }
   __syncthreads();
 
   const float eps2 = eps * eps;
+  const long nv = (long)nx * ny * nz;
+#pragma unroll 1
   for (int pair = 0; pair < 3; ++pair) {
-    // 2. products of this pair into the complex rows (re = first field, im = second)
-    for (int e = threadIdx.x; e < TY * Px; e += kThreads) {
-      const int x = e % Px;
-      const int r = e / Px;
-      float fa = 0.f, fb = 0.f;
-      if (x < nx) {
-        const int c = (1 * HR + r + 1) * nx + x;
-        const bool m = x >= 1 && x <= nx - 2 && ok[c] && ok[c - 1] && ok[c + 1] && ok[c - nx] &&
-                       ok[c + nx] && ok[c - HR * nx] && ok[c + HR * nx];
-        float n0 = 0.f, n1 = 0.f, n2 = 0.f;
-        if (m) {
-          const float gx = 0.5f * (val[c + 1] - val[c - 1]);
-          const float gy = 0.5f * (val[c + nx] - val[c - nx]);
-          const float gz = 0.5f * (val[c + HR * nx] - val[c - HR * nx]);
-          const float inv = 1.0f / sqrtf(gx * gx + gy * gy + gz * gz + eps2);
-          n0 = gx * inv;
-          n1 = gy * inv;
-          n2 = gz * inv;
-        }
-        if (pair == 0) { fa = n0 * n0; fb = n1 * n1; }
-        else if (pair == 1) { fa = n2 * n2; fb = n0 * n1; }
-        else { fa = n0 * n2; fb = n1 * n2; }
-        const int yy = y0 + r;
-        if (yy < ny) {
-          const long vox = ((long)z * ny + yy) * nx + x;
-          if (pair == 0 && mask_out) mask_out[slot * mask_slot_stride + vox] = m ? 1 : 0;
-          if (dbg_prod && slot == 0) {
-            const long nv = (long)nx * ny * nz;
-            dbg_prod[(2 * pair) * nv + vox] = fa;
-            dbg_prod[(2 * pair + 1) * nv + vox] = fb;
-          }
+    auto products = [&](int x, int r) -> float2 {
+      if (x >= nx) return make_float2(0.f, 0.f);
+      const int c = (1 * HR + r + 1) * nx + x;
+      const bool m = x >= 1 && x <= nx - 2 && ok[c] && ok[c - 1] && ok[c + 1] && ok[c - nx] && ok[c + nx] &&
+                     ok[c - HR * nx] && ok[c + HR * nx];
+      float n0 = 0.f, n1 = 0.f, n2 = 0.f;
+      if (m) {
+        const float gx = 0.5f * (val[c + 1] - val[c - 1]);
+        const float gy = 0.5f * (val[c + nx] - val[c - nx]);
+        const float gz = 0.5f * (val[c + HR * nx] - val[c - HR * nx]);
+        const float inv = 1.0f / sqrtf(gx * gx + gy * gy + gz * gz + eps2);
+        n0 = gx * inv;
+        n1 = gy * inv;
+        n2 = gz * inv;
+      }
+      float fa, fb;
+      if (pair == 0) { fa = n0 * n0; fb = n1 * n1; }
+      else if (pair == 1) { fa = n2 * n2; fb = n0 * n1; }
+      else { fa = n0 * n2; fb = n1 * n2; }
+      const int yy = y0 + r;
+      if (yy < ny) {
+        const long vox = ((long)z * ny + yy) * nx + x;
+        if (pair == 0 && mask_out) mask_out[slot * mask_slot_stride + vox] = m ? 1 : 0;
+        if (dbg_prod && slot == 0) {
+          dbg_prod[(2 * pair) * nv + vox] = fa;
+          dbg_prod[(2 * pair + 1) * nv + vox] = fb;
         }
       }
-      buf[x * TY + r] = make_float2(fa, fb);
-    }
+      return make_float2(fa, fb);
+    };
+    auto none = [](int, int, float2, int) {};
+    fft_io<LC, TY, kThreads, false, false, true, WS>(buf, tw, pl, products, none);
     __syncthreads();
-    fft_lds<TY, kThreads, kMaxLen * TY, false>(buf, tw, pl);
-    // 3. split the packed transform: Fa = (Z_k + conj Z_{P-k}) / 2, Fb = -i (Z_k - conj Z_{P-k}) / 2
-    for (int r = 0; r < TY; ++r) {
+    // split the packed transform: Fa = (Z_k + conj Z_{P-k}) / 2, Fb = -i (Z_k - conj Z_{P-k}) / 2
+    for (int e = threadIdx.x; e < TY * H; e += kThreads) {
+      const int r = e / H, k = e % H;
       const int yy = y0 + r;
-      if (yy >= ny) break;
+      if (yy >= ny) continue;
+      const float2 zk = buf[k * WS + r];
+      const float2 zc = buf[((Px - k) % Px) * WS + r];
       float2* oa = out + slot * out_slot_stride + (((long)(2 * pair) * nz + z) * ny + yy) * Hp;
       float2* ob = out + slot * out_slot_stride + (((long)(2 * pair + 1) * nz + z) * ny + yy) * Hp;
-      for (int k = threadIdx.x; k < H; k += kThreads) {
-        const float2 zk = buf[k * TY + r];
-        const float2 zc = buf[((Px - k) % Px) * TY + r];
-        oa[k] = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y - zc.y));
-        ob[k] = make_float2(0.5f * (zk.y + zc.y), 0.5f * (zc.x - zk.x));
-      }
+      oa[k] = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y - zc.y));
+      ob[k] = make_float2(0.5f * (zk.y + zc.y), 0.5f * (zc.x - zk.x));
     }
     __syncthreads();
   }
@@ -183,7 +200,7 @@ __global__ __launch_bounds__(kThreads) void k_fields_x(
 // ------------------------------------------------------------------------------ y passes
 // Pencils along the middle axis.  Workgroup (x-tile, group g, slot): input rows i < n_in of
 // in[g], zero beyond; output row c takes transform row (c + out_off) mod L.
-template <bool INV, int LMAX>
+template <bool INV, int LC>
 __global__ __launch_bounds__(kThreads) void k_pencil(
     const float2* __restrict__ in, float2* __restrict__ out, int n_in, int n_out, int out_off,
     FftPlan pl, const float2* __restrict__ twtab, int H, int Hp, long long in_gstride,
@@ -197,33 +214,32 @@ __global__ __launch_bounds__(kThreads) void k_pencil(
   const float2* src = in + blockIdx.z * in_sstride + blockIdx.y * in_gstride + kx0;
   float2* dst = out + blockIdx.z * out_sstride + blockIdx.y * out_gstride + kx0;
   load_twiddles(tw, twtab, pl);
-  for (int e = threadIdx.x; e < L * W; e += kThreads) {
-    const int i = e / W, p = e % W;
-    float2 v = make_float2(0.f, 0.f);
-    if (i < n_in && kx0 + p < H) v = src[(long)i * Hp + p];
-    buf[e] = v;
-  }
-  __syncthreads();
-  fft_lds<W, kThreads, LMAX * W, INV>(buf, tw, pl);
-  for (int e = threadIdx.x; e < n_out * W; e += kThreads) {
-    const int c = e / W, p = e % W;
-    if (kx0 + p < H) {
-      const int j = (c + out_off) % L;
-      dst[(long)c * Hp + p] = buf[j * W + p];
-    }
-  }
+  if (LC == 0) __syncthreads();
+  fft_io<LC, W, kThreads, INV, false, false>(
+      buf, tw, pl,
+      [&](int i, int p) -> float2 {
+        return (i < n_in && kx0 + p < H) ? src[(long long)i * Hp + p] : make_float2(0.f, 0.f);
+      },
+      [&](int k, int p, float2 v, int) {
+        int c = k - out_off;
+        if (c < 0) c += L;
+        if (c < n_out && kx0 + p < H) dst[(long long)c * Hp + p] = v;
+      });
 }
 
 // ------------------------------------------------------------------------------ z pass
 // Workgroup (ky, x-tile, slot), ordered so that the slots of one tile run back to back on
-// one XCD and share that tile of A's spectra through its L2.
-template <int LMAX>
+// one XCD and share that tile of A's spectra through its L2.  Per field: z forward with
+// the multiply-accumulate against A's conjugate spectrum done on the last stage's
+// registers; then the sum goes through LDS once for the z inverse, whose last stage
+// stores the kept displacement rows.
+template <int LC>
 __global__ __launch_bounds__(kThreads) void k_zpass(
     const float2* __restrict__ X2, const float2* __restrict__ spec, float2* __restrict__ Y3,
     int nz, int Py, int H, int Hp, int Wz, int out_off, FftPlan pl, const float2* __restrict__ twtab,
     long long x2_sstride, long long y3_sstride, int ntiles, int nslots, int nreal) {
   constexpr int W = kTileW;
-  constexpr int NE = (LMAX * W + kThreads - 1) / kThreads;
+  constexpr int NSLOT = consumer_slots<LC, W, kThreads>();
   extern __shared__ __align__(16) unsigned char smem[];
   const int Pz = pl.L;
   float2* tw = reinterpret_cast<float2*>(smem);
@@ -239,56 +255,50 @@ __global__ __launch_bounds__(kThreads) void k_zpass(
   const int ky = rest / ntiles;
   const int kx0 = tile * W;
   load_twiddles(tw, twtab, pl);
-  float2 acc[NE];
+  if (LC == 0) __syncthreads();
+  float2 acc[NSLOT];
 #pragma unroll
-  for (int u = 0; u < NE; ++u) acc[u] = make_float2(0.f, 0.f);
+  for (int u = 0; u < NSLOT; ++u) acc[u] = make_float2(0.f, 0.f);
   const long long fstride_x2 = (long long)nz * Py * Hp;
   const long long fstride_sp = (long long)Pz * Py * Hp;
+  const long long zs = (long long)Py * Hp;
+#pragma unroll 1
   for (int f = 0; f < 6; ++f) {
     const float2* src = X2 + slot * x2_sstride + f * fstride_x2 + (long long)ky * Hp + kx0;
-    for (int e = threadIdx.x; e < Pz * W; e += kThreads) {
-      const int i = e / W, p = e % W;
-      float2 v = make_float2(0.f, 0.f);
-      if (i < nz && kx0 + p < H) v = src[(long long)i * Py * Hp + p];
-      buf[e] = v;
-    }
-    __syncthreads();
-    fft_lds<W, kThreads, LMAX * W, false>(buf, tw, pl);
     const float2* a = spec + f * fstride_sp + (long long)ky * Hp + kx0;
-#pragma unroll
-    for (int u = 0; u < NE; ++u) {
-      const int e = threadIdx.x + u * kThreads;
-      if (e < Pz * W) {
-        const int i = e / W, p = e % W;
-        if (kx0 + p < H) {
-          const float2 s = a[(long long)i * Py * Hp + p];
-          const float2 v = buf[e];
-          acc[u].x = fmaf(v.x, s.x, fmaf(-v.y, s.y, acc[u].x));
-          acc[u].y = fmaf(v.x, s.y, fmaf(v.y, s.x, acc[u].y));
-        }
-      }
-    }
+    fft_io<LC, W, kThreads, false, false, false>(
+        buf, tw, pl,
+        [&](int i, int p) -> float2 {
+          return (i < nz && kx0 + p < H) ? src[(long long)i * zs + p] : make_float2(0.f, 0.f);
+        },
+        [&](int k, int p, float2 v, int sl) {
+          if (kx0 + p < H) {
+            const float2 sv = a[(long long)k * zs + p];
+            acc[sl].x = fmaf(v.x, sv.x, fmaf(-v.y, sv.y, acc[sl].x));
+            acc[sl].y = fmaf(v.x, sv.y, fmaf(v.y, sv.x, acc[sl].y));
+          }
+        });
     __syncthreads();
   }
-#pragma unroll
-  for (int u = 0; u < NE; ++u) {
-    const int e = threadIdx.x + u * kThreads;
-    if (e < Pz * W) buf[e] = acc[u];
+  if constexpr (LC > 0) {
+    for_each_last_slot<LC, W, kThreads>([&](int k, int p, int sl) { buf[k * W + p] = acc[sl]; });
+  } else {
+    int sl = 0;
+    for (int e = threadIdx.x; e < Pz * W; e += kThreads, ++sl) buf[e] = acc[sl];
   }
   __syncthreads();
-  fft_lds<W, kThreads, LMAX * W, true>(buf, tw, pl);
   float2* dst = Y3 + slot * y3_sstride + (long long)ky * Hp + kx0;
-  for (int e = threadIdx.x; e < Wz * W; e += kThreads) {
-    const int c = e / W, p = e % W;
-    if (kx0 + p < H) {
-      const int j = (c + out_off) % Pz;
-      dst[(long long)c * Py * Hp + p] = buf[j * W + p];
-    }
-  }
+  fft_io<LC, W, kThreads, true, true, false>(
+      buf, tw, pl, [](int, int) { return make_float2(0.f, 0.f); },
+      [&](int k, int p, float2 v, int) {
+        int c = k - out_off;
+        if (c < 0) c += Pz;
+        if (c < Wz && kx0 + p < H) dst[(long long)c * zs + p] = v;
+      });
 }
 
 // Fixed side: z forward of A's fields, stored as w_f * scale * conj(.) in spec[f][kz][ky][kx].
-template <int LMAX>
+template <int LC>
 __global__ __launch_bounds__(kThreads) void k_zstore(
     const float2* __restrict__ X2, float2* __restrict__ spec, int nz, int Py, int H, int Hp,
     FftPlan pl, const float2* __restrict__ twtab, float scale) {
@@ -301,24 +311,19 @@ __global__ __launch_bounds__(kThreads) void k_zstore(
   const int ky = blockIdx.y;
   const int f = blockIdx.z;
   load_twiddles(tw, twtab, pl);
-  const float2* src = X2 + (long long)f * nz * Py * Hp + (long long)ky * Hp + kx0;
-  for (int e = threadIdx.x; e < Pz * W; e += kThreads) {
-    const int i = e / W, p = e % W;
-    float2 v = make_float2(0.f, 0.f);
-    if (i < nz && kx0 + p < H) v = src[(long long)i * Py * Hp + p];
-    buf[e] = v;
-  }
-  __syncthreads();
-  fft_lds<W, kThreads, LMAX * W, false>(buf, tw, pl);
+  if (LC == 0) __syncthreads();
+  const long long zs = (long long)Py * Hp;
+  const float2* src = X2 + (long long)f * nz * zs + (long long)ky * Hp + kx0;
   const float w = (f >= 3 ? 2.0f : 1.0f) * scale;
-  float2* dst = spec + (long long)f * Pz * Py * Hp + (long long)ky * Hp + kx0;
-  for (int e = threadIdx.x; e < Pz * W; e += kThreads) {
-    const int i = e / W, p = e % W;
-    if (kx0 + p < H) {
-      const float2 v = buf[e];
-      dst[(long long)i * Py * Hp + p] = make_float2(w * v.x, -w * v.y);
-    }
-  }
+  float2* dst = spec + (long long)f * Pz * zs + (long long)ky * Hp + kx0;
+  fft_io<LC, W, kThreads, false, false, false>(
+      buf, tw, pl,
+      [&](int i, int p) -> float2 {
+        return (i < nz && kx0 + p < H) ? src[(long long)i * zs + p] : make_float2(0.f, 0.f);
+      },
+      [&](int k, int p, float2 v, int) {
+        if (kx0 + p < H) dst[(long long)k * zs + p] = make_float2(w * v.x, -w * v.y);
+      });
 }
 
 // ------------------------------------------------------------------------------ overlap SAT
@@ -416,71 +421,101 @@ __device__ __forceinline__ long long threshold(long long count_a, long long coun
 }
 
 // ------------------------------------------------------------------------------ final x pass
-// Workgroup (row pair group, zc, slot): 8 packed complex pencils = 16 output rows (yc).
+// Workgroup (row group, zc, slot): 8 packed complex pencils = 16 output rows (yc).
 // Two real rows with half spectra S1, S2 are recovered at once from Z = S1 + i S2 extended
-// by Hermitian symmetry: z = IFFT(Z), S1 row = Re z, S2 row = Im z.
-template <bool WRITE_MAP>
+// by Hermitian symmetry: z = IFFT(Z), S1 row = Re z, S2 row = Im z.  The first FFT stage
+// builds Z straight from the two rows; the last stage normalises and reduces in registers.
+// Overlaps: for a fixed-side box, N(chi) = D(hx + 1) - D(lx) where D(x) is the 4-corner
+// combination of the SAT over the row's z and y ranges; D rows are built in LDS first.
+template <bool WRITE_MAP, int LC>
 __global__ __launch_bounds__(kThreads) void k_final_x(
     const float2* __restrict__ Y4, const int* __restrict__ sat, unsigned long long* __restrict__ keys,
     OverlapGeom g, int Wx, int Wy, int Wz, int H, int Hp, FftPlan pl, const float2* __restrict__ twtab,
     long long y4_sstride, long long sat_sstride, long long count_a, float gamma,
     float* __restrict__ cmap, long long* __restrict__ nmap) {
   constexpr int WP = kRowsX;  // packed pencils
+  constexpr int NR = 2 * WP;  // output rows
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ unsigned long long red[kThreads / 64];
   const int Px = pl.L;
+  const int X1 = g.nB[0] + 1;
   float2* tw = reinterpret_cast<float2*>(smem);
   float2* buf = reinterpret_cast<float2*>(smem + align16(sizeof(float2) * Px));
-  const int yc0 = blockIdx.x * (2 * WP);
+  int* drow = reinterpret_cast<int*>(smem + align16(sizeof(float2) * Px) + align16(sizeof(float2) * Px * (WP + 1)));
+  const int yc0 = blockIdx.x * NR;
   const int zc = blockIdx.y;
   const int slot = blockIdx.z;
   const int* s = sat + slot * sat_sstride;
   load_twiddles(tw, twtab, pl);
   const float2* rows = Y4 + slot * y4_sstride + ((long long)zc * Wy) * Hp;
   const int half = Px / 2;
-  for (int e = threadIdx.x; e < WP * H; e += kThreads) {
-    const int p = e / H, k = e % H;
-    const int r0 = yc0 + 2 * p, r1 = r0 + 1;
-    const float2 a = (r0 < Wy) ? rows[(long long)r0 * Hp + k] : make_float2(0.f, 0.f);
-    const float2 c = (r1 < Wy) ? rows[(long long)r1 * Hp + k] : make_float2(0.f, 0.f);
-    if (k == 0 || k == half) {
-      buf[k * WP + p] = make_float2(a.x, c.x);
-    } else {
-      buf[k * WP + p] = make_float2(a.x - c.y, a.y + c.x);           // S1 + i S2
-      buf[(Px - k) * WP + p] = make_float2(a.x + c.y, c.x - a.y);    // conj(S1) + i conj(S2)
+  // D rows: for row rr (yc = yc0 + rr), D(x) = sum of the SAT over the row's z and y ranges
+  // up to column x (x = 0 .. nB_x); empty ranges give D = 0.
+  const int X = X1, Y = g.nB[1] + 1;
+  const int cz = zc - (g.nA[2] - 1);
+  const int lz = max(1 + cz, 0), hz = min(g.nA[2] - 2 + cz, g.nB[2] - 1);
+  for (int base = 0; base < NR * X1; base += 4 * kThreads) {
+    int d[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = base + u * kThreads + (int)threadIdx.x;
+      d[u] = 0;
+      if (e < NR * X1) {
+        const int rr = e / X1, x = e % X1;
+        const int cy = yc0 + rr - (g.nA[1] - 1);
+        const int ly = max(1 + cy, 0), hy = min(g.nA[1] - 2 + cy, g.nB[1] - 1);
+        if (lz <= hz && ly <= hy && yc0 + rr < Wy) {
+          const long long zh = (long long)(hz + 1) * Y, zl = (long long)lz * Y;
+          d[u] = s[(zh + hy + 1) * X + x] - s[(zl + hy + 1) * X + x] - s[(zh + ly) * X + x] + s[(zl + ly) * X + x];
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = base + u * kThreads + (int)threadIdx.x;
+      if (e < NR * X1) drow[e] = d[u];
     }
   }
-  __syncthreads();
-  fft_lds<WP, kThreads, kMaxLen * WP, true>(buf, tw, pl);
-
   const long long count_b = s[(long long)(g.nB[2] + 1) * (g.nB[1] + 1) * (g.nB[0] + 1) - 1];
   const long long thr = threshold(count_a, count_b, gamma);
-  const int cz = zc - (g.nA[2] - 1);
+  if (LC == 0) __syncthreads();
   unsigned long long best = 0ull;
-  for (int e = threadIdx.x; e < 2 * WP * Wx; e += kThreads) {
-    const int rr = e / Wx, cx = e % Wx;
-    const int yc = yc0 + rr;
-    if (yc >= Wy) continue;
-    const int p = rr >> 1;
+  auto pack = [&](int k, int p) -> float2 {
+    const int r0 = yc0 + 2 * p, r1 = r0 + 1;
+    const int kk = k <= half ? k : Px - k;
+    const float2 a = (r0 < Wy) ? rows[(long long)r0 * Hp + kk] : make_float2(0.f, 0.f);
+    const float2 c = (r1 < Wy) ? rows[(long long)r1 * Hp + kk] : make_float2(0.f, 0.f);
+    if (k == 0 || k == half) return make_float2(a.x, c.x);
+    if (k < half) return make_float2(a.x - c.y, a.y + c.x);  // S1 + i S2
+    return make_float2(a.x + c.y, c.x - a.y);                // conj(S1) + i conj(S2)
+  };
+  auto emit = [&](int j, int p, float2 zv, int) {
+    const int cx = (j + g.nA[0] - 1) % Px;
+    if (cx >= Wx) return;
     const int chx = cx - (g.nA[0] - 1);
-    const int j = (chx + Px) % Px;
-    const float2 zv = buf[j * WP + p];
-    const float sv = (rr & 1) ? zv.y : zv.x;
-    const int cy = yc - (g.nA[1] - 1);
-    const long long n = box_count(s, g, chx, cy, cz);
-    const bool valid = n >= thr;
-    const float c = valid ? sv / (float)n : -INFINITY;
-    const unsigned int canon = (unsigned int)(((long long)zc * Wy + yc) * Wx + cx);
-    if (valid) {
-      const unsigned long long key = ((unsigned long long)ordered_bits(c) << 32) | (0xFFFFFFFFu - canon);
-      best = key > best ? key : best;
+    const int lx = max(1 + chx, 0), hx = min(g.nA[0] - 2 + chx, g.nB[0] - 1);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int rr = 2 * p + h;
+      const int yc = yc0 + rr;
+      if (yc >= Wy) continue;
+      const float sv = h ? zv.y : zv.x;
+      const long long n = (lx <= hx) ? (long long)(drow[rr * X1 + hx + 1] - drow[rr * X1 + lx]) : 0;
+      const bool valid = n >= thr;
+      const float c = valid ? sv / (float)n : -INFINITY;
+      const unsigned int canon = (unsigned int)(((long long)zc * Wy + yc) * Wx + cx);
+      if (valid) {
+        const unsigned long long key = ((unsigned long long)ordered_bits(c) << 32) | (0xFFFFFFFFu - canon);
+        best = key > best ? key : best;
+      }
+      if (WRITE_MAP) {
+        const long long o = ((long long)zc * Wy + yc) * Wx + cx;
+        cmap[o] = c;
+        if (nmap) nmap[o] = n;
+      }
     }
-    if (WRITE_MAP) {
-      const long long o = ((long long)zc * Wy + yc) * Wx + cx;
-      cmap[o] = c;
-      if (nmap) nmap[o] = n;
-    }
-  }
+  };
+  fft_io<LC, WP, kThreads, true, false, false, (LC > 0 ? WP + 1 : WP)>(buf, tw, pl, pack, emit);
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) {
     const unsigned long long o = __shfl_xor(best, d, 64);
@@ -543,7 +578,7 @@ __global__ void k_check_finite(const float* __restrict__ v, long long n, int* __
 }
 
 // Batched C2C along a contiguous axis: in/out [batch][L]; 16 batch rows per workgroup.
-template <bool INV>
+template <bool INV, int LC>
 __global__ __launch_bounds__(kThreads) void k_debug_fft(const float2* __restrict__ in, float2* __restrict__ out,
                                                         int batch, FftPlan pl, const float2* __restrict__ twtab) {
   constexpr int W = kTileW;
@@ -553,16 +588,15 @@ __global__ __launch_bounds__(kThreads) void k_debug_fft(const float2* __restrict
   float2* buf = reinterpret_cast<float2*>(smem + align16(sizeof(float2) * L));
   const int b0 = blockIdx.x * W;
   load_twiddles(tw, twtab, pl);
-  for (int e = threadIdx.x; e < L * W; e += kThreads) {
-    const int p = e / L, i = e % L;
-    buf[i * W + p] = (b0 + p < batch) ? in[(long long)(b0 + p) * L + i] : make_float2(0.f, 0.f);
-  }
-  __syncthreads();
-  fft_lds<W, kThreads, kMaxLen * W, INV>(buf, tw, pl);
-  for (int e = threadIdx.x; e < L * W; e += kThreads) {
-    const int p = e / L, i = e % L;
-    if (b0 + p < batch) out[(long long)(b0 + p) * L + i] = buf[i * W + p];
-  }
+  if (LC == 0) __syncthreads();
+  fft_io<LC, W, kThreads, INV, false, false>(
+      buf, tw, pl,
+      [&](int i, int p) -> float2 {
+        return (b0 + p < batch) ? in[(long long)(b0 + p) * L + i] : make_float2(0.f, 0.f);
+      },
+      [&](int k, int p, float2 v, int) {
+        if (b0 + p < batch) out[(long long)(b0 + p) * L + k] = v;
+      });
 }
 
 }  // namespace csngf

@@ -177,6 +177,8 @@ struct csngf_ctx {
   long long mask_slot = 0;
   int* d_sat = nullptr;
   long long sat_slot = 0;
+  uint8_t* d_flags = nullptr;
+  long long flag_slot = 0;
   unsigned long long* d_keys = nullptr;
   RotResultDev* d_res = nullptr;
   int res_cap = 0;
@@ -254,6 +256,7 @@ void release(csngf_ctx* c) {
   dfree(c->d_buf2);
   dfree(c->d_mask);
   dfree(c->d_sat);
+  dfree(c->d_flags);
   dfree(c->d_keys);
   dfree(c->d_res);
   dfree(c->d_rot);
@@ -293,7 +296,7 @@ int check_dims(const csngf_dims& d, const char* what) {
 
 int launch_pencil(csngf_ctx* c, bool inv, const float2* in, float2* out, int n_in, int n_out, int out_off,
                   const FftPlan& pl, long long in_g, long long out_g, int groups, long long in_s,
-                  long long out_s, int slots) {
+                  long long out_s, int slots, const uint8_t* flags = nullptr, long long flag_s = 0) {
   const dim3 grid(c->tiles, groups, slots);
   const size_t lds = lds_pencil(pl.L);
   hipEvent_t ev = prof_begin(c);
@@ -301,10 +304,10 @@ int launch_pencil(csngf_ctx* c, bool inv, const float2* in, float2* out, int n_i
     constexpr int LC = decltype(lc)::value;
     if (!inv)
       hipLaunchKernelGGL((k_pencil<false, LC>), grid, dim3(kThreads), lds, c->stream, in, out, n_in, n_out, out_off,
-                         pl, c->d_tw, c->H, c->Hp, in_g, out_g, in_s, out_s);
+                         pl, c->d_tw, c->H, c->Hp, in_g, out_g, in_s, out_s, flags, flag_s, groups);
     else
       hipLaunchKernelGGL((k_pencil<true, LC>), grid, dim3(kThreads), lds, c->stream, in, out, n_in, n_out, out_off,
-                         pl, c->d_tw, c->H, c->Hp, in_g, out_g, in_s, out_s);
+                         pl, c->d_tw, c->H, c->Hp, in_g, out_g, in_s, out_s, flags, flag_s, groups);
   });
   prof_end(c, inv ? KT_YINV : KT_YFWD, ev);
   LAUNCHCHK(inv ? "k_pencil<inverse>" : "k_pencil<forward>");
@@ -361,6 +364,14 @@ int run_batch(csngf_ctx* c, const float* dB, const uint8_t* dmB, const int* rotq
                        c->d_sat, nx, ny, nz, c->sat_slot, 0);
     hipLaunchKernelGGL(k_sat_cols, dim3((ny * nx + kThreads - 1) / kThreads, slots), dim3(kThreads), 0, c->stream,
                        c->d_sat, nx, ny, nz, c->sat_slot, 1);
+    OverlapGeom g;
+    for (int i = 0; i < 3; ++i) {
+      g.nA[i] = c->nA[i];
+      g.nB[i] = c->nB[i];
+    }
+    hipLaunchKernelGGL(k_bounds, dim3((c->Wd[2] * c->Wd[1] + kThreads - 1) / kThreads, slots), dim3(kThreads), 0,
+                       c->stream, c->d_sat, g, c->Wd[1], c->Wd[2], c->sat_slot, c->count_a, c->gamma, c->d_flags,
+                       c->flag_slot);
     prof_end(c, KT_SAT, ev);
     LAUNCHCHK("k_sat");
   }
@@ -378,7 +389,7 @@ int run_batch(csngf_ctx* c, const float* dB, const uint8_t* dmB, const int* rotq
       constexpr int LC = decltype(lc)::value;
       hipLaunchKernelGGL((k_zpass<LC>), dim3(nb8), dim3(kThreads), lds, c->stream, c->d_buf2, c->d_spec, c->d_buf1,
                          c->nB[2], c->P[1], c->H, c->Hp, c->Wd[2], out_off, c->plz, c->d_tw, c->buf2_slot,
-                         c->buf1_slot, c->tiles, slots, nreal);
+                         c->buf1_slot, c->tiles, slots, nreal, c->d_flags, c->flag_slot);
     });
     prof_end(c, KT_ZPASS, ev);
     LAUNCHCHK("k_zpass");
@@ -386,7 +397,7 @@ int run_batch(csngf_ctx* c, const float* dB, const uint8_t* dmB, const int* rotq
   // y inverse: Y3 [slot][zc][ky] -> Y4 [slot][zc][yc]
   rc = launch_pencil(c, true, c->d_buf1, c->d_buf2, c->P[1], c->Wd[1], c->P[1] - (c->nA[1] - 1), c->ply,
                      (long long)c->P[1] * c->Hp, (long long)c->Wd[1] * c->Hp, c->Wd[2], c->buf1_slot, c->buf2_slot,
-                     slots);
+                     slots, c->d_flags, c->flag_slot);
   if (rc) return rc;
   {
     OverlapGeom g;
@@ -405,13 +416,13 @@ int run_batch(csngf_ctx* c, const float* dB, const uint8_t* dmB, const int* rotq
         if (ae == hipSuccess)
           hipLaunchKernelGGL((k_final_x<true, LC>), grid, dim3(kThreads), lds, c->stream, c->d_buf2, c->d_sat,
                              c->d_keys, g, c->Wd[0], c->Wd[1], c->Wd[2], c->H, c->Hp, c->plx, c->d_tw, c->buf2_slot,
-                             c->sat_slot, c->count_a, c->gamma, cmap, nmap);
+                             c->sat_slot, c->count_a, c->gamma, cmap, nmap, c->d_flags, c->flag_slot);
       } else {
         ae = allow_lds(k_final_x<false, LC>, lds);
         if (ae == hipSuccess)
           hipLaunchKernelGGL((k_final_x<false, LC>), grid, dim3(kThreads), lds, c->stream, c->d_buf2, c->d_sat,
                              c->d_keys, g, c->Wd[0], c->Wd[1], c->Wd[2], c->H, c->Hp, c->plx, c->d_tw, c->buf2_slot,
-                             c->sat_slot, c->count_a, c->gamma, cmap, nmap);
+                             c->sat_slot, c->count_a, c->gamma, cmap, nmap, c->d_flags, c->flag_slot);
       }
     });
     if (ae != hipSuccess) return hip_fail(ae, "hipFuncSetAttribute(k_final_x)");
@@ -652,7 +663,9 @@ int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims
     c->buf2_slot = std::max(6LL * nB[2] * P[1], (long long)c->Wd[2] * c->Wd[1]) * Hp;
     c->mask_slot = (nvB + 255) / 256 * 256;
     c->sat_slot = ((long long)(nB[0] + 1) * (nB[1] + 1) * (nB[2] + 1) + 63) / 64 * 64;
-    const long long per = sizeof(float2) * (c->buf1_slot + c->buf2_slot) + c->mask_slot + 4 * c->sat_slot;
+    c->flag_slot = ((long long)c->Wd[2] * (1 + c->Wd[1]) + 255) / 256 * 256;
+    const long long per =
+        sizeof(float2) * (c->buf1_slot + c->buf2_slot) + c->mask_slot + 4 * c->sat_slot + c->flag_slot;
     int batch = prm.batch;
     if (batch == 0) {
       size_t fr = 0, tot = 0;
@@ -665,6 +678,7 @@ int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims
     if ((rc = dalloc(&c->d_buf2, sizeof(float2) * c->buf2_slot * batch))) return bail(rc);
     if ((rc = dalloc(&c->d_mask, (size_t)c->mask_slot * batch))) return bail(rc);
     if ((rc = dalloc(&c->d_sat, 4 * (size_t)c->sat_slot * batch))) return bail(rc);
+    if ((rc = dalloc(&c->d_flags, (size_t)c->flag_slot * batch))) return bail(rc);
     if ((rc = dalloc(&c->d_keys, sizeof(unsigned long long) * batch))) return bail(rc);
     c->workspace_bytes = per * batch;
   }

@@ -204,10 +204,16 @@ template <bool INV, int LC>
 __global__ __launch_bounds__(kThreads) void k_pencil(
     const float2* __restrict__ in, float2* __restrict__ out, int n_in, int n_out, int out_off,
     FftPlan pl, const float2* __restrict__ twtab, int H, int Hp, long long in_gstride,
-    long long out_gstride, long long in_sstride, long long out_sstride) {
+    long long out_gstride, long long in_sstride, long long out_sstride, const uint8_t* __restrict__ flags,
+    long long flag_sstride, int ngroups) {
   constexpr int W = kTileW;
   extern __shared__ __align__(16) unsigned char smem[];
   const int L = pl.L;
+  // flags (inverse pass only): group g is skipped when flags[g] == 0; output row c of group g
+  // is stored only when flags[ngroups + g * n_out + c] != 0.
+  const uint8_t* fl = flags ? flags + blockIdx.z * flag_sstride : nullptr;
+  if (fl && !fl[blockIdx.y]) return;
+  const uint8_t* rowfl = fl ? fl + ngroups + (long long)blockIdx.y * n_out : nullptr;
   float2* tw = reinterpret_cast<float2*>(smem);
   float2* buf = reinterpret_cast<float2*>(smem + align16(sizeof(float2) * L));
   const int kx0 = blockIdx.x * W;
@@ -223,7 +229,7 @@ __global__ __launch_bounds__(kThreads) void k_pencil(
       [&](int k, int p, float2 v, int) {
         int c = k - out_off;
         if (c < 0) c += L;
-        if (c < n_out && kx0 + p < H) dst[(long long)c * Hp + p] = v;
+        if (c < n_out && kx0 + p < H && (!rowfl || rowfl[c])) dst[(long long)c * Hp + p] = v;
       });
 }
 
@@ -237,7 +243,8 @@ template <int LC>
 __global__ __launch_bounds__(kThreads) void k_zpass(
     const float2* __restrict__ X2, const float2* __restrict__ spec, float2* __restrict__ Y3,
     int nz, int Py, int H, int Hp, int Wz, int out_off, FftPlan pl, const float2* __restrict__ twtab,
-    long long x2_sstride, long long y3_sstride, int ntiles, int nslots, int nreal) {
+    long long x2_sstride, long long y3_sstride, int ntiles, int nslots, int nreal,
+    const uint8_t* __restrict__ flags, long long flag_sstride) {
   constexpr int W = kTileW;
   constexpr int NSLOT = consumer_slots<LC, W, kThreads>();
   extern __shared__ __align__(16) unsigned char smem[];
@@ -288,12 +295,13 @@ __global__ __launch_bounds__(kThreads) void k_zpass(
   }
   __syncthreads();
   float2* dst = Y3 + slot * y3_sstride + (long long)ky * Hp + kx0;
+  const uint8_t* zflag = flags + slot * flag_sstride;
   fft_io<LC, W, kThreads, true, true, false>(
       buf, tw, pl, [](int, int) { return make_float2(0.f, 0.f); },
       [&](int k, int p, float2 v, int) {
         int c = k - out_off;
         if (c < 0) c += Pz;
-        if (c < Wz && kx0 + p < H) dst[(long long)c * zs + p] = v;
+        if (c < Wz && kx0 + p < H && zflag[c]) dst[(long long)c * zs + p] = v;
       });
 }
 
@@ -420,6 +428,36 @@ __device__ __forceinline__ long long threshold(long long count_a, long long coun
   return tt > 1 ? tt : 1;
 }
 
+// ------------------------------------------------------------------------------ gamma pruning
+// Upper bounds of N(chi) from the SAT: over a z-row (all y and x of B) and over a (z, y) row
+// (all x of B).  flags[slot] = zflag[Wz] then rowflag[Wz][Wy]; a 0 flag means no displacement
+// of that z-row (resp. row) can reach the overlap threshold, so the inverse passes skip it.
+__global__ __launch_bounds__(kThreads) void k_bounds(const int* __restrict__ sat, OverlapGeom g, int Wy, int Wz,
+                                                     long long sat_sstride, long long count_a, float gamma,
+                                                     uint8_t* __restrict__ flags, long long flag_sstride) {
+  const int slot = blockIdx.y;
+  const int t = blockIdx.x * kThreads + threadIdx.x;
+  if (t >= Wz * Wy) return;
+  const int zc = t / Wy, yc = t % Wy;
+  const int* s = sat + slot * sat_sstride;
+  const int X = g.nB[0] + 1, Y = g.nB[1] + 1;
+  const long long count_b = s[(long long)(g.nB[2] + 1) * Y * X - 1];
+  const long long thr = threshold(count_a, count_b, gamma);
+  const int cz = zc - (g.nA[2] - 1), cy = yc - (g.nA[1] - 1);
+  const int lz = max(1 + cz, 0), hz = min(g.nA[2] - 2 + cz, g.nB[2] - 1);
+  const int ly = max(1 + cy, 0), hy = min(g.nA[1] - 2 + cy, g.nB[1] - 1);
+  uint8_t* f = flags + slot * flag_sstride;
+  auto at = [&](int z, int y) { return (long long)s[((long long)z * Y + y) * X + (X - 1)]; };
+  long long rb = 0;
+  if (lz <= hz && ly <= hy) rb = at(hz + 1, hy + 1) - at(lz, hy + 1) - at(hz + 1, ly) + at(lz, ly);
+  f[Wz + t] = rb >= thr ? 1 : 0;
+  if (yc == 0) {
+    long long pb = 0;
+    if (lz <= hz) pb = at(hz + 1, Y - 1) - at(lz, Y - 1);
+    f[zc] = pb >= thr ? 1 : 0;
+  }
+}
+
 // ------------------------------------------------------------------------------ final x pass
 // Workgroup (row group, zc, slot): 8 packed complex pencils = 16 output rows (yc).
 // Two real rows with half spectra S1, S2 are recovered at once from Z = S1 + i S2 extended
@@ -432,7 +470,8 @@ __global__ __launch_bounds__(kThreads) void k_final_x(
     const float2* __restrict__ Y4, const int* __restrict__ sat, unsigned long long* __restrict__ keys,
     OverlapGeom g, int Wx, int Wy, int Wz, int H, int Hp, FftPlan pl, const float2* __restrict__ twtab,
     long long y4_sstride, long long sat_sstride, long long count_a, float gamma,
-    float* __restrict__ cmap, long long* __restrict__ nmap) {
+    float* __restrict__ cmap, long long* __restrict__ nmap, const uint8_t* __restrict__ flags,
+    long long flag_sstride) {
   constexpr int WP = kRowsX;  // packed pencils
   constexpr int NR = 2 * WP;  // output rows
   extern __shared__ __align__(16) unsigned char smem[];
@@ -446,6 +485,14 @@ __global__ __launch_bounds__(kThreads) void k_final_x(
   const int zc = blockIdx.y;
   const int slot = blockIdx.z;
   const int* s = sat + slot * sat_sstride;
+  // rows whose overlap bound is below the threshold hold no valid displacement and were
+  // not produced by the inverse passes; without a map to write, skip groups of such rows
+  const uint8_t* rowfl = flags + slot * flag_sstride + Wz + (long long)zc * Wy;
+  if (!WRITE_MAP) {
+    bool any = false;
+    for (int rr = 0; rr < NR; ++rr) any |= (yc0 + rr < Wy) && rowfl[yc0 + rr];
+    if (!any) return;
+  }
   load_twiddles(tw, twtab, pl);
   const float2* rows = Y4 + slot * y4_sstride + ((long long)zc * Wy) * Hp;
   const int half = Px / 2;
@@ -483,8 +530,8 @@ __global__ __launch_bounds__(kThreads) void k_final_x(
   auto pack = [&](int k, int p) -> float2 {
     const int r0 = yc0 + 2 * p, r1 = r0 + 1;
     const int kk = k <= half ? k : Px - k;
-    const float2 a = (r0 < Wy) ? rows[(long long)r0 * Hp + kk] : make_float2(0.f, 0.f);
-    const float2 c = (r1 < Wy) ? rows[(long long)r1 * Hp + kk] : make_float2(0.f, 0.f);
+    const float2 a = (r0 < Wy && rowfl[r0]) ? rows[(long long)r0 * Hp + kk] : make_float2(0.f, 0.f);
+    const float2 c = (r1 < Wy && rowfl[r1]) ? rows[(long long)r1 * Hp + kk] : make_float2(0.f, 0.f);
     if (k == 0 || k == half) return make_float2(a.x, c.x);
     if (k < half) return make_float2(a.x - c.y, a.y + c.x);  // S1 + i S2
     return make_float2(a.x + c.y, c.x - a.y);                // conj(S1) + i conj(S2)

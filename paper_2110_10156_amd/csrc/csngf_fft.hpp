@@ -301,44 +301,70 @@ __device__ void fft_lds(float2* __restrict__ buf, const float2* __restrict__ tw,
 // stage writes buf in natural order instead.  buf must not be in use by other threads on
 // entry (caller synchronises).  On return the group is NOT synchronised after the last
 // stage; callers reusing buf (or reading it with OUT_LDS) must __syncthreads() first.
+// The thread index behind an empty asm: index arithmetic derived from it cannot be hoisted
+// out of callers' loops (which would keep dozens of addresses live across them).
+__device__ __forceinline__ int opaque_tid() {
+  int t = (int)threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
 template <int L, int R, int NS, int W, int WS, int T, bool INV, bool FROM_LD, bool TO_ST, typename LD, typename ST>
 __device__ __forceinline__ void fft_stage_io(float2* __restrict__ buf, const float2* __restrict__ tw, LD& ld, ST& st) {
+  const int tx = opaque_tid();
   constexpr int LR = L / R;
   constexpr int NBF = LR * W;
   constexpr int NB = (NBF + T - 1) / T;
   constexpr int TWSTEP = L / (NS * R);
-  float2 v[NB][R];
+  auto finish = [&](float2* v, int p, int j, int u) {
+    const int k = j % NS, q = j / NS;
+    if constexpr (NS > 1) {
 #pragma unroll
-  for (int u = 0; u < NB; ++u) {
-    const int bf = (int)threadIdx.x + u * T;
-    if (NBF % T == 0 || bf < NBF) {
-      const int p = bf % W, j = bf / W;
-#pragma unroll
-      for (int t = 0; t < R; ++t) v[u][t] = FROM_LD ? ld(j + t * LR, p) : buf[(j + t * LR) * WS + p];
+      for (int t = 1; t < R; ++t) {
+        float2 w = tw[t * k * TWSTEP];
+        if (INV) w.y = -w.y;
+        v[t] = cmul(v[t], w);
+      }
     }
-  }
-  if constexpr (!FROM_LD && !TO_ST) __syncthreads();
+    dft<R, INV>(v);
+    const int base = q * NS * R + k;
 #pragma unroll
-  for (int u = 0; u < NB; ++u) {
-    const int bf = (int)threadIdx.x + u * T;
-    if (NBF % T == 0 || bf < NBF) {
-      const int p = bf % W, j = bf / W;
-      const int k = j % NS, q = j / NS;
-      if constexpr (NS > 1) {
+    for (int t = 0; t < R; ++t) {
+      if constexpr (TO_ST) st(base + t * NS, p, v[t], u * R + t);
+      else buf[(base + t * NS) * WS + p] = v[t];
+    }
+  };
+  if constexpr (FROM_LD || TO_ST) {
+    // not in place (inputs come from the producer, or outputs go to the consumer): one
+    // butterfly at a time keeps only R values live
 #pragma unroll
-        for (int t = 1; t < R; ++t) {
-          float2 w = tw[t * k * TWSTEP];
-          if (INV) w.y = -w.y;
-          v[u][t] = cmul(v[u][t], w);
-        }
+    for (int u = 0; u < NB; ++u) {
+      const int bf = tx + u * T;
+      if (NBF % T == 0 || bf < NBF) {
+        const int p = bf % W, j = bf / W;
+        float2 v[R];
+#pragma unroll
+        for (int t = 0; t < R; ++t) v[t] = FROM_LD ? ld(j + t * LR, p) : buf[(j + t * LR) * WS + p];
+        finish(v, p, j, u);
       }
-      dft<R, INV>(v[u]);
-      const int base = q * NS * R + k;
+    }
+  } else {
+    // in place: every butterfly of the group is read before any is written
+    float2 v[NB][R];
 #pragma unroll
-      for (int t = 0; t < R; ++t) {
-        if constexpr (TO_ST) st(base + t * NS, p, v[u][t], u * R + t);
-        else buf[(base + t * NS) * WS + p] = v[u][t];
+    for (int u = 0; u < NB; ++u) {
+      const int bf = tx + u * T;
+      if (NBF % T == 0 || bf < NBF) {
+        const int p = bf % W, j = bf / W;
+#pragma unroll
+        for (int t = 0; t < R; ++t) v[u][t] = buf[(j + t * LR) * WS + p];
       }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int bf = tx + u * T;
+      if (NBF % T == 0 || bf < NBF) finish(v[u], bf % W, bf / W, u);
     }
   }
   if constexpr (!TO_ST) __syncthreads();

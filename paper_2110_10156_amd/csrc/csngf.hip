@@ -91,8 +91,11 @@ size_t a16(size_t b) { return (b + 15) & ~size_t(15); }
 
 size_t lds_fields(int Px, int nx) {
   return a16(sizeof(float2) * Px) + a16(sizeof(float2) * Px * (kRowsX + 1)) + a16(sizeof(float) * 3 * (kRowsX + 2) * nx) +
-         a16((size_t)3 * (kRowsX + 2) * nx);
+         a16(sizeof(float) * 3 * kRowsX * nx) + a16((size_t)3 * (kRowsX + 2) * nx);
 }
+
+// slices per field-stage workgroup (z march); each new slice costs one resampled halo plane
+constexpr int kSlicesX = 8;
 size_t lds_pencil(int L) { return a16(sizeof(float2) * L) + a16(sizeof(float2) * L * kTileW); }
 size_t lds_final(int Px, int nxB) {
   return a16(sizeof(float2) * Px) + a16(sizeof(float2) * Px * (kRowsX + 1)) + a16(sizeof(int) * 2 * kRowsX * (nxB + 1));
@@ -316,7 +319,8 @@ int launch_pencil(csngf_ctx* c, bool inv, const float2* in, float2* out, int n_i
 
 int launch_fields(csngf_ctx* c, bool moving, const float* vol, const uint8_t* um, const int* n3, const int* rotq,
                   float2* out, long long out_slot, uint8_t* mask_out, long long mask_slot, float* dbg, int slots) {
-  const dim3 grid((n3[1] + kRowsX - 1) / kRowsX, n3[2], slots);
+  const int tz = kSlicesX;
+  const dim3 grid((n3[1] + kRowsX - 1) / kRowsX, (n3[2] + tz - 1) / tz, slots);
   const size_t lds = lds_fields(c->plx.L, n3[0]);
   if (lds > kLdsMax) return fail(CSNGF_E_UNSUPPORTED, "x extent too large for the field stage");
   hipError_t ae = hipSuccess;
@@ -327,12 +331,12 @@ int launch_fields(csngf_ctx* c, bool moving, const float* vol, const uint8_t* um
       ae = allow_lds(k_fields_x<true, LC>, lds);
       if (ae == hipSuccess)
         hipLaunchKernelGGL((k_fields_x<true, LC>), grid, dim3(kThreads), lds, c->stream, vol, um, n3[0], n3[1], n3[2],
-                           rotq, c->eps, c->plx, c->d_tw, out, c->H, c->Hp, out_slot, mask_out, mask_slot, dbg);
+                           tz, rotq, c->eps, c->plx, c->d_tw, out, c->H, c->Hp, out_slot, mask_out, mask_slot, dbg);
     } else {
       ae = allow_lds(k_fields_x<false, LC>, lds);
       if (ae == hipSuccess)
         hipLaunchKernelGGL((k_fields_x<false, LC>), grid, dim3(kThreads), lds, c->stream, vol, um, n3[0], n3[1], n3[2],
-                           rotq, c->eps, c->plx, c->d_tw, out, c->H, c->Hp, out_slot, mask_out, mask_slot, dbg);
+                           tz, rotq, c->eps, c->plx, c->d_tw, out, c->H, c->Hp, out_slot, mask_out, mask_slot, dbg);
     }
   });
   prof_end(c, KT_FIELDS, ev);

@@ -76,17 +76,18 @@ __device__ __forceinline__ bool resample_q16(const float* __restrict__ B, const 
 __device__ __forceinline__ size_t align16(size_t b) { return (b + 15) & ~size_t(15); }
 
 // ------------------------------------------------------------------------------ x pass
-// One workgroup: slice z, rows y0 .. y0+kRowsX-1 of one rotation slot.  The halo (rows
-// y0-1 .. y0+kRowsX, slices z-1 .. z+1) is sampled into LDS; then for each of the 3 field
-// pairs (xx,yy), (zz,xy), (xz,yz) the first FFT stage computes mask, NGF and the pair's
-// products straight from the halo (re = first field, im = second), the transform runs
-// along x (length Px, zero padded from nx) and the result is split into two half spectra.
+// One workgroup: rows y0 .. y0+kRowsX-1 of slices z0 .. z0+tz-1 of one rotation slot,
+// marching along z with a ring of 3 resampled halo planes (rows y0-1 .. y0+kRowsX) in LDS,
+// so each new slice costs one new plane.  Per slice: mask and NGF once per voxel into LDS;
+// then for each of the 3 field pairs (xx,yy), (zz,xy), (xz,yz) the first FFT stage forms
+// the pair's products (re = first field, im = second), the transform runs along x (length
+// Px, zero padded from nx) and the result is split into two half spectra.
 template <int LC>
 constexpr int xrow_stride() { return LC > 0 ? kRowsX + 1 : kRowsX; }
 
 template <bool MOVING, int LC>
 __global__ __launch_bounds__(kThreads) void k_fields_x(
-    const float* __restrict__ vol, const uint8_t* __restrict__ umask, int nx, int ny, int nz,
+    const float* __restrict__ vol, const uint8_t* __restrict__ umask, int nx, int ny, int nz, int tz,
     const int* __restrict__ rotq, float eps, FftPlan pl, const float2* __restrict__ twtab,
     float2* __restrict__ out, int H, int Hp, long long out_slot_stride,
     uint8_t* __restrict__ mask_out, long long mask_slot_stride, float* __restrict__ dbg_prod) {
@@ -95,105 +96,133 @@ __global__ __launch_bounds__(kThreads) void k_fields_x(
   constexpr int HR = TY + 2;
   extern __shared__ __align__(16) unsigned char smem[];
   const int Px = pl.L;
+  const int plane = HR * nx;
   float2* tw = reinterpret_cast<float2*>(smem);
   float2* buf = reinterpret_cast<float2*>(smem + align16(sizeof(float2) * Px));
   float* val = reinterpret_cast<float*>(smem + align16(sizeof(float2) * Px) + align16(sizeof(float2) * Px * (TY + 1)));
-  uint8_t* ok = reinterpret_cast<uint8_t*>(reinterpret_cast<unsigned char*>(val) +
-                                           align16(sizeof(float) * 3 * HR * nx));
+  float* ng = reinterpret_cast<float*>(reinterpret_cast<unsigned char*>(val) + align16(sizeof(float) * 3 * plane));
+  uint8_t* ok = reinterpret_cast<uint8_t*>(reinterpret_cast<unsigned char*>(ng) + align16(sizeof(float) * 3 * TY * nx));
   const int y0 = blockIdx.x * TY;
-  const int z = blockIdx.y;
+  const int z0 = blockIdx.y * tz;
   const int slot = blockIdx.z;
   const int* kq = MOVING ? rotq + 9 * slot : nullptr;
   load_twiddles(tw, twtab, pl);
+  const float eps2 = eps * eps;
+  const long nv = (long)nx * ny * nz;
 
-  // 1. halo samples, HU per thread in flight
-  constexpr int HU = 4;
-  const int nhalo = 3 * HR * nx;
-  for (int base = 0; base < nhalo; base += HU * kThreads) {
-    float v[HU];
-    bool good[HU];
+  // sample halo plane zz (rows y0-1 .. y0+TY) into ring slot (zz - z0 + 1) mod 3
+  auto fill_plane = [&](int zz) {
+    const int ring = (zz - z0 + 1) % 3;
+    float* pv = val + ring * plane;
+    uint8_t* po = ok + ring * plane;
+    constexpr int HU = 4;
+    for (int base = 0; base < plane; base += HU * kThreads) {
+      float v[HU];
+      bool good[HU];
 #pragma unroll
-    for (int u = 0; u < HU; ++u) {
-      const int e = base + u * kThreads + (int)threadIdx.x;
-      v[u] = 0.f;
-      good[u] = false;
-      if (e < nhalo) {
-        const int x = e % nx;
-        const int r = (e / nx) % HR;
-        const int pzl = e / (nx * HR);
-        const int yy = y0 + r - 1, zz = z + pzl - 1;
-        if (yy >= 0 && yy < ny && zz >= 0 && zz < nz) {
-          if (MOVING) {
-            good[u] = resample_q16(vol, umask, nx, ny, nz, kq, x, yy, zz, v[u]);
-          } else {
-            const long o = ((long)zz * ny + yy) * nx + x;
-            v[u] = vol[o];
-            good[u] = umask ? (umask[o] != 0) : true;
+      for (int u = 0; u < HU; ++u) {
+        const int e = base + u * kThreads + (int)threadIdx.x;
+        v[u] = 0.f;
+        good[u] = false;
+        if (e < plane) {
+          const int x = e % nx, r = e / nx;
+          const int yy = y0 + r - 1;
+          if (yy >= 0 && yy < ny && zz >= 0 && zz < nz) {
+            if (MOVING) {
+              good[u] = resample_q16(vol, umask, nx, ny, nz, kq, x, yy, zz, v[u]);
+            } else {
+              const long o = ((long)zz * ny + yy) * nx + x;
+              v[u] = vol[o];
+              good[u] = umask ? (umask[o] != 0) : true;
+            }
           }
         }
       }
-    }
 #pragma unroll
-    for (int u = 0; u < HU; ++u) {
-      const int e = base + u * kThreads + (int)threadIdx.x;
-      if (e < nhalo) {
-        val[e] = v[u];
-        ok[e] = good[u] ? 1 : 0;
+      for (int u = 0; u < HU; ++u) {
+        const int e = base + u * kThreads + (int)threadIdx.x;
+        if (e < plane) {
+          pv[e] = v[u];
+          po[e] = good[u] ? 1 : 0;
+        }
       }
     }
-  }
-  __syncthreads();
+  };
 
-  const float eps2 = eps * eps;
-  const long nv = (long)nx * ny * nz;
+  fill_plane(z0 - 1);
+  fill_plane(z0);
 #pragma unroll 1
-  for (int pair = 0; pair < 3; ++pair) {
-    auto products = [&](int x, int r) -> float2 {
-      if (x >= nx) return make_float2(0.f, 0.f);
-      const int c = (1 * HR + r + 1) * nx + x;
-      const bool m = x >= 1 && x <= nx - 2 && ok[c] && ok[c - 1] && ok[c + 1] && ok[c - nx] && ok[c + nx] &&
-                     ok[c - HR * nx] && ok[c + HR * nx];
-      float n0 = 0.f, n1 = 0.f, n2 = 0.f;
-      if (m) {
-        const float gx = 0.5f * (val[c + 1] - val[c - 1]);
-        const float gy = 0.5f * (val[c + nx] - val[c - nx]);
-        const float gz = 0.5f * (val[c + HR * nx] - val[c - HR * nx]);
-        const float inv = 1.0f / sqrtf(gx * gx + gy * gy + gz * gz + eps2);
-        n0 = gx * inv;
-        n1 = gy * inv;
-        n2 = gz * inv;
+  for (int zi = 0; zi < tz; ++zi) {
+    const int z = z0 + zi;
+    if (z >= nz) break;
+    fill_plane(z + 1);
+    __syncthreads();
+    // mask and NGF of slice z (n = 0 where the eroded mask is 0)
+    {
+      const float* vm = val + ((zi + 0) % 3) * plane;  // slice z - 1
+      const float* vc = val + ((zi + 1) % 3) * plane;  // slice z
+      const float* vp = val + ((zi + 2) % 3) * plane;  // slice z + 1
+      const uint8_t* om = ok + ((zi + 0) % 3) * plane;
+      const uint8_t* oc = ok + ((zi + 1) % 3) * plane;
+      const uint8_t* op = ok + ((zi + 2) % 3) * plane;
+      for (int e = threadIdx.x; e < TY * nx; e += kThreads) {
+        const int x = e % nx, r = e / nx;
+        const int c = (r + 1) * nx + x;
+        const bool m = x >= 1 && x <= nx - 2 && oc[c] && oc[c - 1] && oc[c + 1] && oc[c - nx] && oc[c + nx] &&
+                       om[c] && op[c];
+        float n0 = 0.f, n1 = 0.f, n2 = 0.f;
+        if (m) {
+          const float gx = 0.5f * (vc[c + 1] - vc[c - 1]);
+          const float gy = 0.5f * (vc[c + nx] - vc[c - nx]);
+          const float gz = 0.5f * (vp[c] - vm[c]);
+          const float inv = 1.0f / sqrtf(gx * gx + gy * gy + gz * gz + eps2);
+          n0 = gx * inv;
+          n1 = gy * inv;
+          n2 = gz * inv;
+        }
+        ng[e] = n0;
+        ng[TY * nx + e] = n1;
+        ng[2 * TY * nx + e] = n2;
+        const int yy = y0 + r;
+        if (yy < ny && mask_out) mask_out[slot * mask_slot_stride + ((long)z * ny + yy) * nx + x] = m ? 1 : 0;
       }
-      float fa, fb;
-      if (pair == 0) { fa = n0 * n0; fb = n1 * n1; }
-      else if (pair == 1) { fa = n2 * n2; fb = n0 * n1; }
-      else { fa = n0 * n2; fb = n1 * n2; }
-      const int yy = y0 + r;
-      if (yy < ny) {
-        const long vox = ((long)z * ny + yy) * nx + x;
-        if (pair == 0 && mask_out) mask_out[slot * mask_slot_stride + vox] = m ? 1 : 0;
-        if (dbg_prod && slot == 0) {
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int pair = 0; pair < 3; ++pair) {
+      auto products = [&](int x, int r) -> float2 {
+        if (x >= nx) return make_float2(0.f, 0.f);
+        const int e = r * nx + x;
+        const float n0 = ng[e], n1 = ng[TY * nx + e], n2 = ng[2 * TY * nx + e];
+        float fa, fb;
+        if (pair == 0) { fa = n0 * n0; fb = n1 * n1; }
+        else if (pair == 1) { fa = n2 * n2; fb = n0 * n1; }
+        else { fa = n0 * n2; fb = n1 * n2; }
+        const int yy = y0 + r;
+        if (dbg_prod && slot == 0 && yy < ny) {
+          const long vox = ((long)z * ny + yy) * nx + x;
           dbg_prod[(2 * pair) * nv + vox] = fa;
           dbg_prod[(2 * pair + 1) * nv + vox] = fb;
         }
+        return make_float2(fa, fb);
+      };
+      auto none = [](int, int, float2, int) {};
+      fft_io<LC, TY, kThreads, false, false, true, WS>(buf, tw, pl, products, none);
+      __syncthreads();
+      // split the packed transform: Fa = (Z_k + conj Z_{P-k}) / 2, Fb = -i (Z_k - conj Z_{P-k}) / 2
+      for (int e = threadIdx.x; e < TY * H; e += kThreads) {
+        const int r = e / H, k = e % H;
+        const int yy = y0 + r;
+        if (yy >= ny) continue;
+        const float2 zk = buf[k * WS + r];
+        const float2 zc = buf[((Px - k) % Px) * WS + r];
+        float2* oa = out + slot * out_slot_stride + (((long)(2 * pair) * nz + z) * ny + yy) * Hp;
+        float2* ob = out + slot * out_slot_stride + (((long)(2 * pair + 1) * nz + z) * ny + yy) * Hp;
+        oa[k] = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y - zc.y));
+        ob[k] = make_float2(0.5f * (zk.y + zc.y), 0.5f * (zc.x - zk.x));
       }
-      return make_float2(fa, fb);
-    };
-    auto none = [](int, int, float2, int) {};
-    fft_io<LC, TY, kThreads, false, false, true, WS>(buf, tw, pl, products, none);
-    __syncthreads();
-    // split the packed transform: Fa = (Z_k + conj Z_{P-k}) / 2, Fb = -i (Z_k - conj Z_{P-k}) / 2
-    for (int e = threadIdx.x; e < TY * H; e += kThreads) {
-      const int r = e / H, k = e % H;
-      const int yy = y0 + r;
-      if (yy >= ny) continue;
-      const float2 zk = buf[k * WS + r];
-      const float2 zc = buf[((Px - k) % Px) * WS + r];
-      float2* oa = out + slot * out_slot_stride + (((long)(2 * pair) * nz + z) * ny + yy) * Hp;
-      float2* ob = out + slot * out_slot_stride + (((long)(2 * pair + 1) * nz + z) * ny + yy) * Hp;
-      oa[k] = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y - zc.y));
-      ob[k] = make_float2(0.5f * (zk.y + zc.y), 0.5f * (zc.x - zk.x));
+      __syncthreads();
     }
-    __syncthreads();
   }
 }
 

@@ -320,7 +320,8 @@ int launch_pencil(csngf_ctx* c, bool inv, const float2* in, float2* out, int n_i
 int launch_fields(csngf_ctx* c, bool moving, const float* vol, const uint8_t* um, const int* n3, const int* rotq,
                   float2* out, long long out_slot, uint8_t* mask_out, long long mask_slot, float* dbg, int slots) {
   const int tz = kSlicesX;
-  const dim3 grid((n3[1] + kRowsX - 1) / kRowsX, (n3[2] + tz - 1) / tz, slots);
+  const int nreal = (n3[1] + kRowsX - 1) / kRowsX * ((n3[2] + tz - 1) / tz) * slots;
+  const dim3 grid((nreal + 7) / 8 * 8);
   const size_t lds = lds_fields(c->plx.L, n3[0]);
   if (lds > kLdsMax) return fail(CSNGF_E_UNSUPPORTED, "x extent too large for the field stage");
   hipError_t ae = hipSuccess;
@@ -331,12 +332,12 @@ int launch_fields(csngf_ctx* c, bool moving, const float* vol, const uint8_t* um
       ae = allow_lds(k_fields_x<true, LC>, lds);
       if (ae == hipSuccess)
         hipLaunchKernelGGL((k_fields_x<true, LC>), grid, dim3(kThreads), lds, c->stream, vol, um, n3[0], n3[1], n3[2],
-                           tz, rotq, c->eps, c->plx, c->d_tw, out, c->H, c->Hp, out_slot, mask_out, mask_slot, dbg);
+                           tz, slots, rotq, c->eps, c->plx, c->d_tw, out, c->H, c->Hp, out_slot, mask_out, mask_slot, dbg);
     } else {
       ae = allow_lds(k_fields_x<false, LC>, lds);
       if (ae == hipSuccess)
         hipLaunchKernelGGL((k_fields_x<false, LC>), grid, dim3(kThreads), lds, c->stream, vol, um, n3[0], n3[1], n3[2],
-                           tz, rotq, c->eps, c->plx, c->d_tw, out, c->H, c->Hp, out_slot, mask_out, mask_slot, dbg);
+                           tz, slots, rotq, c->eps, c->plx, c->d_tw, out, c->H, c->Hp, out_slot, mask_out, mask_slot, dbg);
     }
   });
   prof_end(c, KT_FIELDS, ev);

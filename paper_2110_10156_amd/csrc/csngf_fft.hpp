@@ -309,7 +309,7 @@ __device__ __forceinline__ int opaque_tid() {
   return t;
 }
 
-template <int L, int R, int NS, int W, int WS, int T, bool INV, bool FROM_LD, bool TO_ST, typename LD, typename ST>
+template <int L, int R, int NS, int W, int WS, int WSO, int T, bool INV, bool FROM_LD, bool TO_ST, typename LD, typename ST>
 __device__ __forceinline__ void fft_stage_io(float2* __restrict__ buf, const float2* __restrict__ tw, LD& ld, ST& st) {
   const int tx = opaque_tid();
   constexpr int LR = L / R;
@@ -331,7 +331,7 @@ __device__ __forceinline__ void fft_stage_io(float2* __restrict__ buf, const flo
 #pragma unroll
     for (int t = 0; t < R; ++t) {
       if constexpr (TO_ST) st(base + t * NS, p, v[t], u * R + t);
-      else buf[(base + t * NS) * WS + p] = v[t];
+      else buf[(base + t * NS) * WSO + p] = v[t];
     }
   };
   if constexpr (FROM_LD || TO_ST) {
@@ -370,13 +370,15 @@ __device__ __forceinline__ void fft_stage_io(float2* __restrict__ buf, const flo
   if constexpr (!TO_ST) __syncthreads();
 }
 
-template <int L, int S, int W, int WS, int T, bool INV, bool IN_LDS, bool OUT_LDS, typename LD, typename ST>
+template <int L, int S, int W, int WS, int WSO, int T, bool INV, bool IN_LDS, bool OUT_LDS, typename LD, typename ST>
 __device__ __forceinline__ void fft_io_stages(float2* __restrict__ buf, const float2* __restrict__ tw, LD& ld, ST& st) {
   constexpr CPlan P = make_cplan(L);
   if constexpr (S < P.nst) {
     constexpr bool first = (S == 0), last = (S + 1 == P.nst);
-    fft_stage_io<L, P.r[S], P.ns[S], W, WS, T, INV, first && !IN_LDS, last && !OUT_LDS>(buf, tw, ld, st);
-    fft_io_stages<L, S + 1, W, WS, T, INV, IN_LDS, OUT_LDS>(buf, tw, ld, st);
+    // the last stage writes its LDS output with row stride WSO, every other write uses WS
+    fft_stage_io<L, P.r[S], P.ns[S], W, WS, (last ? WSO : WS), T, INV, first && !IN_LDS, last && !OUT_LDS>(buf, tw,
+                                                                                                           ld, st);
+    fft_io_stages<L, S + 1, W, WS, WSO, T, INV, IN_LDS, OUT_LDS>(buf, tw, ld, st);
   }
 }
 
@@ -418,12 +420,13 @@ constexpr int consumer_slots() {
 
 // LC > 0: compile-time plan with fused I/O.  LC == 0: run-time plan: the producer fills buf,
 // the LDS transform runs, and the consumer reads buf (slot = position in the thread's loop).
-template <int LC, int W, int T, bool INV, bool IN_LDS, bool OUT_LDS, int WS = W, typename LD, typename ST>
+// WSO: row stride of the final LDS result (OUT_LDS), e.g. padded for a transposing reader.
+template <int LC, int W, int T, bool INV, bool IN_LDS, bool OUT_LDS, int WSO = W, typename LD, typename ST>
 __device__ __forceinline__ void fft_io(float2* __restrict__ buf, const float2* __restrict__ tw, const FftPlan& pl,
                                        LD&& ld, ST&& st) {
-  static_assert(LC > 0 || WS == W, "padded rows need a compile-time plan");
+  static_assert(LC > 0 || WSO == W, "a padded result needs a compile-time plan");
   if constexpr (LC > 0) {
-    fft_io_stages<LC, 0, W, WS, T, INV, IN_LDS, OUT_LDS>(buf, tw, ld, st);
+    fft_io_stages<LC, 0, W, W, WSO, T, INV, IN_LDS, OUT_LDS>(buf, tw, ld, st);
   } else {
     const int L = pl.L;
     if constexpr (!IN_LDS) {

@@ -87,7 +87,7 @@ constexpr int xrow_stride() { return LC > 0 ? kRowsX + 1 : kRowsX; }
 
 template <bool MOVING, int LC>
 __global__ __launch_bounds__(kThreads) void k_fields_x(
-    const float* __restrict__ vol, const uint8_t* __restrict__ umask, int nx, int ny, int nz, int tz,
+    const float* __restrict__ vol, const uint8_t* __restrict__ umask, int nx, int ny, int nz, int tz, int nslots,
     const int* __restrict__ rotq, float eps, FftPlan pl, const float2* __restrict__ twtab,
     float2* __restrict__ out, int H, int Hp, long long out_slot_stride,
     uint8_t* __restrict__ mask_out, long long mask_slot_stride, float* __restrict__ dbg_prod) {
@@ -102,9 +102,16 @@ __global__ __launch_bounds__(kThreads) void k_fields_x(
   float* val = reinterpret_cast<float*>(smem + align16(sizeof(float2) * Px) + align16(sizeof(float2) * Px * (TY + 1)));
   float* ng = reinterpret_cast<float*>(reinterpret_cast<unsigned char*>(val) + align16(sizeof(float) * 3 * plane));
   uint8_t* ok = reinterpret_cast<uint8_t*>(reinterpret_cast<unsigned char*>(ng) + align16(sizeof(float) * 3 * TY * nx));
-  const int y0 = blockIdx.x * TY;
-  const int z0 = blockIdx.y * tz;
-  const int slot = blockIdx.z;
+  // XCD-aware order (hardware deals block b to XCD b % 8): each XCD walks a contiguous run
+  // of (y tile, z chunk, slot) with the y tile fastest, so neighbouring tiles' source
+  // footprints in B meet in the same L2.
+  const int nyt = (ny + TY - 1) / TY, nzc = (nz + tz - 1) / tz;
+  const int nb8 = gridDim.x;
+  const int logical = ((int)blockIdx.x % 8) * (nb8 / 8) + (int)blockIdx.x / 8;
+  if (logical >= nyt * nzc * nslots) return;
+  const int y0 = (logical % nyt) * TY;
+  const int z0 = ((logical / nyt) % nzc) * tz;
+  const int slot = logical / (nyt * nzc);
   const int* kq = MOVING ? rotq + 9 * slot : nullptr;
   load_twiddles(tw, twtab, pl);
   const float eps2 = eps * eps;
@@ -591,7 +598,7 @@ __global__ __launch_bounds__(kThreads) void k_final_x(
       }
     }
   };
-  fft_io<LC, WP, kThreads, true, false, false, (LC > 0 ? WP + 1 : WP)>(buf, tw, pl, pack, emit);
+  fft_io<LC, WP, kThreads, true, false, false>(buf, tw, pl, pack, emit);
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) {
     const unsigned long long o = __shfl_xor(best, d, 64);

@@ -101,6 +101,8 @@ def main():
     ap.add_argument("--cpu-rotations", type=int, default=2, help="oracle sample size (0 = skip)")
     ap.add_argument("--plain-rotations", type=int, default=64,
                     help="rotations timed on the one-rotation-per-launch path (0 = skip)")
+    ap.add_argument("--usngf-rotations", type=int, default=200,
+                    help="rotations timed with the unsquared measure, Eq. (3) (0 = skip)")
     ap.add_argument("--no-profile", action="store_true", help="do not record per-kernel events")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
@@ -194,6 +196,18 @@ def main():
             plain = len(pr) / (time.perf_counter() - ts)
         print(f"[bench] plain path {plain:.1f} rot/s", file=sys.stderr, flush=True)
 
+    usngf = None
+    if args.usngf_rotations > 0:
+        with bd.Context(A, pair.dims_b, pad=pair.pad, batch=args.batch, measure="unsquared") as uctx:
+            ur = rots[:args.usngf_rotations]
+            uctx.evaluate(B, ur[:16])
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            uctx.evaluate(B, ur)
+            torch.cuda.synchronize()
+            usngf = len(ur) / (time.perf_counter() - ts)
+        print(f"[bench] unsquared measure {usngf:.1f} rot/s", file=sys.stderr, flush=True)
+
     cpu = None
     if args.cpu_rotations > 0:
         cpu = cpu_baseline(pair, args.cpu_rotations)
@@ -221,6 +235,7 @@ def main():
                        "p99": round(float(np.percentile(lat_ms, 99)), 3),
                        "what": f"one csngf_evaluate call of {len(rots)} rotations, host to host"},
         "plain_rotations_per_s": None if plain is None else round(plain, 2),
+        "usngf_rotations_per_s": None if usngf is None else round(usngf, 2),
         "path_bytes_per_rotation": yard,
         "path_hbm_frac": round(yard * value / (HBM_PEAK_GBS * 1e9), 4),
         "best": {"rot_index": best.rot_index, "shift": list(best.shift), "score": best.score},

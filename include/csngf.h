@@ -56,6 +56,11 @@ extern "C" {
  * stream has passed it.  Without the flag they are host pointers and calls are
  * synchronous.  Rotation matrices and result structs are always host memory. */
 #define CSNGF_DEVICE_PTRS 1u
+/* params.flags: score with the unsquared similarity <n_A, n_B> (Eq. (3); the USNGF variant of
+ * Sec. 5.1) instead of the squared one of Eq. (2).  Its separable parts are the 3 NGF
+ * components (weight 1) instead of the 6 products of Eq. (6); scores lie in [-1, 1] and
+ * change sign with the gradient sign of either volume. */
+#define CSNGF_UNSQUARED 2u
 
 typedef struct csngf_ctx csngf_ctx;
 
@@ -69,7 +74,7 @@ typedef struct {
   float gamma;          /* minimum overlap fraction in [0, 1], Sec. 3.2; default 0.5 */
   int32_t pad[3];       /* FFT size (Px, Py, Pz); 0 = smallest supported >= n_A + n_B - 1 */
   int32_t batch;        /* rotations in flight per launch sequence; 0 = automatic */
-  uint32_t flags;       /* CSNGF_DEVICE_PTRS */
+  uint32_t flags;       /* CSNGF_DEVICE_PTRS | CSNGF_UNSQUARED */
 } csngf_params;
 
 typedef struct {

@@ -31,7 +31,8 @@ int csngf_debug_fft(const void* in, void* out, int32_t L, int32_t batch, int32_t
  * R9 != NULL: moving side, vol resampled under R9 (quantised as in csngf_evaluate).
  * R9 == NULL: fixed side, vol used directly (vmask optional).  Px: the x FFT size
  * (0 = smallest supported >= 2 nx - 1).  flags: CSNGF_DEVICE_PTRS for device pointers
- * (vol, vmask, prod6, mask); host otherwise (then synchronous). */
+ * (vol, vmask, prod6, mask); host otherwise (then synchronous).  With CSNGF_UNSQUARED only
+ * the first 3 planes of prod6 are written: M n_x, M n_y, M n_z. */
 int csngf_debug_fields(const float* vol, const uint8_t* vmask, csngf_dims d, const double* R9,
                        float eps, int32_t Px, float* prod6, uint8_t* mask, uint32_t flags);
 

@@ -14,6 +14,8 @@ What it computes, in the paper's order (Ofverstedt, Lindblad, Sladoje, "Cross-Si
   with N(chi) the number of overlapping mask voxels (the mask cross-correlation).
 * Sec. 3.1, Eq. (6)-(8): the same sums through 6 separable products and frequency-domain
   cross-correlation (summed before one inverse transform).
+* Sec. 2, Eq. (3) and Sec. 5.1 (USNGF): the unsquared variant s = <n_A, n_B>, whose three
+  separable parts are the per-axis products (measure="unsquared").
 * Sec. 3.2: B resampled under a candidate rotation by trilinear interpolation (inverse
   mapping), its NGF taken after resampling; only displacements meeting a minimum overlap
   gamma (0.5) count; zero padding makes the correlation linear; the best displacement per
@@ -179,10 +181,11 @@ def _overlap_slices(shape_a, shape_b, chi_xyz):
     return tuple(sa), tuple(sb)
 
 
-def similarity_at(fa: Fields, fb: Fields, chi_xyz):
+def similarity_at(fa: Fields, fb: Fields, chi_xyz, measure: str = "squared"):
     """Eq. (5) at a single displacement by direct summation: returns (S, N).
 
-    S = sum_x M_A(x) M_B(x + chi) <n_A(x), n_B(x + chi)>^2 and N = sum_x M_A(x) M_B(x + chi).
+    S = sum_x M_A(x) M_B(x + chi) s(x) with s = <n_A(x), n_B(x + chi)>^2 (Eq. (2)) or, for
+    measure="unsquared", s = <n_A(x), n_B(x + chi)> (Eq. (3)); N = sum_x M_A(x) M_B(x + chi).
     """
     sl = _overlap_slices(fa.mask.shape, fb.mask.shape, chi_xyz)
     if sl is None:
@@ -192,10 +195,11 @@ def similarity_at(fa: Fields, fb: Fields, chi_xyz):
     dot = np.zeros(m.shape, dtype=np.float64)
     for k in range(3):
         dot += fa.n[k][sa] * fb.n[k][sb]
-    return float(np.sum(np.where(m, dot * dot, 0.0))), int(np.count_nonzero(m))
+    s = dot if measure == "unsquared" else dot * dot
+    return float(np.sum(np.where(m, s, 0.0))), int(np.count_nonzero(m))
 
 
-def correlation_maps_direct(fa: Fields, fb: Fields):
+def correlation_maps_direct(fa: Fields, fb: Fields, measure: str = "squared"):
     """Eq. (5) numerators and overlaps for every chi by direct summation (small volumes)."""
     nza, nya, nxa = fa.mask.shape
     nzb, nyb, nxb = fb.mask.shape
@@ -206,13 +210,25 @@ def correlation_maps_direct(fa: Fields, fb: Fields):
         for iy in range(W[1]):
             for ix in range(W[2]):
                 chi = (ix - (nxa - 1), iy - (nya - 1), iz - (nza - 1))
-                S[iz, iy, ix], N[iz, iy, ix] = similarity_at(fa, fb, chi)
+                S[iz, iy, ix], N[iz, iy, ix] = similarity_at(fa, fb, chi, measure)
     return S, N
 
 
 # ----------------------------------------------------------------------------- Eq. (6)-(8)
 _PAIRS = ((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))
 _WEIGHTS = (1.0, 1.0, 1.0, 2.0, 2.0, 2.0)
+
+
+def _separable_parts(fa: Fields, fb: Fields, measure: str):
+    """(weight, A-side field, B-side field) of the separable expansion: the 6 products of
+    Eq. (6) for the squared measure, the 3 components of Eq. (3) for the unsquared one."""
+    ma = fa.mask.astype(np.float64)
+    mb = fb.mask.astype(np.float64)
+    if measure == "unsquared":
+        return [(1.0, ma * fa.n[k], mb * fb.n[k]) for k in range(3)]
+    if measure != "squared":
+        raise ValueError(f"unknown measure {measure!r}")
+    return [(w, ma * fa.n[k] * fa.n[l], mb * fb.n[k] * fb.n[l]) for (k, l), w in zip(_PAIRS, _WEIGHTS)]
 
 
 def _linear_from_circular(circ: np.ndarray, shape_a, shape_b, P_zyx):
@@ -225,13 +241,14 @@ def _linear_from_circular(circ: np.ndarray, shape_a, shape_b, P_zyx):
     return circ[np.ix_(*idx)]
 
 
-def correlation_maps_fft(fa: Fields, fb: Fields, P_xyz=None):
+def correlation_maps_fft(fa: Fields, fb: Fields, P_xyz=None, measure: str = "squared"):
     """S and N for every chi via zero-padded FP64 FFT cross-correlation (Eq. (6)-(8)).
 
-    S is the sum over the 6 separable products (cross products weighted 2), correlated in
-    the frequency domain and summed before one inverse transform; N is the mask
-    correlation, rounded to the nearest integer (asserting it is within 1e-6 of one).
-    ``P_xyz`` (each >= n_A + n_B - 1) defaults to the smallest size that avoids wrap-around.
+    S is the sum over the separable parts (6 products with cross products weighted 2, or
+    the 3 components for measure="unsquared"), correlated in the frequency domain and
+    summed before one inverse transform; N is the mask correlation, rounded to the nearest
+    integer (asserting it is within 1e-6 of one).  ``P_xyz`` (each >= n_A + n_B - 1)
+    defaults to the smallest size that avoids wrap-around.
     """
     sa, sb = fa.mask.shape, fb.mask.shape
     need = tuple(sa[a] + sb[a] - 1 for a in range(3))
@@ -244,9 +261,7 @@ def correlation_maps_fft(fa: Fields, fb: Fields, P_xyz=None):
     ma = fa.mask.astype(np.float64)
     mb = fb.mask.astype(np.float64)
     acc = None
-    for (k, l), w in zip(_PAIRS, _WEIGHTS):
-        a = ma * fa.n[k] * fa.n[l]
-        b = mb * fb.n[k] * fb.n[l]
+    for w, a, b in _separable_parts(fa, fb, measure):
         term = w * np.conj(sfft.rfftn(a, s=P, workers=WORKERS)) * sfft.rfftn(b, s=P, workers=WORKERS)
         acc = term if acc is None else acc + term
     S_circ = sfft.irfftn(acc, s=P, workers=WORKERS)
@@ -292,10 +307,11 @@ class RotationResult:
 
 def evaluate(A, B, rotations, mask_a=None, mask_b=None, eps: float = EPS_DEFAULT,
              gamma: float = GAMMA_DEFAULT, P_xyz=None, keep_maps: bool = False,
-             method: str = "fft"):
+             method: str = "fft", measure: str = "squared"):
     """Score every rotation over all displacements; return (per-rotation results, best index).
 
-    ``method`` is "fft" (Eq. (6)-(8)) or "direct" (Eq. (5) summed directly; small volumes).
+    ``method`` is "fft" (Eq. (6)-(8)) or "direct" (Eq. (5) summed directly; small volumes);
+    ``measure`` is "squared" (Eq. (2), CSNGF) or "unsquared" (Eq. (3), USNGF).
     The best index is None when no rotation has a valid displacement.
     """
     fa = fixed_fields(A, mask_a, eps)
@@ -308,9 +324,9 @@ def evaluate(A, B, rotations, mask_a=None, mask_b=None, eps: float = EPS_DEFAULT
         fb = moving_fields(B, Rq, mask_b, eps)
         count_b = int(np.count_nonzero(fb.mask))
         if method == "direct":
-            S, N = correlation_maps_direct(fa, fb)
+            S, N = correlation_maps_direct(fa, fb, measure)
         else:
-            S, N = correlation_maps_fft(fa, fb, P_xyz)
+            S, N = correlation_maps_fft(fa, fb, P_xyz, measure)
         C, _ = normalise(S, N, count_a, count_b, gamma)
         am = argmax_map(C)
         if am is None:

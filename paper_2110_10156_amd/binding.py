@@ -22,6 +22,7 @@ E_OUT_OF_MEMORY = -4
 E_DEVICE = -5
 E_NO_VALID_SHIFT = -6
 DEVICE_PTRS = 1
+UNSQUARED = 2
 
 _NAMES = {0: "OK", -1: "E_INVALID_ARG", -2: "E_UNSUPPORTED", -3: "E_NO_DEVICE", -4: "E_OUT_OF_MEMORY",
           -5: "E_DEVICE", -6: "E_NO_VALID_SHIFT"}
@@ -138,7 +139,11 @@ def supported_length(L: int) -> bool:
 class Context:
     """Owns a csngf_ctx: A's resident spectra and the rotation workspaces."""
 
-    def __init__(self, A, dims_b, *, mask_a=None, eps=1e-5, gamma=0.5, pad=(0, 0, 0), batch=0, stream=None):
+    def __init__(self, A, dims_b, *, mask_a=None, eps=1e-5, gamma=0.5, pad=(0, 0, 0), batch=0, stream=None,
+                 measure="squared"):
+        """measure: "squared" (Eq. (2), CSNGF) or "unsquared" (Eq. (3), USNGF)."""
+        if measure not in ("squared", "unsquared"):
+            raise ValueError(f"unknown measure {measure!r}")
         self.device = _is_device(A)
         if not self.device:
             A = np.ascontiguousarray(A, dtype=np.float32)
@@ -147,7 +152,7 @@ class Context:
         p.gamma = gamma
         p.pad[:] = list(pad)
         p.batch = batch
-        p.flags = DEVICE_PTRS if self.device else 0
+        p.flags = (DEVICE_PTRS if self.device else 0) | (UNSQUARED if measure == "unsquared" else 0)
         h = C.c_void_p()
         if isinstance(dims_b, tuple):
             dims_b = Dims(*dims_b)
@@ -241,15 +246,17 @@ def debug_fft(x_dev, inverse=False, out=None, stream=None):
     return out
 
 
-def debug_fields(vol, R=None, mask=None, eps=1e-5, Px=0):
-    """Products (6, nz, ny, nx) float32 and eroded mask (nz, ny, nx) uint8 of the field stage."""
+def debug_fields(vol, R=None, mask=None, eps=1e-5, Px=0, unsquared=False):
+    """Separable fields (6 products, or the 3 NGF components with unsquared=True) as
+    float32 (k, nz, ny, nx) and the eroded mask (nz, ny, nx) uint8 of the field stage."""
     vol = np.ascontiguousarray(vol, dtype=np.float32)
-    prod = np.empty((6,) + vol.shape, dtype=np.float32)
+    prod = np.empty((3 if unsquared else 6,) + vol.shape, dtype=np.float32)
     m = np.empty(vol.shape, dtype=np.uint8)
     Rp = None
     if R is not None:
         Rr = np.ascontiguousarray(np.asarray(R, dtype=np.float64).reshape(9))
         Rp = Rr.ctypes.data
     mk = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
-    _check(lib().csngf_debug_fields(_ptr(vol), _ptr(mk), dims_of(vol), Rp, eps, Px, _ptr(prod), _ptr(m), 0))
+    _check(lib().csngf_debug_fields(_ptr(vol), _ptr(mk), dims_of(vol), Rp, eps, Px, _ptr(prod), _ptr(m),
+                                    UNSQUARED if unsquared else 0))
     return prod, m

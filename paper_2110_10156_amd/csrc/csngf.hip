@@ -167,6 +167,7 @@ struct csngf_ctx {
   int H = 0, Hp = 0, tiles = 0;
   float eps = 1e-5f, gamma = 0.5f;
   uint32_t flags = 0;
+  int nf = 6;  // separable fields: 6 (squared measure) or 3 (unsquared)
   int batch = 1;
   FftPlan plx{}, ply{}, plz{};
   float2* d_tw = nullptr;
@@ -332,12 +333,12 @@ int launch_fields(csngf_ctx* c, bool moving, const float* vol, const uint8_t* um
       ae = allow_lds(k_fields_x<true, LC>, lds);
       if (ae == hipSuccess)
         hipLaunchKernelGGL((k_fields_x<true, LC>), grid, dim3(kThreads), lds, c->stream, vol, um, n3[0], n3[1], n3[2],
-                           tz, slots, rotq, c->eps, c->plx, c->d_tw, out, c->H, c->Hp, out_slot, mask_out, mask_slot, dbg);
+                           tz, slots, c->nf, rotq, c->eps, c->plx, c->d_tw, out, c->H, c->Hp, out_slot, mask_out, mask_slot, dbg);
     } else {
       ae = allow_lds(k_fields_x<false, LC>, lds);
       if (ae == hipSuccess)
         hipLaunchKernelGGL((k_fields_x<false, LC>), grid, dim3(kThreads), lds, c->stream, vol, um, n3[0], n3[1], n3[2],
-                           tz, slots, rotq, c->eps, c->plx, c->d_tw, out, c->H, c->Hp, out_slot, mask_out, mask_slot, dbg);
+                           tz, slots, c->nf, rotq, c->eps, c->plx, c->d_tw, out, c->H, c->Hp, out_slot, mask_out, mask_slot, dbg);
     }
   });
   prof_end(c, KT_FIELDS, ev);
@@ -382,7 +383,7 @@ int run_batch(csngf_ctx* c, const float* dB, const uint8_t* dmB, const int* rotq
   }
   // y forward: X1 [slot][f][z][y] -> X2 [slot][f][z][ky]
   rc = launch_pencil(c, false, c->d_buf1, c->d_buf2, c->nB[1], c->P[1], 0, c->ply, (long long)c->nB[1] * c->Hp,
-                     (long long)c->P[1] * c->Hp, 6 * c->nB[2], c->buf1_slot, c->buf2_slot, slots);
+                     (long long)c->P[1] * c->Hp, c->nf * c->nB[2], c->buf1_slot, c->buf2_slot, slots);
   if (rc) return rc;
   {
     const int nreal = c->P[1] * c->tiles * slots;
@@ -394,7 +395,7 @@ int run_batch(csngf_ctx* c, const float* dB, const uint8_t* dmB, const int* rotq
       constexpr int LC = decltype(lc)::value;
       hipLaunchKernelGGL((k_zpass<LC>), dim3(nb8), dim3(kThreads), lds, c->stream, c->d_buf2, c->d_spec, c->d_buf1,
                          c->nB[2], c->P[1], c->H, c->Hp, c->Wd[2], out_off, c->plz, c->d_tw, c->buf2_slot,
-                         c->buf1_slot, c->tiles, slots, nreal, c->d_flags, c->flag_slot);
+                         c->buf1_slot, c->tiles, slots, nreal, c->d_flags, c->flag_slot, c->nf);
     });
     prof_end(c, KT_ZPASS, ev);
     LAUNCHCHK("k_zpass");
@@ -549,7 +550,7 @@ int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims
   if (!(prm.eps > 0.f) || !std::isfinite(prm.eps)) return fail(CSNGF_E_INVALID_ARG, "eps must be finite and > 0");
   if (!(prm.gamma >= 0.f && prm.gamma <= 1.f)) return fail(CSNGF_E_INVALID_ARG, "gamma must lie in [0, 1]");
   if (prm.batch < 0) return fail(CSNGF_E_INVALID_ARG, "batch must be >= 0");
-  if (prm.flags & ~CSNGF_DEVICE_PTRS) return fail(CSNGF_E_INVALID_ARG, "unknown flag bits");
+  if (prm.flags & ~(CSNGF_DEVICE_PTRS | CSNGF_UNSQUARED)) return fail(CSNGF_E_INVALID_ARG, "unknown flag bits");
   if (maskA) return fail(CSNGF_E_UNSUPPORTED, "a user mask on the fixed volume is not supported (pass NULL)");
   const int nA[3] = {dA.nx, dA.ny, dA.nz}, nB[3] = {dB.nx, dB.ny, dB.nz};
   int P[3];
@@ -590,6 +591,7 @@ int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims
   c->eps = prm.eps;
   c->gamma = prm.gamma;
   c->flags = prm.flags;
+  c->nf = (prm.flags & CSNGF_UNSQUARED) ? 3 : 6;
   c->H = P[0] / 2 + 1;
   c->Hp = (c->H + kTileW - 1) / kTileW * kTileW;
   c->tiles = c->Hp / kTileW;
@@ -610,7 +612,7 @@ int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims
   }
   const long long Hp = c->Hp;
   c->count_a = (long long)(nA[0] - 2) * (nA[1] - 2) * (nA[2] - 2);
-  c->spec_bytes = (long long)sizeof(float2) * 6 * P[2] * P[1] * Hp;
+  c->spec_bytes = (long long)sizeof(float2) * c->nf * P[2] * P[1] * Hp;
   if ((rc = dalloc(&c->d_spec, (size_t)c->spec_bytes))) return bail(rc);
   if ((rc = dalloc(&c->d_flag, sizeof(int)))) return bail(rc);
 
@@ -627,7 +629,7 @@ int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims
       dA_ptr = tmpA;
     }
     float2 *x1 = nullptr, *x2 = nullptr;
-    const long long x1e = 6LL * nA[2] * nA[1] * Hp, x2e = 6LL * nA[2] * P[1] * Hp;
+    const long long x1e = (long long)c->nf * nA[2] * nA[1] * Hp, x2e = (long long)c->nf * nA[2] * P[1] * Hp;
     rc = dalloc(&x1, sizeof(float2) * x1e);
     if (!rc) rc = dalloc(&x2, sizeof(float2) * x2e);
     if (!rc && (prm.flags & CSNGF_DEVICE_PTRS)) {
@@ -637,15 +639,15 @@ int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims
     if (!rc) rc = launch_fields(c, false, dA_ptr, nullptr, nA, nullptr, x1, 0, nullptr, 0, nullptr, 1);
     if (!rc)
       rc = launch_pencil(c, false, x1, x2, nA[1], P[1], 0, c->ply, (long long)nA[1] * Hp, (long long)P[1] * Hp,
-                         6 * nA[2], 0, 0, 1);
+                         c->nf * nA[2], 0, 0, 1);
     if (!rc) {
       const float scale = (float)(1.0 / ((double)P[0] * (double)P[1] * (double)P[2]));
-      const dim3 grid(c->tiles, P[1], 6);
+      const dim3 grid(c->tiles, P[1], c->nf);
       const size_t lds = lds_pencil(P[2]);
       with_len(P[2], [&](auto lc) {
         constexpr int LC = decltype(lc)::value;
         hipLaunchKernelGGL((k_zstore<LC>), grid, dim3(kThreads), lds, c->stream, x2, c->d_spec, nA[2], P[1], c->H,
-                           c->Hp, c->plz, c->d_tw, scale);
+                           c->Hp, c->plz, c->d_tw, scale, c->nf);
       });
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) rc = hip_fail(e, "k_zstore");
@@ -664,8 +666,8 @@ int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims
   // ---- rotation workspaces
   {
     const long long nvB = (long long)nB[0] * nB[1] * nB[2];
-    c->buf1_slot = std::max(6LL * nB[2] * nB[1], (long long)c->Wd[2] * P[1]) * Hp;
-    c->buf2_slot = std::max(6LL * nB[2] * P[1], (long long)c->Wd[2] * c->Wd[1]) * Hp;
+    c->buf1_slot = std::max((long long)c->nf * nB[2] * nB[1], (long long)c->Wd[2] * P[1]) * Hp;
+    c->buf2_slot = std::max((long long)c->nf * nB[2] * P[1], (long long)c->Wd[2] * c->Wd[1]) * Hp;
     c->mask_slot = (nvB + 255) / 256 * 256;
     c->sat_slot = ((long long)(nB[0] + 1) * (nB[1] + 1) * (nB[2] + 1) + 63) / 64 * 64;
     c->flag_slot = ((long long)c->Wd[2] * (1 + c->Wd[1]) + 255) / 256 * 256;
@@ -883,6 +885,7 @@ int csngf_debug_fields(const float* vol, const uint8_t* vmask, csngf_dims d, con
   csngf_ctx tmp;
   tmp.stream = nullptr;
   tmp.eps = eps;
+  tmp.nf = (flags & CSNGF_UNSQUARED) ? 3 : 6;
   factor_plan(Px, tmp.plx);
   tmp.plx.tw_off = 0;
   tmp.H = Px / 2 + 1;
@@ -905,7 +908,7 @@ int csngf_debug_fields(const float* vol, const uint8_t* vmask, csngf_dims d, con
   };
   const int n3[3] = {d.nx, d.ny, d.nz};
   if ((rc = dalloc(&tmp.d_tw, sizeof(float2) * Px))) return done(rc);
-  if ((rc = dalloc(&x1, sizeof(float2) * 6 * (size_t)d.nz * d.ny * tmp.Hp))) return done(rc);
+  if ((rc = dalloc(&x1, sizeof(float2) * tmp.nf * (size_t)d.nz * d.ny * tmp.Hp))) return done(rc);
   owned.push_back(x1);
   if ((rc = dalloc(&drot, sizeof(kq)))) return done(rc);
   owned.push_back(drot);
@@ -923,7 +926,7 @@ int csngf_debug_fields(const float* vol, const uint8_t* vmask, csngf_dims d, con
       if (hipMemcpy(dvm, vmask, nv, hipMemcpyHostToDevice) != hipSuccess)
         return done(hip_fail(hipGetLastError(), "upload"));
     }
-    if ((rc = dalloc(&dprod, sizeof(float) * 6 * nv))) return done(rc);
+    if ((rc = dalloc(&dprod, sizeof(float) * tmp.nf * nv))) return done(rc);
     owned.push_back(dprod);
     if ((rc = dalloc(&dmask, nv))) return done(rc);
     owned.push_back(dmask);
@@ -932,7 +935,7 @@ int csngf_debug_fields(const float* vol, const uint8_t* vmask, csngf_dims d, con
   if (rc) return done(rc);
   if (hipDeviceSynchronize() != hipSuccess) return done(hip_fail(hipGetLastError(), "k_fields_x"));
   if (!dev) {
-    if (hipMemcpy(prod6, dprod, sizeof(float) * 6 * nv, hipMemcpyDeviceToHost) != hipSuccess ||
+    if (hipMemcpy(prod6, dprod, sizeof(float) * tmp.nf * nv, hipMemcpyDeviceToHost) != hipSuccess ||
         hipMemcpy(mask, dmask, nv, hipMemcpyDeviceToHost) != hipSuccess)
       return done(hip_fail(hipGetLastError(), "download"));
   }

@@ -88,7 +88,7 @@ constexpr int xrow_stride() { return LC > 0 ? kRowsX + 1 : kRowsX; }
 template <bool MOVING, int LC>
 __global__ __launch_bounds__(kThreads) void k_fields_x(
     const float* __restrict__ vol, const uint8_t* __restrict__ umask, int nx, int ny, int nz, int tz, int nslots,
-    const int* __restrict__ rotq, float eps, FftPlan pl, const float2* __restrict__ twtab,
+    int nf, const int* __restrict__ rotq, float eps, FftPlan pl, const float2* __restrict__ twtab,
     float2* __restrict__ out, int H, int Hp, long long out_slot_stride,
     uint8_t* __restrict__ mask_out, long long mask_slot_stride, float* __restrict__ dbg_prod) {
   constexpr int TY = kRowsX;
@@ -195,21 +195,26 @@ __global__ __launch_bounds__(kThreads) void k_fields_x(
       }
     }
     __syncthreads();
+    // 6 fields (squared measure): (xx,yy), (zz,xy), (xz,yz); 3 fields (unsquared): (x,y), (z,-)
+    const int npairs = (nf + 1) / 2;
 #pragma unroll 1
-    for (int pair = 0; pair < 3; ++pair) {
+    for (int pair = 0; pair < npairs; ++pair) {
       auto products = [&](int x, int r) -> float2 {
         if (x >= nx) return make_float2(0.f, 0.f);
         const int e = r * nx + x;
         const float n0 = ng[e], n1 = ng[TY * nx + e], n2 = ng[2 * TY * nx + e];
         float fa, fb;
-        if (pair == 0) { fa = n0 * n0; fb = n1 * n1; }
+        if (nf == 3) {
+          fa = pair == 0 ? n0 : n2;
+          fb = pair == 0 ? n1 : 0.f;
+        } else if (pair == 0) { fa = n0 * n0; fb = n1 * n1; }
         else if (pair == 1) { fa = n2 * n2; fb = n0 * n1; }
         else { fa = n0 * n2; fb = n1 * n2; }
         const int yy = y0 + r;
         if (dbg_prod && slot == 0 && yy < ny) {
           const long vox = ((long)z * ny + yy) * nx + x;
           dbg_prod[(2 * pair) * nv + vox] = fa;
-          dbg_prod[(2 * pair + 1) * nv + vox] = fb;
+          if (2 * pair + 1 < nf) dbg_prod[(2 * pair + 1) * nv + vox] = fb;
         }
         return make_float2(fa, fb);
       };
@@ -224,9 +229,11 @@ __global__ __launch_bounds__(kThreads) void k_fields_x(
         const float2 zk = buf[k * WS + r];
         const float2 zc = buf[((Px - k) % Px) * WS + r];
         float2* oa = out + slot * out_slot_stride + (((long)(2 * pair) * nz + z) * ny + yy) * Hp;
-        float2* ob = out + slot * out_slot_stride + (((long)(2 * pair + 1) * nz + z) * ny + yy) * Hp;
         oa[k] = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y - zc.y));
-        ob[k] = make_float2(0.5f * (zk.y + zc.y), 0.5f * (zc.x - zk.x));
+        if (2 * pair + 1 < nf) {
+          float2* ob = out + slot * out_slot_stride + (((long)(2 * pair + 1) * nz + z) * ny + yy) * Hp;
+          ob[k] = make_float2(0.5f * (zk.y + zc.y), 0.5f * (zc.x - zk.x));
+        }
       }
       __syncthreads();
     }
@@ -280,7 +287,7 @@ __global__ __launch_bounds__(kThreads) void k_zpass(
     const float2* __restrict__ X2, const float2* __restrict__ spec, float2* __restrict__ Y3,
     int nz, int Py, int H, int Hp, int Wz, int out_off, FftPlan pl, const float2* __restrict__ twtab,
     long long x2_sstride, long long y3_sstride, int ntiles, int nslots, int nreal,
-    const uint8_t* __restrict__ flags, long long flag_sstride) {
+    const uint8_t* __restrict__ flags, long long flag_sstride, int nf) {
   constexpr int W = kTileW;
   constexpr int NSLOT = consumer_slots<LC, W, kThreads>();
   extern __shared__ __align__(16) unsigned char smem[];
@@ -306,7 +313,7 @@ __global__ __launch_bounds__(kThreads) void k_zpass(
   const long long fstride_sp = (long long)Pz * Py * Hp;
   const long long zs = (long long)Py * Hp;
 #pragma unroll 1
-  for (int f = 0; f < 6; ++f) {
+  for (int f = 0; f < nf; ++f) {
     const float2* src = X2 + slot * x2_sstride + f * fstride_x2 + (long long)ky * Hp + kx0;
     const float2* a = spec + f * fstride_sp + (long long)ky * Hp + kx0;
     fft_io<LC, W, kThreads, false, false, false>(
@@ -341,11 +348,12 @@ __global__ __launch_bounds__(kThreads) void k_zpass(
       });
 }
 
-// Fixed side: z forward of A's fields, stored as w_f * scale * conj(.) in spec[f][kz][ky][kx].
+// Fixed side: z forward of A's fields, stored as w_f * scale * conj(.) in spec[f][kz][ky][kx]
+// (w_f = 2 for the cross products of the squared measure, else 1).
 template <int LC>
 __global__ __launch_bounds__(kThreads) void k_zstore(
     const float2* __restrict__ X2, float2* __restrict__ spec, int nz, int Py, int H, int Hp,
-    FftPlan pl, const float2* __restrict__ twtab, float scale) {
+    FftPlan pl, const float2* __restrict__ twtab, float scale, int nf) {
   constexpr int W = kTileW;
   extern __shared__ __align__(16) unsigned char smem[];
   const int Pz = pl.L;
@@ -358,7 +366,7 @@ __global__ __launch_bounds__(kThreads) void k_zstore(
   if (LC == 0) __syncthreads();
   const long long zs = (long long)Py * Hp;
   const float2* src = X2 + (long long)f * nz * zs + (long long)ky * Hp + kx0;
-  const float w = (f >= 3 ? 2.0f : 1.0f) * scale;
+  const float w = (nf == 6 && f >= 3 ? 2.0f : 1.0f) * scale;  // Eq. (6) cross terms x2
   float2* dst = spec + (long long)f * Pz * zs + (long long)ky * Hp + kx0;
   fft_io<LC, W, kThreads, false, false, false>(
       buf, tw, pl,

@@ -294,3 +294,47 @@ def test_device_pointer_path_with_torch_stream():
         Ch, Nh = hctx.evaluate_map(pair.B, np.eye(3))
     assert np.array_equal(Cm.cpu().numpy(), Ch) and np.array_equal(Nm.cpu().numpy(), Nh)
     assert tuple(best.shift) == pair.true_shift
+
+
+# ----------------------------------------------------------------------------- USNGF (Eq. (3))
+def test_unsquared_field_stage_against_oracle():
+    rng = np.random.default_rng(40)
+    pair = synth.config0()
+    R = _rand_rot(rng, 40)
+    prod, m = bd.debug_fields(pair.B, R=R, unsquared=True)
+    Rq = O.quantize_rotation(R)
+    f = O.moving_fields(pair.B, Rq)
+    Bh, _ = O.rotate_resample(pair.B, Rq)
+    g = O.gradient(Bh)
+    bound = _field_bound(pair.B, np.sum(g * g, axis=0), 1e-5)
+    assert np.array_equal(m.astype(bool), f.mask)
+    for k in range(3):
+        assert np.all(np.abs(prod[k] - np.where(f.mask, f.n[k], 0.0)) <= bound)
+
+
+@pytest.mark.parametrize("case", range(3))
+def test_unsquared_maps_against_oracle(case):
+    rng = np.random.default_rng(60 + case)
+    if case == 0:
+        pair = synth.config0()
+        A, B, R, P = pair.A, pair.B, np.eye(3), pair.pad
+    else:
+        from scipy.ndimage import gaussian_filter
+        sa = tuple(int(v) for v in rng.integers(6, 20, size=3))
+        sb = tuple(int(v) for v in rng.integers(6, 20, size=3))
+        A = gaussian_filter(rng.random(sa), 1.0).astype(np.float32)
+        B = gaussian_filter(rng.random(sb), 1.0).astype(np.float32)
+        R, P = _rand_rot(rng, 50), (0, 0, 0)
+    _say("usngf", case, A.shape, B.shape)
+    with bd.Context(A, bd.dims_of(B), pad=P, measure="unsquared") as ctx:
+        Pused = tuple(ctx.info().pad)
+        Cg, Ng = ctx.evaluate_map(B, R)
+        Cn, Nn = ctx.evaluate_map(-B, R)
+    fa = O.fixed_fields(A)
+    fb = O.moving_fields(B, O.quantize_rotation(R))
+    S, N = O.correlation_maps_fft(fa, fb, Pused, measure="unsquared")
+    Co, _ = O.normalise(S, N, int(fa.mask.sum()), int(fb.mask.sum()))
+    _compare_maps(Cg, Ng, Co, N, f"usngf{case}")
+    # sign sensitivity of the unsquared measure: exact negation on the GPU as well
+    v = np.isfinite(Cg)
+    assert np.array_equal(np.isfinite(Cn), v) and np.array_equal(Cn[v], -Cg[v])

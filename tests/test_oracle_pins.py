@@ -377,3 +377,77 @@ def test_translated_copy_recovers_shift(t):
       max(0, tx):max(0, tx) + src.shape[2]] = src
     res, best = O.evaluate(A, B, np.eye(3)[None])
     assert res[0].shift == t
+
+
+# ----------------------------------------------------------------------------- USNGF, Eq. (3)
+def _brute_force_unsquared(fa, fb):
+    """Nested loops with the plain (unsquared) dot product of Eq. (3)."""
+    na, nb = fa.mask.shape, fb.mask.shape
+    ma, mb = fa.mask.tolist(), fb.mask.tolist()
+    A = [fa.n[k].tolist() for k in range(3)]
+    B = [fb.n[k].tolist() for k in range(3)]
+    W = tuple(na[i] + nb[i] - 1 for i in range(3))
+    S = np.zeros(W)
+    for cz in range(-(na[0] - 1), nb[0]):
+        for cy in range(-(na[1] - 1), nb[1]):
+            for cx in range(-(na[2] - 1), nb[2]):
+                s = 0.0
+                for z in range(max(0, -cz), min(na[0], nb[0] - cz)):
+                    for y in range(max(0, -cy), min(na[1], nb[1] - cy)):
+                        for x in range(max(0, -cx), min(na[2], nb[2] - cx)):
+                            if ma[z][y][x] and mb[z + cz][y + cy][x + cx]:
+                                s += sum(A[k][z][y][x] * B[k][z + cz][y + cy][x + cx] for k in range(3))
+                S[cz + na[0] - 1, cy + na[1] - 1, cx + na[2] - 1] = s
+    return S
+
+
+def test_unsquared_fft_route_matches_brute_force():
+    rng = np.random.default_rng(31)
+    A, B = rng.random((5, 6, 4)), rng.random((4, 5, 6))
+    Rq = O.quantize_rotation(_rand_rot(rng, 30))
+    fa, fb = O.fixed_fields(A, rng.random(A.shape) > 0.1), O.moving_fields(B, Rq)
+    Sb = _brute_force_unsquared(fa, fb)
+    Sf, _ = O.correlation_maps_fft(fa, fb, measure="unsquared")
+    Sd, _ = O.correlation_maps_direct(fa, fb, measure="unsquared")
+    assert np.max(np.abs(Sf - Sb)) < 1e-12 and np.max(np.abs(Sd - Sb)) < 1e-12
+
+
+def test_unsquared_is_antisymmetric_in_the_sign_of_b():
+    """Eq. (3) changes sign with the gradient sign (the sensitivity Sec. 2 and Sec. 5.1 discuss):
+    C_us(A, -B) = -C_us(A, B) exactly, while the squared measure is unchanged."""
+    rng = np.random.default_rng(32)
+    A, B = rng.random((6, 6, 7)), rng.random((7, 6, 6))
+    R = _rand_rot(rng)[None]
+    r1, _ = O.evaluate(A, B, R, keep_maps=True, measure="unsquared")
+    r2, _ = O.evaluate(A, -B, R, keep_maps=True, measure="unsquared")
+    v = np.isfinite(r1[0].C)
+    assert np.array_equal(np.isfinite(r2[0].C), v)
+    assert np.array_equal(r1[0].C[v], -r2[0].C[v])
+
+
+@pytest.mark.parametrize("sign", [1.0, -1.0])
+def test_unsquared_parallel_and_orthogonal_closed_forms(sign):
+    rng = np.random.default_rng(33)
+    eps = 1e-5
+    d = rng.normal(size=3)
+    d /= np.linalg.norm(d)
+    A = _ramp((8, 9, 8), d, 2e-5)
+    B = _ramp((9, 8, 8), sign * d, 0.4, 0.1)
+    R = _rand_rot(rng, 30)
+    Rq = O.quantize_rotation(R)
+    gA, gB = 2e-5 * d, sign * 0.4 * (Rq.T @ d)
+    expect = float((gA / math.sqrt(gA @ gA + eps * eps)) @ (gB / math.sqrt(gB @ gB + eps * eps)))
+    res, _ = O.evaluate(A, B, R[None], keep_maps=True, measure="unsquared")
+    C = res[0].C
+    v = np.isfinite(C)
+    assert v.sum() > 10 and np.max(np.abs(C[v] - expect)) < 1e-9
+    assert np.sign(expect) == sign
+    # squared measure on the same pair is the square of the unsquared one
+    rs, _ = O.evaluate(A, B, R[None], keep_maps=True)
+    assert np.max(np.abs(rs[0].C[v] - expect ** 2)) < 1e-9
+    # orthogonal ramps: zero
+    Ao = _ramp((8, 9, 8), (1, 0, 0), 0.3)
+    Bo = _ramp((9, 8, 8), (0, 0, 1), 0.3)
+    ro, _ = O.evaluate(Ao, Bo, np.eye(3)[None], keep_maps=True, measure="unsquared")
+    vo = np.isfinite(ro[0].C)
+    assert np.max(np.abs(ro[0].C[vo])) < 1e-12

@@ -141,6 +141,16 @@ int csngf_evaluate_map(csngf_ctx* ctx, const float* B, const uint8_t* maskB, con
 
 int csngf_destroy(csngf_ctx* ctx);
 
+/* One level of the Gaussian pyramid of the global search (Sec. 3.2): blur vol (dims d) with
+ * a Gaussian of standard deviation sigma voxels per axis (taps exp(-k^2 / (2 sigma^2)) for
+ * |k| <= int(4 sigma + 0.5), normalised to sum 1, edge samples replicated; sigma = 0 copies)
+ * and keep every factor-th voxel from index 0: out dims m = ceil(n / factor) per axis,
+ * out[z][y][x] = blurred[factor z][factor y][factor x].  *out_dims receives m (may be
+ * queried with out = NULL).  Device pointers with CSNGF_DEVICE_PTRS in flags (asynchronous
+ * on stream), host pointers otherwise (synchronous).  factor >= 1, sigma in [0, 64]. */
+int csngf_smooth_downsample(const float* vol, csngf_dims d, float sigma, int32_t factor, float* out,
+                            csngf_dims* out_dims, uint32_t flags, void* stream);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* csngf_last_error(void);
 

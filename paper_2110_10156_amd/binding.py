@@ -72,6 +72,8 @@ SIGNATURES = {
     "csngf_debug_fft": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p]),
     "csngf_debug_fields": (C.c_int, [C.c_void_p, C.c_void_p, Dims, C.c_void_p, C.c_float, C.c_int32,
                                      C.c_void_p, C.c_void_p, C.c_uint32]),
+    "csngf_smooth_downsample": (C.c_int, [C.c_void_p, Dims, C.c_float, C.c_int32, C.c_void_p, C.POINTER(Dims),
+                                          C.c_uint32, C.c_void_p]),
     "csngf_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
     "csngf_profile_read": (C.c_int, [C.c_void_p, C.POINTER(KernelStat), C.c_int32, C.POINTER(C.c_int32)]),
     "csngf_profile_reset": (C.c_int, [C.c_void_p]),
@@ -260,3 +262,26 @@ def debug_fields(vol, R=None, mask=None, eps=1e-5, Px=0, unsquared=False):
     _check(lib().csngf_debug_fields(_ptr(vol), _ptr(mk), dims_of(vol), Rp, eps, Px, _ptr(prod), _ptr(m),
                                     UNSQUARED if unsquared else 0))
     return prod, m
+
+
+def smooth_downsample(vol, sigma, factor, stream=None):
+    """Gaussian blur (sigma voxels) then keep every factor-th voxel: numpy in -> numpy out,
+    CUDA tensor in -> CUDA tensor out (on the given stream, else the current one)."""
+    dev = _is_device(vol)
+    if not dev:
+        vol = np.ascontiguousarray(vol, dtype=np.float32)
+    od = Dims()
+    _check(lib().csngf_smooth_downsample(_ptr(vol), dims_of(vol), float(sigma), int(factor), None, C.byref(od),
+                                         DEVICE_PTRS if dev else 0, None))
+    shape = (od.nz, od.ny, od.nx)
+    if dev:
+        import torch
+        out = torch.empty(shape, dtype=torch.float32, device=vol.device)
+        s = stream if stream is not None else torch.cuda.current_stream(vol.device)
+        _check(lib().csngf_smooth_downsample(_ptr(vol), dims_of(vol), float(sigma), int(factor), _ptr(out),
+                                             C.byref(od), DEVICE_PTRS, C.c_void_p(s.cuda_stream)))
+        return out
+    out = np.empty(shape, dtype=np.float32)
+    _check(lib().csngf_smooth_downsample(_ptr(vol), dims_of(vol), float(sigma), int(factor), _ptr(out), C.byref(od),
+                                         0, None))
+    return out

@@ -110,8 +110,8 @@ void with_len(int L, Fn&& fn) {
   case N:                                      \
     fn(std::integral_constant<int, N>{});      \
     return;
-    CSNGF_CASE(16) CSNGF_CASE(32) CSNGF_CASE(64) CSNGF_CASE(96) CSNGF_CASE(128) CSNGF_CASE(192)
-    CSNGF_CASE(220) CSNGF_CASE(256) CSNGF_CASE(352)
+    CSNGF_CASE(16) CSNGF_CASE(32) CSNGF_CASE(48) CSNGF_CASE(56) CSNGF_CASE(64) CSNGF_CASE(88) CSNGF_CASE(96)
+    CSNGF_CASE(110) CSNGF_CASE(128) CSNGF_CASE(176) CSNGF_CASE(192) CSNGF_CASE(220) CSNGF_CASE(256) CSNGF_CASE(352)
 #undef CSNGF_CASE
     default:
       fn(std::integral_constant<int, 0>{});
@@ -829,6 +829,77 @@ int csngf_destroy(csngf_ctx* c) {
   if (!c) return fail(CSNGF_E_INVALID_ARG, "ctx is NULL");
   release(c);
   return CSNGF_OK;
+}
+
+int csngf_smooth_downsample(const float* vol, csngf_dims d, float sigma, int32_t factor, float* out,
+                            csngf_dims* out_dims, uint32_t flags, void* stream) {
+  if (!vol || !out_dims) return fail(CSNGF_E_INVALID_ARG, "NULL argument");
+  if (d.nx < 1 || d.ny < 1 || d.nz < 1) return fail(CSNGF_E_INVALID_ARG, "extents must be >= 1");
+  if (factor < 1) return fail(CSNGF_E_INVALID_ARG, "factor must be >= 1");
+  if (!(sigma >= 0.f && sigma <= 64.f)) return fail(CSNGF_E_INVALID_ARG, "sigma must lie in [0, 64]");
+  if (flags & ~CSNGF_DEVICE_PTRS) return fail(CSNGF_E_INVALID_ARG, "unknown flag bits");
+  const int n[3] = {d.nx, d.ny, d.nz};
+  int m[3];
+  for (int i = 0; i < 3; ++i) m[i] = (n[i] + factor - 1) / factor;
+  *out_dims = csngf_dims{m[0], m[1], m[2]};
+  if (!out) return CSNGF_OK;
+  int rc = check_device();
+  if (rc) return rc;
+  const bool dev = flags & CSNGF_DEVICE_PTRS;
+  const size_t nv = (size_t)n[0] * n[1] * n[2], mv = (size_t)m[0] * m[1] * m[2];
+  if (!dev && !all_finite(vol, nv)) return fail(CSNGF_E_INVALID_ARG, "non-finite volume");
+  // taps, in double then rounded
+  const int K = sigma > 0.f ? (int)(4.0 * sigma + 0.5) : 0;
+  std::vector<float> w(2 * K + 1);
+  {
+    std::vector<double> wd(2 * K + 1);
+    double sum = 0;
+    for (int k = -K; k <= K; ++k) {
+      wd[k + K] = K ? std::exp(-(double)k * k / (2.0 * (double)sigma * sigma)) : 1.0;
+      sum += wd[k + K];
+    }
+    for (int k = 0; k <= 2 * K; ++k) w[k] = (float)(wd[k] / sum);
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  std::vector<void*> owned;
+  auto done = [&](int code) {
+    (void)hipStreamSynchronize(s);
+    for (void* p : owned) (void)hipFree(p);
+    return code;
+  };
+  float *dw = nullptr, *t1 = nullptr, *t2 = nullptr, *din = const_cast<float*>(vol), *dout = out;
+  if ((rc = dalloc(&dw, sizeof(float) * w.size()))) return done(rc);
+  owned.push_back(dw);
+  // pass x keeps m0 of n0 columns, pass y m1 of n1 rows, pass z m2 of n2 slices
+  if ((rc = dalloc(&t1, sizeof(float) * (size_t)m[0] * n[1] * n[2]))) return done(rc);
+  owned.push_back(t1);
+  if ((rc = dalloc(&t2, sizeof(float) * (size_t)m[0] * m[1] * n[2]))) return done(rc);
+  owned.push_back(t2);
+  if (!dev) {
+    if ((rc = dalloc(&din, sizeof(float) * nv))) return done(rc);
+    owned.push_back(din);
+    if ((rc = dalloc(&dout, sizeof(float) * mv))) return done(rc);
+    owned.push_back(dout);
+    if (hipMemcpyAsync(din, vol, sizeof(float) * nv, hipMemcpyHostToDevice, s) != hipSuccess)
+      return done(hip_fail(hipGetLastError(), "upload"));
+  }
+  if (hipMemcpyAsync(dw, w.data(), sizeof(float) * w.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+    return done(hip_fail(hipGetLastError(), "upload"));
+  auto blur = [&](const float* a, float* b, int outer, int len, int inner, int mm) {
+    const long long total = (long long)outer * mm * inner;
+    hipLaunchKernelGGL(k_blur_axis, dim3((unsigned)((total + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, a, b,
+                       outer, len, inner, mm, factor, dw, K);
+  };
+  blur(din, t1, n[2] * n[1], n[0], 1, m[0]);          // along x
+  blur(t1, t2, n[2], n[1], m[0], m[1]);               // along y
+  blur(t2, dout, 1, n[2], m[1] * m[0], m[2]);         // along z
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return done(hip_fail(e, "k_blur_axis"));
+  if (!dev) {
+    if (hipMemcpyAsync(out, dout, sizeof(float) * mv, hipMemcpyDeviceToHost, s) != hipSuccess)
+      return done(hip_fail(hipGetLastError(), "download"));
+  }
+  return done(CSNGF_OK);
 }
 
 // ---------------------------------------------------------------------------- debug / profile

@@ -668,6 +668,30 @@ __global__ void k_check_finite(const float* __restrict__ v, long long n, int* __
   if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
 }
 
+// ------------------------------------------------------------------------------ pyramid
+// One separable pass of a Gaussian blur along one axis, keeping every step-th output sample:
+// out[.., i, ..] = sum_k w[k] in[.., clamp(i * step + k - K), ..] along the axis, edges
+// replicated.  in is [outer][n][inner] (the blurred axis in the middle), out is [outer][m][inner].
+__global__ __launch_bounds__(kThreads) void k_blur_axis(const float* __restrict__ in, float* __restrict__ out,
+                                                        int outer, int n, int inner, int m, int step,
+                                                        const float* __restrict__ w, int K) {
+  const long long t = (long long)blockIdx.x * kThreads + threadIdx.x;
+  const long long total = (long long)outer * m * inner;
+  if (t >= total) return;
+  const int ii = (int)(t % inner);
+  const int i = (int)((t / inner) % m);
+  const long long o = t / ((long long)inner * m);
+  const float* src = in + o * n * inner + ii;
+  const int c = i * step;
+  float acc = 0.f;
+  for (int k = -K; k <= K; ++k) {
+    int j = c + k;
+    j = j < 0 ? 0 : (j >= n ? n - 1 : j);
+    acc = fmaf(w[k + K], src[(long long)j * inner], acc);
+  }
+  out[t] = acc;
+}
+
 // Batched C2C along a contiguous axis: in/out [batch][L]; 16 batch rows per workgroup.
 template <bool INV, int LC>
 __global__ __launch_bounds__(kThreads) void k_debug_fft(const float2* __restrict__ in, float2* __restrict__ out,

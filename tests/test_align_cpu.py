@@ -1,0 +1,85 @@
+"""Global search driver (pyramid + random rotations, Sec. 3.2): host logic on the CPU, with
+the FP64 oracle (and scipy's Gaussian filter) as the evaluator."""
+import math
+
+import numpy as np
+import pytest
+from scipy.ndimage import gaussian_filter
+
+import oracle as O
+from paper_2110_10156_amd import align, synth
+
+
+class OracleEvaluator:
+    """Pyramid levels with scipy (edge-replicating Gaussian, radius int(4 sigma + 0.5)) and
+    scores from the FP64 oracle."""
+
+    def level(self, A, B, sigma, d):
+        def f(v):
+            v = np.asarray(v, dtype=np.float64)
+            if sigma > 0:
+                v = gaussian_filter(v, sigma, mode="nearest", truncate=4.0)
+            return v[::d, ::d, ::d]
+        return f(A), f(B)
+
+    def score(self, Ak, Bk, Rs):
+        res, _ = O.evaluate(Ak, Bk, Rs)
+        return [r.score for r in res], [r.shift for r in res]
+
+
+def test_candidates_keep_starts_first_and_stay_in_range():
+    rng = np.random.default_rng(0)
+    starts = [(0.0, 0.0, 0.0), (40.0, -10.0, 5.0)]
+    c = align.candidates(starts, 30.0, 500, rng)
+    assert len(c) == 502 and c[:2] == starts
+    d = np.array(c[2:])
+    near0 = np.all(np.abs(d) <= 30.0, axis=1)
+    near1 = np.all(np.abs(d - np.array(starts[1])) <= 30.0, axis=1)
+    assert np.all(near0 | near1) and near0.any() and near1.any()
+    assert align.candidates(starts, 0.0, 0, rng) == starts
+
+
+def test_top_p_is_stable_on_ties():
+    assert align.top_p([0.2, 0.7, 0.7, -np.inf, 0.1], 3) == [1, 2, 0]
+    assert align.top_p([0.5], 3) == [0]
+
+
+def test_corner_distance():
+    s = (10, 12, 14)
+    assert align.corner_distance(s, s, np.eye(3), (1, 2, 3), np.eye(3), (1, 2, 3)) == 0.0
+    assert abs(align.corner_distance(s, s, np.eye(3), (0, 0, 0), np.eye(3), (3, 0, 4)) - 5.0) < 1e-12
+    # a half turn about z through B's centre moves every corner of a centred block by twice
+    # its xy distance from the axis
+    R = np.diag([-1.0, -1.0, 1.0])
+    n = (5, 5, 5)
+    expect = 2 * math.hypot(2.0, 2.0)
+    assert abs(align.corner_distance(n, n, np.eye(3), (0, 0, 0), R, (0, 0, 0)) - expect) < 1e-12
+
+
+def test_paper_schedule_values():
+    s = align.PAPER_SCHEDULE
+    assert s["d"] == (4, 2, 2, 1) and s["a"] == (5000, 3000, 300, 0) and s["p"] == (1, 20, 3, 1)
+    assert s["u"] == (180.0, 30.0, 10.0, 0.0) and s["sigma"] == (5.0, 3.0, 2.0, 1.5)
+    assert s["start"] == ((0.0, 0.0, 0.0),)
+
+
+def test_oracle_driven_search_recovers_a_shift_and_small_rotation():
+    """A 32^3 pair rotated by 12 deg about z and shifted: a two-level search finds both."""
+    pair = synth.config0()
+    rng = np.random.default_rng(5)
+    from scipy.ndimage import affine_transform
+    R_true = synth.euler_xyz_matrix(0.0, 0.0, 12.0)
+    c = (np.array([32, 32, 32]) - 1) / 2.0
+    # B(y) = A(R^-1 (y - c) + c - t) sampled on B's grid, in (z, y, x) array order
+    t = np.array([2.0, -3.0, 1.0])
+    Rinv = np.linalg.inv(R_true)
+    P = np.array([[0, 0, 1], [0, 1, 0], [1, 0, 0]], dtype=float)  # xyz <-> zyx
+    M = P @ Rinv @ P
+    off = P @ (c - Rinv @ c - t)
+    B = affine_transform(pair.A.astype(np.float64), M, offset=off, order=1, mode="nearest")
+    sched = {"sigma": (1.0, 0.0), "d": (2, 1), "u": (20.0, 3.0), "a": (60, 20), "p": (1, 3, 1),
+             "start": ((0.0, 0.0, 0.0),)}
+    res = align.align(pair.A, B, sched, seed=1, evaluator=OracleEvaluator())
+    dE = align.corner_distance(pair.A.shape, B.shape, R_true, tuple(t), res.R, res.shift)
+    assert dE < 3.0, (res.euler_deg, res.shift, dE)
+    assert len(res.levels) == 2 and res.levels[0].candidates == 61 and res.levels[1].candidates == 23

@@ -57,11 +57,18 @@ def kernel_bytes(nA, nB, P):
     }
 
 
-def source_hash():
-    h = hashlib.sha256()
-    for f in ("csngf_kernels.hpp", "csngf_fft.hpp"):
-        with open(os.path.join(ROOT, "paper_2110_10156_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+KERNEL_SOURCE = {"z_mac_inverse": "k_zpass", "y_forward": "k_pencil", "y_inverse": "k_pencil",
+                 "fields_x": "k_fields_x", "x_c2r_argmax": "k_final_x"}
+
+
+def source_hash(kernel="z_mac_inverse"):
+    """Hash of the FFT engine plus the source text of the kernel's own function."""
+    csrc = os.path.join(ROOT, "paper_2110_10156_amd", "csrc")
+    h = hashlib.sha256(open(os.path.join(csrc, "csngf_fft.hpp"), "rb").read())
+    text = open(os.path.join(csrc, "csngf_kernels.hpp")).read()
+    name = KERNEL_SOURCE.get(kernel, kernel)
+    m = re.search(r"void " + re.escape(name) + r"\(.*?\n}\n", text, flags=re.S)
+    h.update((m.group(0) if m else text).encode())
     return h.hexdigest()[:16]
 
 
@@ -75,7 +82,7 @@ def read_traffic(kernel, workload):
     m = re.search(r"source_hash:\s*([0-9a-f]+)", text)
     b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
     r = re.search(r"rotations_per_launch:\s*([0-9]+)", text)
-    if not (m and b and r) or m.group(1) != source_hash():
+    if not (m and b and r) or m.group(1) != source_hash(kernel):
         return None
     return float(b.group(1)), int(r.group(1))
 
@@ -103,6 +110,8 @@ def main():
                     help="rotations timed on the one-rotation-per-launch path (0 = skip)")
     ap.add_argument("--usngf-rotations", type=int, default=200,
                     help="rotations timed with the unsquared measure, Eq. (3) (0 = skip)")
+    ap.add_argument("--align-runs", type=int, default=5,
+                    help="full global alignments (paper schedule) timed for p50/p99 latency (0 = skip)")
     ap.add_argument("--no-profile", action="store_true", help="do not record per-kernel events")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
@@ -208,6 +217,26 @@ def main():
             usngf = len(ur) / (time.perf_counter() - ts)
         print(f"[bench] unsquared measure {usngf:.1f} rot/s", file=sys.stderr, flush=True)
 
+    align_stats = None
+    if args.align_runs > 0:
+        from paper_2110_10156_amd import align as al
+        alat, dEs, ok = [], [], 0
+        al.align(pair.A, pair.B, al.PAPER_SCHEDULE, seed=1000)  # warm-up (kernels, contexts)
+        for r in range(args.align_runs):
+            torch.cuda.synchronize()
+            res = al.align(A, B, al.PAPER_SCHEDULE, seed=r)
+            alat.append(res.seconds)
+            dE = al.corner_distance(pair.A.shape, pair.B.shape, pair.true_rotation, pair.true_shift, res.R, res.shift)
+            dEs.append(dE)
+            ok += dE < 5.0
+            print(f"[bench] alignment {r}: {res.seconds:.3f} s, d_E {dE:.2f} vx", file=sys.stderr, flush=True)
+        la = np.array(alat) * 1e3
+        align_stats = {"p50_ms": round(float(np.percentile(la, 50)), 1), "p99_ms": round(float(np.percentile(la, 99)), 1),
+                       "runs": args.align_runs, "success_dE_lt_5": ok, "median_dE_vx": round(float(np.median(dEs)), 2),
+                       "evaluations": sum(p + a for p, a in zip(al.PAPER_SCHEDULE["p"], al.PAPER_SCHEDULE["a"])),
+                       "what": "global rigid alignment of the 176x176x110 pair with the paper's pyramid schedule "
+                               "(host to host, seeds 0..runs-1)"}
+
     cpu = None
     if args.cpu_rotations > 0:
         cpu = cpu_baseline(pair, args.cpu_rotations)
@@ -231,6 +260,7 @@ def main():
         "config": {"workload": "176x176x110 float32 pair (3.4 Mvoxel), 4-class shell phantom, "
                                f"{len(rots)} random rotations per step, FFT 352x352x220, full displacement map",
                    "rotations_per_step": len(rots), "fft_size": list(info.pad), "slots": slots},
+        "alignment_latency": align_stats,
         "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 3),
                        "p99": round(float(np.percentile(lat_ms, 99)), 3),
                        "what": f"one csngf_evaluate call of {len(rots)} rotations, host to host"},

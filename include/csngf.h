@@ -61,6 +61,10 @@ extern "C" {
  * components (weight 1) instead of the 6 products of Eq. (6); scores lie in [-1, 1] and
  * change sign with the gradient sign of either volume. */
 #define CSNGF_UNSQUARED 2u
+/* params.flags: record each context's per-batch launch sequence once as a HIP graph and
+ * replay it for every full batch of rotations (re-recorded when B's device pointers change;
+ * ignored while profiling is enabled).  Results are identical to the eager launches. */
+#define CSNGF_GRAPHS 4u
 
 typedef struct csngf_ctx csngf_ctx;
 
@@ -74,7 +78,7 @@ typedef struct {
   float gamma;          /* minimum overlap fraction in [0, 1], Sec. 3.2; default 0.5 */
   int32_t pad[3];       /* FFT size (Px, Py, Pz); 0 = smallest supported >= n_A + n_B - 1 */
   int32_t batch;        /* rotations in flight per launch sequence; 0 = automatic */
-  uint32_t flags;       /* CSNGF_DEVICE_PTRS | CSNGF_UNSQUARED */
+  uint32_t flags;       /* CSNGF_DEVICE_PTRS | CSNGF_UNSQUARED | CSNGF_GRAPHS */
 } csngf_params;
 
 typedef struct {
@@ -133,6 +137,19 @@ int csngf_get_info(const csngf_ctx* ctx, csngf_info* out);
 int csngf_evaluate(csngf_ctx* ctx, const float* B, const uint8_t* maskB, const double* R,
                    int32_t n, csngf_rot_result* per_rot, csngf_best* best);
 
+/* Asynchronous form of csngf_evaluate: validates and quantises the rotations, enqueues the
+ * whole evaluation on the context's stream and returns.  B and maskB must stay valid until
+ * csngf_wait returns.  One evaluation may be in flight per context; contexts on different
+ * streams run concurrently on the device (many volume pairs at once). */
+int csngf_evaluate_async(csngf_ctx* ctx, const float* B, const uint8_t* maskB, const double* R, int32_t n);
+
+/* 1 when the context has no evaluation in flight or it has finished, 0 while it runs. */
+int csngf_query(csngf_ctx* ctx);
+
+/* Wait for the evaluation in flight and return its results exactly as csngf_evaluate would
+ * (per_rot: n entries or NULL; best or NULL).  CSNGF_E_INVALID_ARG when none is in flight. */
+int csngf_wait(csngf_ctx* ctx, csngf_rot_result* per_rot, csngf_best* best);
+
 /* Full maps for one rotation (diagnosis and parity): C[Wz][Wy][Wx] float32 with -inf where
  * chi is invalid, and optionally N[Wz][Wy][Wx] int64 (may be NULL).  Index i = chi + n_A - 1
  * per axis.  Host or device pointers per params.flags. */
@@ -150,6 +167,16 @@ int csngf_destroy(csngf_ctx* ctx);
  * on stream), host pointers otherwise (synchronous).  factor >= 1, sigma in [0, 64]. */
 int csngf_smooth_downsample(const float* vol, csngf_dims d, float sigma, int32_t factor, float* out,
                             csngf_dims* out_dims, uint32_t flags, void* stream);
+
+/* Autotuner: for the shapes of A and B and the base params (eps, gamma, flags), time the
+ * candidate configurations - FFT size per axis (the smallest supported length and, if that
+ * has no compile-time plan, the smallest one that has, within 1.5x) and rotation slots in
+ * flight (the automatic choice, half and double) - on n_probe deterministic random
+ * rotations, and return the fastest in *best (pad and batch set) and its rate in rotations/s
+ * (*best_rate may be NULL).  Creates and destroys contexts; results do not depend on the
+ * choice (any FFT size >= n_A + n_B - 1 gives the same linear correlation). */
+int csngf_autotune(const float* A, csngf_dims dA, const float* B, csngf_dims dB, const csngf_params* base,
+                   int32_t n_probe, csngf_params* best, double* best_rate);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* csngf_last_error(void);

@@ -23,6 +23,7 @@ E_DEVICE = -5
 E_NO_VALID_SHIFT = -6
 DEVICE_PTRS = 1
 UNSQUARED = 2
+GRAPHS = 4
 
 _NAMES = {0: "OK", -1: "E_INVALID_ARG", -2: "E_UNSUPPORTED", -3: "E_NO_DEVICE", -4: "E_OUT_OF_MEMORY",
           -5: "E_DEVICE", -6: "E_NO_VALID_SHIFT"}
@@ -67,6 +68,11 @@ SIGNATURES = {
     "csngf_evaluate": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                  C.POINTER(RotResult), C.POINTER(Best)]),
     "csngf_evaluate_map": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "csngf_evaluate_async": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
+    "csngf_query": (C.c_int, [C.c_void_p]),
+    "csngf_wait": (C.c_int, [C.c_void_p, C.POINTER(RotResult), C.POINTER(Best)]),
+    "csngf_autotune": (C.c_int, [C.c_void_p, Dims, C.c_void_p, Dims, C.POINTER(Params), C.c_int32,
+                                 C.POINTER(Params), C.POINTER(C.c_double)]),
     "csngf_destroy": (C.c_int, [C.c_void_p]),
     "csngf_last_error": (C.c_char_p, []),
     "csngf_debug_fft": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p]),
@@ -142,8 +148,9 @@ class Context:
     """Owns a csngf_ctx: A's resident spectra and the rotation workspaces."""
 
     def __init__(self, A, dims_b, *, mask_a=None, eps=1e-5, gamma=0.5, pad=(0, 0, 0), batch=0, stream=None,
-                 measure="squared"):
-        """measure: "squared" (Eq. (2), CSNGF) or "unsquared" (Eq. (3), USNGF)."""
+                 measure="squared", graphs=False):
+        """measure: "squared" (Eq. (2), CSNGF) or "unsquared" (Eq. (3), USNGF); graphs: replay
+        each full batch from a recorded HIP graph."""
         if measure not in ("squared", "unsquared"):
             raise ValueError(f"unknown measure {measure!r}")
         self.device = _is_device(A)
@@ -154,7 +161,8 @@ class Context:
         p.gamma = gamma
         p.pad[:] = list(pad)
         p.batch = batch
-        p.flags = (DEVICE_PTRS if self.device else 0) | (UNSQUARED if measure == "unsquared" else 0)
+        p.flags = ((DEVICE_PTRS if self.device else 0) | (UNSQUARED if measure == "unsquared" else 0)
+                   | (GRAPHS if graphs else 0))
         h = C.c_void_p()
         if isinstance(dims_b, tuple):
             dims_b = Dims(*dims_b)
@@ -190,6 +198,26 @@ class Context:
         best = Best()
         rc = lib().csngf_evaluate(self.h, _ptr(B), _ptr(mask_b), R.ctypes.data if n else None, n, per,
                                   C.byref(best))
+        if rc != OK and not (allow_no_valid and rc == E_NO_VALID_SHIFT):
+            _check(rc)
+        return per[:n], best
+
+    def evaluate_async(self, B, rotations, mask_b=None):
+        """Enqueue an evaluation; keep B alive and call wait() for the results."""
+        B, mask_b = self._b(B, mask_b)
+        R = np.ascontiguousarray(np.asarray(rotations, dtype=np.float64).reshape(-1, 9))
+        self._inflight = (B, mask_b, R)
+        _check(lib().csngf_evaluate_async(self.h, _ptr(B), _ptr(mask_b), R.ctypes.data if len(R) else None, len(R)))
+
+    def done(self):
+        return bool(_check_query(lib().csngf_query(self.h)))
+
+    def wait(self, allow_no_valid=True):
+        n = len(self._inflight[2]) if getattr(self, "_inflight", None) is not None else 0
+        per = (RotResult * max(n, 1))()
+        best = Best()
+        rc = lib().csngf_wait(self.h, per, C.byref(best))
+        self._inflight = None
         if rc != OK and not (allow_no_valid and rc == E_NO_VALID_SHIFT):
             _check(rc)
         return per[:n], best
@@ -238,6 +266,29 @@ class Context:
 
     def __exit__(self, *a):
         self.close()
+
+
+def _check_query(rc):
+    if rc < 0:
+        _check(rc)
+    return rc
+
+
+def autotune(A, B, *, n_probe=64, measure="squared", gamma=0.5, eps=1e-5, graphs=False):
+    """Fastest (pad, batch) for this pair's shapes; returns (dict(pad=..., batch=...), rotations/s)."""
+    dev = _is_device(A)
+    if not dev:
+        A = np.ascontiguousarray(A, dtype=np.float32)
+        B = np.ascontiguousarray(B, dtype=np.float32)
+    p = default_params()
+    p.eps, p.gamma = eps, gamma
+    p.flags = ((DEVICE_PTRS if dev else 0) | (UNSQUARED if measure == "unsquared" else 0)
+               | (GRAPHS if graphs else 0))
+    out = Params()
+    rate = C.c_double()
+    _check(lib().csngf_autotune(_ptr(A), dims_of(A), _ptr(B), dims_of(B), C.byref(p), n_probe, C.byref(out),
+                                C.byref(rate)))
+    return {"pad": tuple(out.pad), "batch": out.batch}, rate.value
 
 
 def debug_fft(x_dev, inverse=False, out=None, stream=None):

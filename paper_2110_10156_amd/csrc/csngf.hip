@@ -2,7 +2,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <random>
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
@@ -196,8 +198,19 @@ struct csngf_ctx {
   int* h_rot = nullptr;
   int h_rot_cap = 0;
   long long workspace_bytes = 0;
+  // asynchronous evaluation in flight
+  bool pending = false;
+  int pend_n = 0;
+  std::vector<int> pend_kq;
+  hipEvent_t done_ev = nullptr;
+  // graph replay of a full batch (CSNGF_GRAPHS)
+  hipGraphExec_t gexec = nullptr;
+  const float* g_B = nullptr;
+  const uint8_t* g_mB = nullptr;
+  int* d_rot_stage = nullptr;
+  RotResultDev* d_res_stage = nullptr;
   bool prof = false;
-  std::vector<PendingEv> pending;
+  std::vector<PendingEv> prof_pending;
   std::vector<hipEvent_t> ev_pool;
   long long stat_launches[KT_COUNT] = {0};
   double stat_ms[KT_COUNT] = {0};
@@ -228,11 +241,11 @@ void prof_end(csngf_ctx* c, int type, hipEvent_t start) {
   hipEvent_t e = nullptr;
   if (ev_get(c, &e) != hipSuccess) return;
   hipEventRecord(e, c->stream);
-  c->pending.push_back({type, start, e});
+  c->prof_pending.push_back({type, start, e});
 }
 
 void prof_fold(csngf_ctx* c) {
-  for (auto& p : c->pending) {
+  for (auto& p : c->prof_pending) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
       c->stat_ms[p.type] += ms;
@@ -241,7 +254,7 @@ void prof_fold(csngf_ctx* c) {
     c->ev_pool.push_back(p.a);
     c->ev_pool.push_back(p.b);
   }
-  c->pending.clear();
+  c->prof_pending.clear();
 }
 
 template <typename T>
@@ -267,9 +280,13 @@ void release(csngf_ctx* c) {
   dfree(c->d_B);
   dfree(c->d_mB);
   dfree(c->d_flag);
+  dfree(c->d_rot_stage);
+  dfree(c->d_res_stage);
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->done_ev) (void)hipEventDestroy(c->done_ev);
   if (c->h_res) hipHostFree(c->h_res);
   if (c->h_rot) hipHostFree(c->h_rot);
-  for (auto& p : c->pending) {
+  for (auto& p : c->prof_pending) {
     hipEventDestroy(p.a);
     hipEventDestroy(p.b);
   }
@@ -443,6 +460,41 @@ int run_batch(csngf_ctx* c, const float* dB, const uint8_t* dmB, const int* rotq
   return CSNGF_OK;
 }
 
+// A full batch through a captured graph: the launch sequence of run_batch is recorded once
+// (reading rotations from, and writing results to, fixed staging slots) and replayed; it is
+// re-recorded when the moving volume's device pointers change.
+int run_graph_batch(csngf_ctx* c, const float* dB, const uint8_t* dmB, int base) {
+  if (!c->gexec || c->g_B != dB || c->g_mB != dmB) {
+    if (c->gexec) {
+      (void)hipGraphExecDestroy(c->gexec);
+      c->gexec = nullptr;
+    }
+    HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    int rc = run_batch(c, dB, dmB, c->d_rot_stage, c->batch, c->d_res_stage, nullptr, nullptr);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->stream, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      c->gexec = nullptr;
+      return hip_fail(e, "hipGraphInstantiate");
+    }
+    c->g_B = dB;
+    c->g_mB = dmB;
+  }
+  HIPCHK(hipMemcpyAsync(c->d_rot_stage, c->d_rot + 9 * (size_t)base, sizeof(int) * 9 * (size_t)c->batch,
+                        hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipGraphLaunch(c->gexec, c->stream));
+  HIPCHK(hipMemcpyAsync(c->d_res + base, c->d_res_stage, sizeof(RotResultDev) * (size_t)c->batch,
+                        hipMemcpyDeviceToDevice, c->stream));
+  return CSNGF_OK;
+}
+
 template <typename T>
 int dalloc(T** p, size_t bytes) {
   *p = nullptr;
@@ -550,7 +602,8 @@ int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims
   if (!(prm.eps > 0.f) || !std::isfinite(prm.eps)) return fail(CSNGF_E_INVALID_ARG, "eps must be finite and > 0");
   if (!(prm.gamma >= 0.f && prm.gamma <= 1.f)) return fail(CSNGF_E_INVALID_ARG, "gamma must lie in [0, 1]");
   if (prm.batch < 0) return fail(CSNGF_E_INVALID_ARG, "batch must be >= 0");
-  if (prm.flags & ~(CSNGF_DEVICE_PTRS | CSNGF_UNSQUARED)) return fail(CSNGF_E_INVALID_ARG, "unknown flag bits");
+  if (prm.flags & ~(CSNGF_DEVICE_PTRS | CSNGF_UNSQUARED | CSNGF_GRAPHS))
+    return fail(CSNGF_E_INVALID_ARG, "unknown flag bits");
   if (maskA) return fail(CSNGF_E_UNSUPPORTED, "a user mask on the fixed volume is not supported (pass NULL)");
   const int nA[3] = {dA.nx, dA.ny, dA.nz}, nB[3] = {dB.nx, dB.ny, dB.nz};
   int P[3];
@@ -687,6 +740,12 @@ int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims
     if ((rc = dalloc(&c->d_sat, 4 * (size_t)c->sat_slot * batch))) return bail(rc);
     if ((rc = dalloc(&c->d_flags, (size_t)c->flag_slot * batch))) return bail(rc);
     if ((rc = dalloc(&c->d_keys, sizeof(unsigned long long) * batch))) return bail(rc);
+    if (prm.flags & CSNGF_GRAPHS) {
+      if ((rc = dalloc(&c->d_rot_stage, sizeof(int) * 9 * (size_t)batch))) return bail(rc);
+      if ((rc = dalloc(&c->d_res_stage, sizeof(RotResultDev) * (size_t)batch))) return bail(rc);
+    }
+    if (hipEventCreateWithFlags(&c->done_ev, hipEventDisableTiming) != hipSuccess)
+      return bail(hip_fail(hipGetLastError(), "hipEventCreate"));
     c->workspace_bytes = per * batch;
   }
   *out = c;
@@ -713,47 +772,67 @@ int csngf_get_info(const csngf_ctx* c, csngf_info* o) {
   return CSNGF_OK;
 }
 
-int csngf_evaluate(csngf_ctx* c, const float* B, const uint8_t* maskB, const double* R, int32_t n,
-                   csngf_rot_result* per_rot, csngf_best* best) {
+int csngf_evaluate_async(csngf_ctx* c, const float* B, const uint8_t* maskB, const double* R, int32_t n) {
   if (!c) return fail(CSNGF_E_INVALID_ARG, "ctx is NULL");
+  if (c->pending) return fail(CSNGF_E_INVALID_ARG, "an evaluation is already in flight on this context");
   if (!B) return fail(CSNGF_E_INVALID_ARG, "moving volume B is NULL");
   if (n < 0) return fail(CSNGF_E_INVALID_ARG, "n must be >= 0");
   if (n > 0 && !R) return fail(CSNGF_E_INVALID_ARG, "rotations are NULL");
-  if (n == 0) {
-    if (best) {
-      std::memset(best, 0, sizeof(*best));
-      best->score = -INFINITY;
-      best->rot_index = -1;
-    }
-    return CSNGF_OK;
-  }
   std::vector<int> kq((size_t)n * 9);
   for (int r = 0; r < n; ++r)
     if (quantise(R + 9 * (size_t)r, &kq[9 * (size_t)r], nullptr))
       return fail(CSNGF_E_INVALID_ARG, "rotation " + std::to_string(r) + " has a non-finite entry or |R_ij| > 2");
   HIPCHK(hipSetDevice(c->dev));
-  int rc = ensure_rot_capacity(c, n);
-  if (rc) return rc;
-  const float* dB = nullptr;
-  const uint8_t* dmB = nullptr;
-  if ((rc = stage_moving(c, B, maskB, &dB, &dmB))) return rc;
-  std::memcpy(c->h_rot, kq.data(), sizeof(int) * 9 * (size_t)n);
-  HIPCHK(hipMemcpyAsync(c->d_rot, c->h_rot, sizeof(int) * 9 * (size_t)n, hipMemcpyHostToDevice, c->stream));
-  for (int base = 0; base < n; base += c->batch) {
-    const int m = std::min(c->batch, n - base);
-    if ((rc = run_batch(c, dB, dmB, c->d_rot + 9 * (size_t)base, m, c->d_res + base, nullptr, nullptr))) return rc;
+  int rc;
+  if (n > 0) {
+    if ((rc = ensure_rot_capacity(c, n))) return rc;
+    const float* dB = nullptr;
+    const uint8_t* dmB = nullptr;
+    if ((rc = stage_moving(c, B, maskB, &dB, &dmB))) return rc;
+    std::memcpy(c->h_rot, kq.data(), sizeof(int) * 9 * (size_t)n);
+    HIPCHK(hipMemcpyAsync(c->d_rot, c->h_rot, sizeof(int) * 9 * (size_t)n, hipMemcpyHostToDevice, c->stream));
+    const bool graphs = (c->flags & CSNGF_GRAPHS) && !c->prof;
+    for (int base = 0; base < n; base += c->batch) {
+      const int m = std::min(c->batch, n - base);
+      if (graphs && m == c->batch)
+        rc = run_graph_batch(c, dB, dmB, base);
+      else
+        rc = run_batch(c, dB, dmB, c->d_rot + 9 * (size_t)base, m, c->d_res + base, nullptr, nullptr);
+      if (rc) return rc;
+    }
+    HIPCHK(hipMemcpyAsync(c->h_res, c->d_res, sizeof(RotResultDev) * (size_t)n, hipMemcpyDeviceToHost, c->stream));
   }
-  HIPCHK(hipMemcpyAsync(c->h_res, c->d_res, sizeof(RotResultDev) * (size_t)n, hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(hipStreamSynchronize(c->stream));
-  int bad = 0;
-  if ((rc = read_flag(c, &bad))) return rc;
+  HIPCHK(hipEventRecord(c->done_ev, c->stream));
+  c->pending = true;
+  c->pend_n = n;
+  c->pend_kq.swap(kq);
+  return CSNGF_OK;
+}
+
+int csngf_query(csngf_ctx* c) {
+  if (!c) return fail(CSNGF_E_INVALID_ARG, "ctx is NULL");
+  if (!c->pending) return 1;
+  const hipError_t e = hipEventQuery(c->done_ev);
+  if (e == hipSuccess) return 1;
+  if (e == hipErrorNotReady) return 0;
+  return hip_fail(e, "hipEventQuery");
+}
+
+int csngf_wait(csngf_ctx* c, csngf_rot_result* per_rot, csngf_best* best) {
+  if (!c) return fail(CSNGF_E_INVALID_ARG, "ctx is NULL");
+  if (!c->pending) return fail(CSNGF_E_INVALID_ARG, "no evaluation in flight on this context");
+  c->pending = false;
+  HIPCHK(hipEventSynchronize(c->done_ev));
+  const int n = c->pend_n;
+  int rc, bad = 0;
+  if (n > 0 && (rc = read_flag(c, &bad))) return rc;
   if (bad) return fail(CSNGF_E_INVALID_ARG, "moving volume B has a non-finite value");
   int bi = -1;
   for (int r = 0; r < n; ++r) {
     const RotResultDev& x = c->h_res[r];
     if (x.valid && (bi < 0 || x.score > c->h_res[bi].score)) bi = r;
   }
-  if (per_rot) std::memcpy(per_rot, c->h_res, sizeof(csngf_rot_result) * (size_t)n);
+  if (per_rot && n > 0) std::memcpy(per_rot, c->h_res, sizeof(csngf_rot_result) * (size_t)n);
   if (best) {
     std::memset(best, 0, sizeof(*best));
     best->rot_index = bi;
@@ -764,16 +843,25 @@ int csngf_evaluate(csngf_ctx* c, const float* B, const uint8_t* maskB, const dou
       best->score = x.score;
       for (int i = 0; i < 3; ++i) best->shift[i] = x.shift[i];
       best->overlap = x.overlap;
-      for (int i = 0; i < 9; ++i) best->R[i] = kq[9 * (size_t)bi + i] / 65536.0;
+      for (int i = 0; i < 9; ++i) best->R[i] = c->pend_kq[9 * (size_t)bi + i] / 65536.0;
     }
   }
-  if (bi < 0) return fail(CSNGF_E_NO_VALID_SHIFT, "no displacement meets the minimum overlap for any rotation");
+  if (bi < 0 && n > 0)
+    return fail(CSNGF_E_NO_VALID_SHIFT, "no displacement meets the minimum overlap for any rotation");
   return CSNGF_OK;
+}
+
+int csngf_evaluate(csngf_ctx* c, const float* B, const uint8_t* maskB, const double* R, int32_t n,
+                   csngf_rot_result* per_rot, csngf_best* best) {
+  int rc = csngf_evaluate_async(c, B, maskB, R, n);
+  if (rc) return rc;
+  return csngf_wait(c, per_rot, best);
 }
 
 int csngf_evaluate_map(csngf_ctx* c, const float* B, const uint8_t* maskB, const double* R9, float* C,
                        int64_t* N) {
   if (!c) return fail(CSNGF_E_INVALID_ARG, "ctx is NULL");
+  if (c->pending) return fail(CSNGF_E_INVALID_ARG, "an evaluation is in flight on this context");
   if (!B || !R9 || !C) return fail(CSNGF_E_INVALID_ARG, "NULL argument");
   int kq[9];
   if (quantise(R9, kq, nullptr)) return fail(CSNGF_E_INVALID_ARG, "rotation has a non-finite entry or |R_ij| > 2");
@@ -900,6 +988,99 @@ int csngf_smooth_downsample(const float* vol, csngf_dims d, float sigma, int32_t
       return done(hip_fail(hipGetLastError(), "download"));
   }
   return done(CSNGF_OK);
+}
+
+// ---------------------------------------------------------------------------- autotuner
+namespace {
+bool fast_length(int L) {
+  for (int f : kFastLengths)
+    if (f == L) return true;
+  return false;
+}
+
+// Deterministic probe rotations: normalised Gaussian quaternions from a fixed seed.
+std::vector<double> probe_rotations(int n) {
+  std::mt19937 gen(20211019u);
+  std::normal_distribution<double> nd(0.0, 1.0);
+  std::vector<double> R((size_t)n * 9);
+  for (int i = 0; i < n; ++i) {
+    double w = nd(gen), x = nd(gen), y = nd(gen), z = nd(gen);
+    const double s = 1.0 / std::sqrt(w * w + x * x + y * y + z * z);
+    w *= s; x *= s; y *= s; z *= s;
+    double* r = &R[9 * (size_t)i];
+    r[0] = 1 - 2 * (y * y + z * z); r[1] = 2 * (x * y - w * z);     r[2] = 2 * (x * z + w * y);
+    r[3] = 2 * (x * y + w * z);     r[4] = 1 - 2 * (x * x + z * z); r[5] = 2 * (y * z - w * x);
+    r[6] = 2 * (x * z - w * y);     r[7] = 2 * (y * z + w * x);     r[8] = 1 - 2 * (x * x + y * y);
+  }
+  return R;
+}
+}  // namespace
+
+extern "C" int csngf_autotune(const float* A, csngf_dims dA, const float* B, csngf_dims dB, const csngf_params* base,
+                              int32_t n_probe, csngf_params* best, double* best_rate) {
+  if (!A || !B || !best) return fail(CSNGF_E_INVALID_ARG, "NULL argument");
+  if (n_probe < 1) return fail(CSNGF_E_INVALID_ARG, "n_probe must be >= 1");
+  csngf_params prm;
+  csngf_default_params(&prm);
+  if (base) {
+    if (base->struct_size != sizeof(csngf_params)) return fail(CSNGF_E_INVALID_ARG, "params.struct_size mismatch");
+    prm = *base;
+  }
+  const int nA[3] = {dA.nx, dA.ny, dA.nz}, nB[3] = {dB.nx, dB.ny, dB.nz};
+  std::vector<int> cand[3];
+  for (int i = 0; i < 3; ++i) {
+    const int need = nA[i] + nB[i] - 1;
+    const int s0 = smallest_supported_at_least(need);
+    if (s0 < 0) return fail(CSNGF_E_UNSUPPORTED, "no supported FFT size >= n_A + n_B - 1");
+    cand[i].push_back(s0);
+    for (int L = s0 + 1; L <= kMaxLen && L <= need + need / 2; ++L)
+      if (fast_length(L) && !fast_length(s0)) {
+        cand[i].push_back(L);
+        break;
+      }
+  }
+  const std::vector<double> R = probe_rotations(n_probe);
+  std::vector<csngf_rot_result> per((size_t)n_probe);
+  double best_r = -1.0;
+  csngf_params best_p = prm;
+  auto probe = [&](csngf_params q, int* used_batch) -> double {
+    csngf_ctx* ctx = nullptr;
+    if (csngf_create(A, dA, nullptr, dB, &q, &ctx) != CSNGF_OK) return -1.0;
+    *used_batch = ctx->batch;
+    double rate = -1.0;
+    int rc = csngf_evaluate(ctx, B, nullptr, R.data(), n_probe, per.data(), nullptr);
+    if (rc == CSNGF_OK || rc == CSNGF_E_NO_VALID_SHIFT) {
+      const auto t0 = std::chrono::steady_clock::now();
+      rc = csngf_evaluate(ctx, B, nullptr, R.data(), n_probe, per.data(), nullptr);
+      const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      if (rc == CSNGF_OK || rc == CSNGF_E_NO_VALID_SHIFT) rate = n_probe / dt;
+    }
+    csngf_destroy(ctx);
+    return rate;
+  };
+  for (int px : cand[0])
+    for (int py : cand[1])
+      for (int pz : cand[2]) {
+        csngf_params q = prm;
+        q.pad[0] = px;
+        q.pad[1] = py;
+        q.pad[2] = pz;
+        q.batch = 0;
+        int b0 = 0;
+        const double r0 = probe(q, &b0);
+        if (r0 > best_r) { best_r = r0; best_p = q; best_p.batch = b0; }
+        for (int b : {b0 / 2, b0 * 2}) {
+          if (b < 1 || b > 64 || b == b0) continue;
+          q.batch = b;
+          int bu = 0;
+          const double r = probe(q, &bu);
+          if (r > best_r) { best_r = r; best_p = q; }
+        }
+      }
+  if (best_r <= 0) return fail(CSNGF_E_DEVICE, "no candidate configuration could be evaluated");
+  *best = best_p;
+  if (best_rate) *best_rate = best_r;
+  return CSNGF_OK;
 }
 
 // ---------------------------------------------------------------------------- debug / profile

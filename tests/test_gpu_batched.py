@@ -1,0 +1,70 @@
+"""Many pairs in flight, graph replay and the autotuner: same results as the plain path."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2110_10156_amd import binding as bd
+from paper_2110_10156_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _same(pa, pb):
+    for a, b in zip(pa, pb):
+        assert a.valid == b.valid and a.score == b.score and tuple(a.shift) == tuple(b.shift)
+        assert a.overlap == b.overlap
+
+
+def test_graph_replay_equals_eager_across_calls_and_pointer_changes():
+    import torch
+    pair = synth.config1(n_random=40)
+    dev = torch.device("cuda:0")
+    A = torch.from_numpy(pair.A).to(dev)
+    B1 = torch.from_numpy(pair.B).to(dev)
+    B2 = B1.clone()
+    with bd.Context(A, pair.dims_b, batch=7) as eager, bd.Context(A, pair.dims_b, batch=7, graphs=True) as graph:
+        ref, rb = eager.evaluate(B1, pair.rotations)
+        for i, B in enumerate((B1, B1, B2, B1)):
+            _say("graph replay", i)
+            got, gb = graph.evaluate(B, pair.rotations)     # 5 full batches replayed + 1 eager tail
+            _same(ref, got)
+            assert gb.rot_index == rb.rot_index
+            mid, _ = eager.evaluate(B2, pair.rotations[:9])  # eager work between replays
+            torch.cuda.synchronize()
+            _same(ref[:9], mid)
+
+
+def test_concurrent_contexts_equal_sequential():
+    pairs = [synth.cube_pair(s, n_random=12) for s in (16, 24, 40)] + [synth.config0()]
+    ctxs = [bd.Context(p.A, p.dims_b, graphs=(i % 2 == 0)) for i, p in enumerate(pairs)]
+    rots = [np.concatenate([p.rotations, synth.random_rotations(9, 70 + i)]) for i, p in enumerate(pairs)]
+    seq = [c.evaluate(p.B, r) for c, p, r in zip(ctxs, pairs, rots)]
+    for c, p, r in zip(ctxs, pairs, rots):
+        c.evaluate_async(p.B, r)
+    conc = [c.wait() for c in ctxs]
+    for (ps, bs), (pc, bc) in zip(seq, conc):
+        _same(ps, pc)
+        assert bs.rot_index == bc.rot_index
+    with pytest.raises(bd.CsngfError):
+        ctxs[0].wait()          # nothing in flight
+    for c in ctxs:
+        c.close()
+
+
+def test_autotune_returns_an_equivalent_configuration():
+    pair = synth.cube_pair(48, n_random=6)
+    cfg, rate = bd.autotune(pair.A, pair.B, n_probe=48)
+    _say("autotune 48^3", cfg, round(rate, 1))
+    assert rate > 0 and cfg["batch"] >= 1 and all(p >= 95 for p in cfg["pad"])
+    with bd.Context(pair.A, pair.dims_b) as c0, bd.Context(pair.A, pair.dims_b, **cfg) as c1:
+        p0, b0 = c0.evaluate(pair.B, pair.rotations)
+        p1, b1 = c1.evaluate(pair.B, pair.rotations)
+    assert b0.rot_index == b1.rot_index and tuple(b0.shift) == tuple(b1.shift)
+    for a, b in zip(p0, p1):
+        assert abs(a.score - b.score) <= 1e-4 and a.overlap == b.overlap

@@ -98,6 +98,65 @@ def cpu_baseline(pair, n_rot):
                       f"(FP64 numpy/scipy, {dt:.1f} s; FFTs on {O.WORKERS} threads, the rest single-threaded)"}
 
 
+def many_pairs(torch, bd, synth, big_pair, n_pairs, n_rot, budget_gib=160.0):
+    """Uneven-size batch: n_pairs pairs with sizes drawn uniformly from synth.MIXED_SHAPES
+    (seed 3000 + i), n_rot random rotations each.  One phantom pair per distinct size stands
+    in for every pair of that size (throughput depends on sizes only).
+    Sequential: pair after pair, one synchronous evaluation each, default parameters (the
+    evaluation calls are timed, context creation is not).
+    Concurrent: all contexts alive, each on its own stream, every evaluation in flight at
+    once, graph replay, autotuned (P, slots) with slots capped to an equal share of
+    budget_gib of HBM per context."""
+    dev = torch.device("cuda:0")
+    sizes = [synth.MIXED_SHAPES[int(np.random.default_rng(3000 + i).integers(0, len(synth.MIXED_SHAPES)))]
+             for i in range(n_pairs)]
+    vols = {}
+    for sz in sorted(set(sizes)):
+        p = big_pair if sz == big_pair.dims_a else synth.mixed_pair_of_size(sz)
+        vols[sz] = (torch.from_numpy(p.A).to(dev), torch.from_numpy(p.B).to(dev))
+    rots = [synth.random_rotations(n_rot, 5000 + i) for i in range(n_pairs)]
+    tuned, share = {}, budget_gib * 2**30 / n_pairs
+    for sz in sorted(set(sizes)):
+        A, B = vols[sz]
+        cfg, _ = bd.autotune(A, B, n_probe=64, graphs=True)
+        with bd.Context(A, bd.dims_of(B), pad=cfg["pad"], batch=1) as c1:
+            per_slot = c1.info().workspace_bytes
+        cfg["batch"] = int(max(1, min(cfg["batch"], share // per_slot)))
+        tuned[sz] = cfg
+    torch.cuda.synchronize()
+    out = {"pairs": n_pairs, "rotations_per_pair": n_rot,
+           "sizes": {f"{s[0]}x{s[1]}x{s[2]}": sizes.count(s) for s in sorted(set(sizes))},
+           "concurrent_params": {f"{s[0]}x{s[1]}x{s[2]}": tuned[s] for s in sorted(set(sizes))}}
+    # sequential
+    total = 0.0
+    for sz, r in zip(sizes, rots):
+        A, B = vols[sz]
+        with bd.Context(A, bd.dims_of(B)) as c:
+            c.evaluate(B, r[:8])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            c.evaluate(B, r)
+            total += time.perf_counter() - t0
+    out["sequential_rotations_per_s"] = round(n_pairs * n_rot / total, 1)
+    print(f"[bench] many pairs sequential: {n_pairs * n_rot / total:.1f} rot/s", file=sys.stderr, flush=True)
+    # concurrent
+    ctxs = [bd.Context(vols[sz][0], bd.dims_of(vols[sz][1]), graphs=True, **tuned[sz]) for sz in sizes]
+    for c, sz, r in zip(ctxs, sizes, rots):            # warm-up: graph recording, first launches
+        c.evaluate(vols[sz][1], r[:c.info().batch])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c, sz, r in zip(ctxs, sizes, rots):
+        c.evaluate_async(vols[sz][1], r)
+    for c in ctxs:
+        c.wait()
+    dt = time.perf_counter() - t0
+    for c in ctxs:
+        c.close()
+    out["concurrent_rotations_per_s"] = round(n_pairs * n_rot / dt, 1)
+    print(f"[bench] many pairs concurrent: {n_pairs * n_rot / dt:.1f} rot/s", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +171,9 @@ def main():
                     help="rotations timed with the unsquared measure, Eq. (3) (0 = skip)")
     ap.add_argument("--align-runs", type=int, default=5,
                     help="full global alignments (paper schedule) timed for p50/p99 latency (0 = skip)")
+    ap.add_argument("--batched-pairs", type=int, default=32,
+                    help="uneven volume pairs (48^3 .. 176x176x110) for the many-pairs measurement (0 = skip)")
+    ap.add_argument("--batched-rotations", type=int, default=256, help="rotations per pair in that measurement")
     ap.add_argument("--no-profile", action="store_true", help="do not record per-kernel events")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
@@ -237,6 +299,10 @@ def main():
                        "what": "global rigid alignment of the 176x176x110 pair with the paper's pyramid schedule "
                                "(host to host, seeds 0..runs-1)"}
 
+    batched = None
+    if args.batched_pairs > 0:
+        batched = many_pairs(torch, bd, synth, pair, args.batched_pairs, args.batched_rotations)
+
     cpu = None
     if args.cpu_rotations > 0:
         cpu = cpu_baseline(pair, args.cpu_rotations)
@@ -261,6 +327,7 @@ def main():
                                f"{len(rots)} random rotations per step, FFT 352x352x220, full displacement map",
                    "rotations_per_step": len(rots), "fft_size": list(info.pad), "slots": slots},
         "alignment_latency": align_stats,
+        "many_pairs": batched,
         "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 3),
                        "p99": round(float(np.percentile(lat_ms, 99)), 3),
                        "what": f"one csngf_evaluate call of {len(rots)} rotations, host to host"},

@@ -30,7 +30,7 @@ import numpy as np
 __all__ = [
     "quat_to_matrix", "axis_angle_matrix", "euler_xyz_matrix", "random_rotations",
     "intensity_map_f", "VolumePair", "config0", "config1", "config2", "cube_pair",
-    "mixed_pair", "MIXED_SHAPES",
+    "mixed_pair", "mixed_pair_of_size", "MIXED_SHAPES",
 ]
 
 
@@ -286,6 +286,13 @@ def mixed_pair(i: int, n_random: int = 256) -> VolumePair:
     n_xyz = MIXED_SHAPES[int(rng.integers(0, len(MIXED_SHAPES)))]
     pad = tuple(2 * v for v in n_xyz)
     return _shell_pair(f"mixed{i}", rng, n_xyz, n_random, 3100 + i, pad)
+
+
+def mixed_pair_of_size(n_xyz, seed: int = 3999, n_random: int = 0) -> VolumePair:
+    """A pair of the given size built as config2 (4-class shell phantom, permuted, smoothed, noisy)."""
+    rng = np.random.default_rng(seed)
+    return _shell_pair(f"mixed{n_xyz[0]}x{n_xyz[1]}x{n_xyz[2]}", rng, tuple(n_xyz), n_random, seed + 1,
+                       tuple(2 * v for v in n_xyz))
 
 
 def cube_pair(side: int, seed: int = 7, n_random: int = 4) -> VolumePair:

@@ -157,6 +157,37 @@ def many_pairs(torch, bd, synth, big_pair, n_pairs, n_rot, budget_gib=160.0):
     return out
 
 
+def serving(torch, bd, synth, big_pair, rates, n_req, n_rot, budget_gib=96.0):
+    """Poisson request streams: each request pairs a fixed volume of a size drawn uniformly
+    from synth.MIXED_SHAPES with its moving volume and n_rot random rotations.  One phantom
+    pair per size stands in for every request of that size, so the spectra cache is keyed by
+    size.  Latency is finish - arrival on the server clock."""
+    from paper_2110_10156_amd import serve
+    dev = torch.device("cuda:0")
+    vols = {}
+    for sz in synth.MIXED_SHAPES:
+        p = big_pair if sz == big_pair.dims_a else synth.mixed_pair_of_size(sz)
+        vols[sz] = (torch.from_numpy(p.A).to(dev), torch.from_numpy(p.B).to(dev))
+    out = {"requests_per_rate": n_req, "rotations_per_request": n_rot, "hbm_budget_gib": budget_gib}
+    srv = serve.Server(hbm_budget=int(budget_gib * 2**30))
+    warm = [serve.Request(-1 - i, str(sz), *vols[sz], synth.random_rotations(8, 77)) for i, sz in
+            enumerate(synth.MIXED_SHAPES)]
+    serve.run_stream(srv, lambda i: warm[i], np.zeros(len(warm)))
+    for rate in rates:
+        rng = np.random.default_rng(int(rate * 100))
+        sizes = [synth.MIXED_SHAPES[int(rng.integers(0, len(synth.MIXED_SHAPES)))] for _ in range(n_req)]
+        rots = [synth.random_rotations(n_rot, 7000 + i) for i in range(n_req)]
+        arr = serve.poisson_arrivals(rate, n_req, seed=int(rate * 10))
+        res = serve.run_stream(srv, lambda i: serve.Request(i, str(sizes[i]), *vols[sizes[i]], rots[i]), arr)
+        summ = serve.summarize(res, n_rot)
+        out[f"{rate:g}_req_per_s"] = summ
+        print(f"[bench] serving {rate:g} req/s: {summ}", file=sys.stderr, flush=True)
+    out["contexts_created"] = srv.stats.created
+    out["peak_in_flight"] = srv.stats.peak_inflight
+    srv.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -174,6 +205,10 @@ def main():
     ap.add_argument("--batched-pairs", type=int, default=32,
                     help="uneven volume pairs (48^3 .. 176x176x110) for the many-pairs measurement (0 = skip)")
     ap.add_argument("--batched-rotations", type=int, default=256, help="rotations per pair in that measurement")
+    ap.add_argument("--serve-rates", default="5,10,20",
+                    help="Poisson arrival rates (requests/s) for the serving measurement ('' = skip)")
+    ap.add_argument("--serve-requests", type=int, default=40, help="requests per rate")
+    ap.add_argument("--serve-rotations", type=int, default=200, help="rotations per request")
     ap.add_argument("--no-profile", action="store_true", help="do not record per-kernel events")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
@@ -303,6 +338,11 @@ def main():
     if args.batched_pairs > 0:
         batched = many_pairs(torch, bd, synth, pair, args.batched_pairs, args.batched_rotations)
 
+    served = None
+    if args.serve_rates:
+        served = serving(torch, bd, synth, pair, [float(r) for r in args.serve_rates.split(",")],
+                         args.serve_requests, args.serve_rotations)
+
     cpu = None
     if args.cpu_rotations > 0:
         cpu = cpu_baseline(pair, args.cpu_rotations)
@@ -328,6 +368,7 @@ def main():
                    "rotations_per_step": len(rots), "fft_size": list(info.pad), "slots": slots},
         "alignment_latency": align_stats,
         "many_pairs": batched,
+        "serving": served,
         "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 3),
                        "p99": round(float(np.percentile(lat_ms, 99)), 3),
                        "what": f"one csngf_evaluate call of {len(rots)} rotations, host to host"},

@@ -168,6 +168,13 @@ int csngf_destroy(csngf_ctx* ctx);
 int csngf_smooth_downsample(const float* vol, csngf_dims d, float sigma, int32_t factor, float* out,
                             csngf_dims* out_dims, uint32_t flags, void* stream);
 
+/* Device memory a context would hold, without allocating anything (admission control of a
+ * server): *spectra_bytes for A's resident spectra, *slot_bytes per rotation slot of
+ * workspace (a context holds batch slots), and the FFT size pad_out[3] that would be used.
+ * Any output may be NULL. */
+int csngf_footprint(csngf_dims dA, csngf_dims dB, const csngf_params* p, int64_t* spectra_bytes,
+                    int64_t* slot_bytes, int32_t* pad_out);
+
 /* Autotuner: for the shapes of A and B and the base params (eps, gamma, flags), time the
  * candidate configurations - FFT size per axis (the smallest supported length and, if that
  * has no compile-time plan, the smallest one that has, within 1.5x) and rotation slots in

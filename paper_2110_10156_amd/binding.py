@@ -73,6 +73,8 @@ SIGNATURES = {
     "csngf_wait": (C.c_int, [C.c_void_p, C.POINTER(RotResult), C.POINTER(Best)]),
     "csngf_autotune": (C.c_int, [C.c_void_p, Dims, C.c_void_p, Dims, C.POINTER(Params), C.c_int32,
                                  C.POINTER(Params), C.POINTER(C.c_double)]),
+    "csngf_footprint": (C.c_int, [Dims, Dims, C.POINTER(Params), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                  C.POINTER(C.c_int32)]),
     "csngf_destroy": (C.c_int, [C.c_void_p]),
     "csngf_last_error": (C.c_char_p, []),
     "csngf_debug_fft": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p]),
@@ -289,6 +291,19 @@ def autotune(A, B, *, n_probe=64, measure="squared", gamma=0.5, eps=1e-5, graphs
     _check(lib().csngf_autotune(_ptr(A), dims_of(A), _ptr(B), dims_of(B), C.byref(p), n_probe, C.byref(out),
                                 C.byref(rate)))
     return {"pad": tuple(out.pad), "batch": out.batch}, rate.value
+
+
+def footprint(dims_a, dims_b, *, pad=(0, 0, 0), measure="squared"):
+    """(spectra bytes, workspace bytes per rotation slot, FFT size) of a context, without allocating."""
+    p = default_params()
+    p.pad[:] = list(pad)
+    p.flags = UNSQUARED if measure == "unsquared" else 0
+    sb, wb = C.c_int64(), C.c_int64()
+    P = (C.c_int32 * 3)()
+    da = dims_a if isinstance(dims_a, Dims) else Dims(*dims_a)
+    db = dims_b if isinstance(dims_b, Dims) else Dims(*dims_b)
+    _check(lib().csngf_footprint(da, db, C.byref(p), C.byref(sb), C.byref(wb), P))
+    return sb.value, wb.value, tuple(P)
 
 
 def debug_fft(x_dev, inverse=False, out=None, stream=None):

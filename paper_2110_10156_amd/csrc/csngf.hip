@@ -990,6 +990,41 @@ int csngf_smooth_downsample(const float* vol, csngf_dims d, float sigma, int32_t
   return done(CSNGF_OK);
 }
 
+// ---------------------------------------------------------------------------- footprint
+extern "C" int csngf_footprint(csngf_dims dA, csngf_dims dB, const csngf_params* p, int64_t* spectra_bytes,
+                               int64_t* slot_bytes, int32_t* pad_out) {
+  csngf_params prm;
+  csngf_default_params(&prm);
+  if (p) {
+    if (p->struct_size != sizeof(csngf_params)) return fail(CSNGF_E_INVALID_ARG, "params.struct_size mismatch");
+    prm = *p;
+  }
+  int rc = check_dims(dA, "A");
+  if (rc) return rc;
+  if ((rc = check_dims(dB, "B"))) return rc;
+  const int nA[3] = {dA.nx, dA.ny, dA.nz}, nB[3] = {dB.nx, dB.ny, dB.nz};
+  int P[3], Wd[3];
+  for (int i = 0; i < 3; ++i) {
+    const int need = nA[i] + nB[i] - 1;
+    P[i] = prm.pad[i] ? prm.pad[i] : smallest_supported_at_least(need);
+    if (P[i] < need || !supported(P[i])) return fail(CSNGF_E_UNSUPPORTED, "FFT size not available");
+    Wd[i] = need;
+  }
+  const int nf = (prm.flags & CSNGF_UNSQUARED) ? 3 : 6;
+  const long long H = P[0] / 2 + 1, Hp = (H + kTileW - 1) / kTileW * kTileW;
+  const long long nvB = (long long)nB[0] * nB[1] * nB[2];
+  const long long buf1 = std::max((long long)nf * nB[2] * nB[1], (long long)Wd[2] * P[1]) * Hp;
+  const long long buf2 = std::max((long long)nf * nB[2] * P[1], (long long)Wd[2] * Wd[1]) * Hp;
+  const long long per = (long long)sizeof(float2) * (buf1 + buf2) + (nvB + 255) / 256 * 256 +
+                        4 * (((long long)(nB[0] + 1) * (nB[1] + 1) * (nB[2] + 1) + 63) / 64 * 64) +
+                        ((long long)Wd[2] * (1 + Wd[1]) + 255) / 256 * 256;
+  if (spectra_bytes) *spectra_bytes = (long long)sizeof(float2) * nf * P[2] * P[1] * Hp;
+  if (slot_bytes) *slot_bytes = per;
+  if (pad_out)
+    for (int i = 0; i < 3; ++i) pad_out[i] = P[i];
+  return CSNGF_OK;
+}
+
 // ---------------------------------------------------------------------------- autotuner
 namespace {
 bool fast_length(int L) {

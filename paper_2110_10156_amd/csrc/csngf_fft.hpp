@@ -194,6 +194,22 @@ __device__ __forceinline__ void fft_stage(float2* __restrict__ buf, const float2
 }
 
 // ---------------------------------------------------------------- compile-time plans
+// floor(j / D) for 0 <= j < MAXJ with one full-rate 24-bit multiply and a shift instead of
+// the quarter-rate 32-bit multiplies of a general division: with M = ceil(2^S / D) and
+// e = M D - 2^S < D, j M / 2^S = j / D + j e / (D 2^S), and j e < 2^S keeps the floor exact.
+template <unsigned D, unsigned MAXJ>
+__device__ __forceinline__ unsigned div_small(unsigned j) {
+  if constexpr ((D & (D - 1)) == 0) {
+    return j / D;
+  } else {
+    constexpr unsigned S = 20;
+    constexpr unsigned long long M = ((1ull << S) + D - 1) / D;
+    static_assert((unsigned long long)(MAXJ - 1) * (M * D - (1ull << S)) < (1ull << S), "inexact");
+    static_assert(M < (1u << 24) && (unsigned long long)(MAXJ - 1) * M < (1ull << 32), "24-bit range");
+    return __umul24(j, (unsigned)M) >> S;
+  }
+}
+
 struct CPlan {
   int nst;
   int r[kMaxStages];
@@ -226,9 +242,9 @@ __device__ __forceinline__ void fft_stage_fixed(float2* __restrict__ buf, const 
   float2 v[NB][R];
 #pragma unroll
   for (int u = 0; u < NB; ++u) {
-    const int bf = (int)threadIdx.x + u * T;
+    const unsigned bf = threadIdx.x + u * T;
     if (NBF % T == 0 || bf < NBF) {
-      const int p = bf % W, j = bf / W;
+      const unsigned p = bf % W, j = bf / W;
 #pragma unroll
       for (int t = 0; t < R; ++t) v[u][t] = buf[(j + t * LR) * W + p];
     }
@@ -236,10 +252,10 @@ __device__ __forceinline__ void fft_stage_fixed(float2* __restrict__ buf, const 
   __syncthreads();
 #pragma unroll
   for (int u = 0; u < NB; ++u) {
-    const int bf = (int)threadIdx.x + u * T;
+    const unsigned bf = threadIdx.x + u * T;
     if (NBF % T == 0 || bf < NBF) {
-      const int p = bf % W, j = bf / W;
-      const int k = j % NS, q = j / NS;
+      const unsigned p = bf % W, j = bf / W;
+      const unsigned q = div_small<NS, LR>(j), k = j - q * NS;
       if constexpr (NS > 1) {
 #pragma unroll
         for (int t = 1; t < R; ++t) {
@@ -294,30 +310,33 @@ __device__ void fft_lds(float2* __restrict__ buf, const float2* __restrict__ tw,
 // ---------------------------------------------------------------- transform with fused I/O
 // Fixed-length transform of W pencils whose first stage takes its inputs from a producer
 // and whose last stage hands its outputs to a consumer, so that neither passes through LDS:
-//   ld(i, p)            -> float2   input element i of pencil p           (IN_LDS = false)
-//   st(k, p, v, slot)              output element k of pencil p; slot is a compile-time
+//   ld(i0, i1, p)       -> float2   input element i0 + i1 of pencil p     (IN_LDS = false)
+//   st(k0, k1, p, v, slot)         output element k0 + k1 of pencil p; slot is a compile-time
 //                                  index (butterfly * R + t) unique per thread (OUT_LDS = false)
+// The element index comes in two parts: i0 / k0 is the same for all R elements of a
+// butterfly and i1 / k1 is a compile-time multiple of the stage stride, so a producer or
+// consumer can form the per-butterfly part of an address once and add a uniform constant.
 // With IN_LDS the first stage reads buf in natural order instead; with OUT_LDS the last
 // stage writes buf in natural order instead.  buf must not be in use by other threads on
 // entry (caller synchronises).  On return the group is NOT synchronised after the last
 // stage; callers reusing buf (or reading it with OUT_LDS) must __syncthreads() first.
 // The thread index behind an empty asm: index arithmetic derived from it cannot be hoisted
 // out of callers' loops (which would keep dozens of addresses live across them).
-__device__ __forceinline__ int opaque_tid() {
-  int t = (int)threadIdx.x;
+__device__ __forceinline__ unsigned opaque_tid() {
+  unsigned t = threadIdx.x;
   asm volatile("" : "+v"(t));
   return t;
 }
 
 template <int L, int R, int NS, int W, int WS, int WSO, int T, bool INV, bool FROM_LD, bool TO_ST, typename LD, typename ST>
 __device__ __forceinline__ void fft_stage_io(float2* __restrict__ buf, const float2* __restrict__ tw, LD& ld, ST& st) {
-  const int tx = opaque_tid();
+  const unsigned tx = opaque_tid();
   constexpr int LR = L / R;
   constexpr int NBF = LR * W;
   constexpr int NB = (NBF + T - 1) / T;
   constexpr int TWSTEP = L / (NS * R);
-  auto finish = [&](float2* v, int p, int j, int u) {
-    const int k = j % NS, q = j / NS;
+  auto finish = [&](float2* v, unsigned p, unsigned j, int u) {
+    const unsigned q = div_small<NS, LR>(j), k = j - q * NS;
     if constexpr (NS > 1) {
 #pragma unroll
       for (int t = 1; t < R; ++t) {
@@ -327,10 +346,10 @@ __device__ __forceinline__ void fft_stage_io(float2* __restrict__ buf, const flo
       }
     }
     dft<R, INV>(v);
-    const int base = q * NS * R + k;
+    const unsigned base = q * NS * R + k;
 #pragma unroll
     for (int t = 0; t < R; ++t) {
-      if constexpr (TO_ST) st(base + t * NS, p, v[t], u * R + t);
+      if constexpr (TO_ST) st(base, t * NS, p, v[t], u * R + t);
       else buf[(base + t * NS) * WSO + p] = v[t];
     }
   };
@@ -339,12 +358,12 @@ __device__ __forceinline__ void fft_stage_io(float2* __restrict__ buf, const flo
     // butterfly at a time keeps only R values live
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
-      const int bf = tx + u * T;
+      const unsigned bf = tx + u * T;
       if (NBF % T == 0 || bf < NBF) {
-        const int p = bf % W, j = bf / W;
+        const unsigned p = bf % W, j = bf / W;
         float2 v[R];
 #pragma unroll
-        for (int t = 0; t < R; ++t) v[t] = FROM_LD ? ld(j + t * LR, p) : buf[(j + t * LR) * WS + p];
+        for (int t = 0; t < R; ++t) v[t] = FROM_LD ? ld(j, t * LR, p) : buf[(j + t * LR) * WS + p];
         finish(v, p, j, u);
       }
     }
@@ -353,9 +372,9 @@ __device__ __forceinline__ void fft_stage_io(float2* __restrict__ buf, const flo
     float2 v[NB][R];
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
-      const int bf = tx + u * T;
+      const unsigned bf = tx + u * T;
       if (NBF % T == 0 || bf < NBF) {
-        const int p = bf % W, j = bf / W;
+        const unsigned p = bf % W, j = bf / W;
 #pragma unroll
         for (int t = 0; t < R; ++t) v[u][t] = buf[(j + t * LR) * WS + p];
       }
@@ -363,7 +382,7 @@ __device__ __forceinline__ void fft_stage_io(float2* __restrict__ buf, const flo
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
-      const int bf = tx + u * T;
+      const unsigned bf = tx + u * T;
       if (NBF % T == 0 || bf < NBF) finish(v[u], bf % W, bf / W, u);
     }
   }
@@ -391,11 +410,11 @@ __device__ __forceinline__ void for_each_last_slot(F&& f) {
   constexpr int NBF = (L / R) * W, NB = (NBF + T - 1) / T;
 #pragma unroll
   for (int u = 0; u < NB; ++u) {
-    const int bf = (int)threadIdx.x + u * T;
+    const unsigned bf = threadIdx.x + u * T;
     if (NBF % T == 0 || bf < NBF) {
-      const int p = bf % W, j = bf / W;
-      const int k = j % NS, q = j / NS;
-      const int base = q * NS * R + k;
+      const unsigned p = bf % W, j = bf / W;
+      const unsigned q = div_small<NS, L / R>(j), k = j - q * NS;
+      const unsigned base = q * NS * R + k;
 #pragma unroll
       for (int t = 0; t < R; ++t) f(base + t * NS, p, u * R + t);
     }
@@ -430,13 +449,13 @@ __device__ __forceinline__ void fft_io(float2* __restrict__ buf, const float2* _
   } else {
     const int L = pl.L;
     if constexpr (!IN_LDS) {
-      for (int e = threadIdx.x; e < L * W; e += T) buf[e] = ld(e / W, e % W);
+      for (int e = threadIdx.x; e < L * W; e += T) buf[e] = ld(e / W, 0, e % W);
     }
     __syncthreads();
     fft_lds<W, T, 0, INV>(buf, tw, pl);
     if constexpr (!OUT_LDS) {
       int slot = 0;
-      for (int e = threadIdx.x; e < L * W; e += T, ++slot) st(e / W, e % W, buf[e], slot);
+      for (int e = threadIdx.x; e < L * W; e += T, ++slot) st(e / W, 0, e % W, buf[e], slot);
     }
   }
 }

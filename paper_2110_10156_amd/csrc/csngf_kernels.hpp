@@ -75,6 +75,43 @@ __device__ __forceinline__ bool resample_q16(const float* __restrict__ B, const 
 
 __device__ __forceinline__ size_t align16(size_t b) { return (b + 15) & ~size_t(15); }
 
+// ------------------------------------------------------------------------- buffer views
+// A raw buffer resource over [base, base + bytes) with a workgroup-uniform base.  Element
+// accesses take a 32-bit byte offset (one 24-bit multiply-add per element instead of 64-bit
+// address arithmetic), and the hardware range check returns zero for a load, and drops a
+// store, at any offset >= bytes: a predicated access passes kNoOff instead of branching.
+// Every view here spans less than 2 GiB, so kNoOff is always out of range.
+constexpr uint32_t kNoOff = 0x80000000u;
+typedef unsigned int u32x2 __attribute__((__vector_size__(8)));
+
+struct RView {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ __forceinline__ RView(const void* base, long long bytes)
+      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000)) {}
+  // (whole-object copies: a bit cast of a single vector element is miscompiled by this
+  // compiler into a read of element 0)
+  __device__ __forceinline__ float2 ld2(uint32_t off) const {
+    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0);
+    float2 x;
+    __builtin_memcpy(&x, &v, 8);
+    return x;
+  }
+  __device__ __forceinline__ void st2(uint32_t off, float2 x) const {
+    u32x2 v;
+    __builtin_memcpy(&v, &x, 8);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)off, 0, 0);
+  }
+  __device__ __forceinline__ unsigned ld1(uint32_t off) const {
+    return __builtin_amdgcn_raw_buffer_load_b8(r, (int)off, 0, 0);
+  }
+};
+
+// byte offset of element (row, col) of a float2 array with a row stride of rs8 bytes
+// (row < 2^24 and rs8 < 2^24, product < 2^31)
+__device__ __forceinline__ uint32_t off2(int row, uint32_t rs8, int col) {
+  return __umul24((unsigned)row, rs8) + 8u * (unsigned)col;
+}
+
 // ------------------------------------------------------------------------------ x pass
 // One workgroup: rows y0 .. y0+kRowsX-1 of slices z0 .. z0+tz-1 of one rotation slot,
 // marching along z with a ring of 3 resampled halo planes (rows y0-1 .. y0+kRowsX) in LDS,
@@ -199,7 +236,8 @@ __global__ __launch_bounds__(kThreads) void k_fields_x(
     const int npairs = (nf + 1) / 2;
 #pragma unroll 1
     for (int pair = 0; pair < npairs; ++pair) {
-      auto products = [&](int x, int r) -> float2 {
+      auto products = [&](int x0, int x1, int r) -> float2 {
+        const int x = x0 + x1;
         if (x >= nx) return make_float2(0.f, 0.f);
         const int e = r * nx + x;
         const float n0 = ng[e], n1 = ng[TY * nx + e], n2 = ng[2 * TY * nx + e];
@@ -218,7 +256,7 @@ __global__ __launch_bounds__(kThreads) void k_fields_x(
         }
         return make_float2(fa, fb);
       };
-      auto none = [](int, int, float2, int) {};
+      auto none = [](int, int, int, float2, int) {};
       fft_io<LC, TY, kThreads, false, false, true, WS>(buf, tw, pl, products, none);
       __syncthreads();
       // split the packed transform: Fa = (Z_k + conj Z_{P-k}) / 2, Fb = -i (Z_k - conj Z_{P-k}) / 2
@@ -260,19 +298,27 @@ __global__ __launch_bounds__(kThreads) void k_pencil(
   float2* tw = reinterpret_cast<float2*>(smem);
   float2* buf = reinterpret_cast<float2*>(smem + align16(sizeof(float2) * L));
   const int kx0 = blockIdx.x * W;
-  const float2* src = in + blockIdx.z * in_sstride + blockIdx.y * in_gstride + kx0;
-  float2* dst = out + blockIdx.z * out_sstride + blockIdx.y * out_gstride + kx0;
+  // views from this tile's first element to the end of its group (rows n_in resp. n_out)
+  const RView src(in + blockIdx.z * in_sstride + blockIdx.y * in_gstride + kx0, 8LL * ((long long)n_in * Hp - kx0));
+  const RView dst(out + blockIdx.z * out_sstride + blockIdx.y * out_gstride + kx0,
+                  8LL * ((long long)n_out * Hp - kx0));
+  const RView rflag(rowfl, n_out);
+  const uint32_t rs8 = 8u * (uint32_t)Hp;
   load_twiddles(tw, twtab, pl);
   if (LC == 0) __syncthreads();
+  // rows i >= n_in lie past the input view and load zero; rows c >= n_out past the output
+  // view (and its flag view) and are dropped; columns >= H are masked by kNoOff
   fft_io<LC, W, kThreads, INV, false, false>(
       buf, tw, pl,
-      [&](int i, int p) -> float2 {
-        return (i < n_in && kx0 + p < H) ? src[(long long)i * Hp + p] : make_float2(0.f, 0.f);
+      [&](int i0, int i1, int p) -> float2 {
+        const uint32_t b = kx0 + p < H ? off2(i0, rs8, p) : kNoOff;
+        return src.ld2(b + (uint32_t)i1 * rs8);
       },
-      [&](int k, int p, float2 v, int) {
-        int c = k - out_off;
+      [&](int k0, int k1, int p, float2 v, int) {
+        int c = k0 + k1 - out_off;
         if (c < 0) c += L;
-        if (c < n_out && kx0 + p < H && (!rowfl || rowfl[c])) dst[(long long)c * Hp + p] = v;
+        const bool keep = kx0 + p < H && (!rowfl || rflag.ld1(c));
+        dst.st2(keep ? off2(c, rs8, p) : kNoOff, v);
       });
 }
 
@@ -312,21 +358,26 @@ __global__ __launch_bounds__(kThreads) void k_zpass(
   const long long fstride_x2 = (long long)nz * Py * Hp;
   const long long fstride_sp = (long long)Pz * Py * Hp;
   const long long zs = (long long)Py * Hp;
+  const long long col0 = (long long)ky * Hp + kx0;
+  const uint32_t zs8 = 8u * (uint32_t)zs;
 #pragma unroll 1
   for (int f = 0; f < nf; ++f) {
-    const float2* src = X2 + slot * x2_sstride + f * fstride_x2 + (long long)ky * Hp + kx0;
-    const float2* a = spec + f * fstride_sp + (long long)ky * Hp + kx0;
+    // views from this pencil tile to the end of field f (moving input, resp. A's spectrum)
+    const RView src(X2 + slot * x2_sstride + f * fstride_x2 + col0, 8 * (fstride_x2 - col0));
+    const RView a(spec + f * fstride_sp + col0, 8 * (fstride_sp - col0));
     fft_io<LC, W, kThreads, false, false, false>(
         buf, tw, pl,
-        [&](int i, int p) -> float2 {
-          return (i < nz && kx0 + p < H) ? src[(long long)i * zs + p] : make_float2(0.f, 0.f);
+        [&](int i0, int i1, int p) -> float2 {
+          // rows i >= nz lie past the view and load zero; masked columns read zero and
+          // are never stored
+          const uint32_t b = kx0 + p < H ? off2(i0, zs8, p) : kNoOff;
+          return src.ld2(b + (uint32_t)i1 * zs8);
         },
-        [&](int k, int p, float2 v, int sl) {
-          if (kx0 + p < H) {
-            const float2 sv = a[(long long)k * zs + p];
-            acc[sl].x = fmaf(v.x, sv.x, fmaf(-v.y, sv.y, acc[sl].x));
-            acc[sl].y = fmaf(v.x, sv.y, fmaf(v.y, sv.x, acc[sl].y));
-          }
+        [&](int k0, int k1, int p, float2 v, int sl) {
+          const uint32_t b = kx0 + p < H ? off2(k0, zs8, p) : kNoOff;
+          const float2 sv = a.ld2(b + (uint32_t)k1 * zs8);
+          acc[sl].x = fmaf(v.x, sv.x, fmaf(-v.y, sv.y, acc[sl].x));
+          acc[sl].y = fmaf(v.x, sv.y, fmaf(v.y, sv.x, acc[sl].y));
         });
     __syncthreads();
   }
@@ -337,14 +388,15 @@ __global__ __launch_bounds__(kThreads) void k_zpass(
     for (int e = threadIdx.x; e < Pz * W; e += kThreads, ++sl) buf[e] = acc[sl];
   }
   __syncthreads();
-  float2* dst = Y3 + slot * y3_sstride + (long long)ky * Hp + kx0;
-  const uint8_t* zflag = flags + slot * flag_sstride;
+  const RView dst(Y3 + slot * y3_sstride + col0, 8 * ((long long)Wz * zs - col0));
+  const RView zflag(flags + slot * flag_sstride, Wz);  // rows c >= Wz read flag 0
   fft_io<LC, W, kThreads, true, true, false>(
-      buf, tw, pl, [](int, int) { return make_float2(0.f, 0.f); },
-      [&](int k, int p, float2 v, int) {
-        int c = k - out_off;
+      buf, tw, pl, [](int, int, int) { return make_float2(0.f, 0.f); },
+      [&](int k0, int k1, int p, float2 v, int) {
+        int c = k0 + k1 - out_off;
         if (c < 0) c += Pz;
-        if (c < Wz && kx0 + p < H && zflag[c]) dst[(long long)c * zs + p] = v;
+        const bool keep = kx0 + p < H && zflag.ld1(c);
+        dst.st2(keep ? off2(c, zs8, p) : kNoOff, v);
       });
 }
 
@@ -370,11 +422,12 @@ __global__ __launch_bounds__(kThreads) void k_zstore(
   float2* dst = spec + (long long)f * Pz * zs + (long long)ky * Hp + kx0;
   fft_io<LC, W, kThreads, false, false, false>(
       buf, tw, pl,
-      [&](int i, int p) -> float2 {
+      [&](int i0, int i1, int p) -> float2 {
+        const int i = i0 + i1;
         return (i < nz && kx0 + p < H) ? src[(long long)i * zs + p] : make_float2(0.f, 0.f);
       },
-      [&](int k, int p, float2 v, int) {
-        if (kx0 + p < H) dst[(long long)k * zs + p] = make_float2(w * v.x, -w * v.y);
+      [&](int k0, int k1, int p, float2 v, int) {
+        if (kx0 + p < H) dst[(long long)(k0 + k1) * zs + p] = make_float2(w * v.x, -w * v.y);
       });
 }
 
@@ -571,7 +624,8 @@ __global__ __launch_bounds__(kThreads) void k_final_x(
   const long long thr = threshold(count_a, count_b, gamma);
   if (LC == 0) __syncthreads();
   unsigned long long best = 0ull;
-  auto pack = [&](int k, int p) -> float2 {
+  auto pack = [&](int k0, int k1, int p) -> float2 {
+    const int k = k0 + k1;
     const int r0 = yc0 + 2 * p, r1 = r0 + 1;
     const int kk = k <= half ? k : Px - k;
     const float2 a = (r0 < Wy && rowfl[r0]) ? rows[(long long)r0 * Hp + kk] : make_float2(0.f, 0.f);
@@ -580,8 +634,8 @@ __global__ __launch_bounds__(kThreads) void k_final_x(
     if (k < half) return make_float2(a.x - c.y, a.y + c.x);  // S1 + i S2
     return make_float2(a.x + c.y, c.x - a.y);                // conj(S1) + i conj(S2)
   };
-  auto emit = [&](int j, int p, float2 zv, int) {
-    const int cx = (j + g.nA[0] - 1) % Px;
+  auto emit = [&](int j0, int j1, int p, float2 zv, int) {
+    const int cx = (j0 + j1 + g.nA[0] - 1) % Px;
     if (cx >= Wx) return;
     const int chx = cx - (g.nA[0] - 1);
     const int lx = max(1 + chx, 0), hx = min(g.nA[0] - 2 + chx, g.nB[0] - 1);
@@ -706,11 +760,11 @@ __global__ __launch_bounds__(kThreads) void k_debug_fft(const float2* __restrict
   if (LC == 0) __syncthreads();
   fft_io<LC, W, kThreads, INV, false, false>(
       buf, tw, pl,
-      [&](int i, int p) -> float2 {
-        return (b0 + p < batch) ? in[(long long)(b0 + p) * L + i] : make_float2(0.f, 0.f);
+      [&](int i0, int i1, int p) -> float2 {
+        return (b0 + p < batch) ? in[(long long)(b0 + p) * L + i0 + i1] : make_float2(0.f, 0.f);
       },
-      [&](int k, int p, float2 v, int) {
-        if (b0 + p < batch) out[(long long)(b0 + p) * L + k] = v;
+      [&](int k0, int k1, int p, float2 v, int) {
+        if (b0 + p < batch) out[(long long)(b0 + p) * L + k0 + k1] = v;
       });
 }
 

@@ -98,7 +98,7 @@ size_t lds_fields(int Px, int nx) {
 
 // slices per field-stage workgroup (z march); each new slice costs one resampled halo plane
 constexpr int kSlicesX = 8;
-size_t lds_pencil(int L) { return a16(sizeof(float2) * L) + a16(sizeof(float2) * L * kTileW); }
+size_t lds_pencil(int L, int W = kTileW) { return a16(sizeof(float2) * L) + a16(sizeof(float2) * L * W); }
 size_t lds_final(int Px, int nxB) {
   return a16(sizeof(float2) * Px) + a16(sizeof(float2) * Px * (kRowsX + 1)) + a16(sizeof(int) * 2 * kRowsX * (nxB + 1));
 }
@@ -318,16 +318,18 @@ int check_dims(const csngf_dims& d, const char* what) {
 int launch_pencil(csngf_ctx* c, bool inv, const float2* in, float2* out, int n_in, int n_out, int out_off,
                   const FftPlan& pl, long long in_g, long long out_g, int groups, long long in_s,
                   long long out_s, int slots, const uint8_t* flags = nullptr, long long flag_s = 0) {
-  const dim3 grid(c->tiles, groups, slots);
-  const size_t lds = lds_pencil(pl.L);
+  // tiles cover the H = Px/2 + 1 bins; the padding columns up to Hp are never touched
+  const int W = inv ? kTileP<true> : kTileP<false>;
+  const dim3 grid((c->H + W - 1) / W, groups, slots);
+  const size_t lds = lds_pencil(pl.L, W);
   hipEvent_t ev = prof_begin(c);
   with_len(pl.L, [&](auto lc) {
     constexpr int LC = decltype(lc)::value;
     if (!inv)
-      hipLaunchKernelGGL((k_pencil<false, LC>), grid, dim3(kThreads), lds, c->stream, in, out, n_in, n_out, out_off,
+      hipLaunchKernelGGL((k_pencil<false, LC>), grid, dim3(kThreadsP<false>), lds, c->stream, in, out, n_in, n_out, out_off,
                          pl, c->d_tw, c->H, c->Hp, in_g, out_g, in_s, out_s, flags, flag_s, groups);
     else
-      hipLaunchKernelGGL((k_pencil<true, LC>), grid, dim3(kThreads), lds, c->stream, in, out, n_in, n_out, out_off,
+      hipLaunchKernelGGL((k_pencil<true, LC>), grid, dim3(kThreadsP<true>), lds, c->stream, in, out, n_in, n_out, out_off,
                          pl, c->d_tw, c->H, c->Hp, in_g, out_g, in_s, out_s, flags, flag_s, groups);
   });
   prof_end(c, inv ? KT_YINV : KT_YFWD, ev);
@@ -349,12 +351,12 @@ int launch_fields(csngf_ctx* c, bool moving, const float* vol, const uint8_t* um
     if (moving) {
       ae = allow_lds(k_fields_x<true, LC>, lds);
       if (ae == hipSuccess)
-        hipLaunchKernelGGL((k_fields_x<true, LC>), grid, dim3(kThreads), lds, c->stream, vol, um, n3[0], n3[1], n3[2],
+        hipLaunchKernelGGL((k_fields_x<true, LC>), grid, dim3(kThreadsF), lds, c->stream, vol, um, n3[0], n3[1], n3[2],
                            tz, slots, c->nf, rotq, c->eps, c->plx, c->d_tw, out, c->H, c->Hp, out_slot, mask_out, mask_slot, dbg);
     } else {
       ae = allow_lds(k_fields_x<false, LC>, lds);
       if (ae == hipSuccess)
-        hipLaunchKernelGGL((k_fields_x<false, LC>), grid, dim3(kThreads), lds, c->stream, vol, um, n3[0], n3[1], n3[2],
+        hipLaunchKernelGGL((k_fields_x<false, LC>), grid, dim3(kThreadsF), lds, c->stream, vol, um, n3[0], n3[1], n3[2],
                            tz, slots, c->nf, rotq, c->eps, c->plx, c->d_tw, out, c->H, c->Hp, out_slot, mask_out, mask_slot, dbg);
     }
   });
@@ -410,7 +412,7 @@ int run_batch(csngf_ctx* c, const float* dB, const uint8_t* dmB, const int* rotq
     ev = prof_begin(c);
     with_len(c->plz.L, [&](auto lc) {
       constexpr int LC = decltype(lc)::value;
-      hipLaunchKernelGGL((k_zpass<LC>), dim3(nb8), dim3(kThreads), lds, c->stream, c->d_buf2, c->d_spec, c->d_buf1,
+      hipLaunchKernelGGL((k_zpass<LC>), dim3(nb8), dim3(kThreadsZ), lds, c->stream, c->d_buf2, c->d_spec, c->d_buf1,
                          c->nB[2], c->P[1], c->H, c->Hp, c->Wd[2], out_off, c->plz, c->d_tw, c->buf2_slot,
                          c->buf1_slot, c->tiles, slots, nreal, c->d_flags, c->flag_slot, c->nf);
     });
@@ -1140,10 +1142,10 @@ int csngf_debug_fft(const void* in, void* out, int32_t L, int32_t batch, int32_t
     with_len(L, [&](auto lc) {
       constexpr int LC = decltype(lc)::value;
       if (inverse)
-        hipLaunchKernelGGL((k_debug_fft<true, LC>), grid, dim3(kThreads), lds, s, (const float2*)in, (float2*)out,
+        hipLaunchKernelGGL((k_debug_fft<true, LC>), grid, dim3(kThreadsP<true>), lds, s, (const float2*)in, (float2*)out,
                            batch, pl, dtw);
       else
-        hipLaunchKernelGGL((k_debug_fft<false, LC>), grid, dim3(kThreads), lds, s, (const float2*)in, (float2*)out,
+        hipLaunchKernelGGL((k_debug_fft<false, LC>), grid, dim3(kThreadsP<false>), lds, s, (const float2*)in, (float2*)out,
                            batch, pl, dtw);
     });
     e = hipGetLastError();

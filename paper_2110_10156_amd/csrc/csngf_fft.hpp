@@ -328,6 +328,14 @@ __device__ __forceinline__ unsigned opaque_tid() {
   return t;
 }
 
+// A per-butterfly LDS index behind an empty asm: the R accesses of the butterfly then
+// address buf[x + constant] with the constant in the instruction's offset field, instead of
+// the compiler folding each constant into the index arithmetic (several ALU ops per access).
+__device__ __forceinline__ unsigned opaque_idx(unsigned x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
 template <int L, int R, int NS, int W, int WS, int WSO, int T, bool INV, bool FROM_LD, bool TO_ST, typename LD, typename ST>
 __device__ __forceinline__ void fft_stage_io(float2* __restrict__ buf, const float2* __restrict__ tw, LD& ld, ST& st) {
   const unsigned tx = opaque_tid();
@@ -347,10 +355,13 @@ __device__ __forceinline__ void fft_stage_io(float2* __restrict__ buf, const flo
     }
     dft<R, INV>(v);
     const unsigned base = q * NS * R + k;
+    if constexpr (TO_ST) {
 #pragma unroll
-    for (int t = 0; t < R; ++t) {
-      if constexpr (TO_ST) st(base, t * NS, p, v[t], u * R + t);
-      else buf[(base + t * NS) * WSO + p] = v[t];
+      for (int t = 0; t < R; ++t) st(base, t * NS, p, v[t], u * R + t);
+    } else {
+      const unsigned wb = opaque_idx(base * WSO + p);
+#pragma unroll
+      for (int t = 0; t < R; ++t) buf[wb + t * NS * WSO] = v[t];
     }
   };
   if constexpr (FROM_LD || TO_ST) {
@@ -362,8 +373,14 @@ __device__ __forceinline__ void fft_stage_io(float2* __restrict__ buf, const flo
       if (NBF % T == 0 || bf < NBF) {
         const unsigned p = bf % W, j = bf / W;
         float2 v[R];
+        if constexpr (FROM_LD) {
 #pragma unroll
-        for (int t = 0; t < R; ++t) v[t] = FROM_LD ? ld(j, t * LR, p) : buf[(j + t * LR) * WS + p];
+          for (int t = 0; t < R; ++t) v[t] = ld(j, t * LR, p);
+        } else {
+          const unsigned rb = opaque_idx(j * WS + p);
+#pragma unroll
+          for (int t = 0; t < R; ++t) v[t] = buf[rb + t * LR * WS];
+        }
         finish(v, p, j, u);
       }
     }
@@ -375,8 +392,9 @@ __device__ __forceinline__ void fft_stage_io(float2* __restrict__ buf, const flo
       const unsigned bf = tx + u * T;
       if (NBF % T == 0 || bf < NBF) {
         const unsigned p = bf % W, j = bf / W;
+        const unsigned rb = opaque_idx(j * WS + p);
 #pragma unroll
-        for (int t = 0; t < R; ++t) v[u][t] = buf[(j + t * LR) * WS + p];
+        for (int t = 0; t < R; ++t) v[u][t] = buf[rb + t * LR * WS];
       }
     }
     __syncthreads();

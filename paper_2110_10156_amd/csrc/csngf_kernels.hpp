@@ -18,8 +18,37 @@
 
 namespace csngf {
 
-constexpr int kThreads = 256;
-constexpr int kTileW = 16;   // adjacent x-bins per pencil tile in the y/z passes
+constexpr int kThreads = 256;  // workgroup size of the small kernels
+constexpr int kTileW = 16;     // adjacent x-bins per pencil tile in the z pass (and row pitch unit)
+// Workgroup sizes and y tile widths of the FFT passes.  LDS, not registers, limits how many
+// workgroups a CU holds in these passes, so a larger workgroup raises the resident waves.
+// Defaults are the fastest measured on a 176x176x110 pair (FFT 352x352x220); each can be
+// overridden at build time (-DCSNGF_TF=... and so on) for tuning.
+#ifndef CSNGF_TF
+#define CSNGF_TF 512
+#endif
+#ifndef CSNGF_TPF
+#define CSNGF_TPF 256
+#endif
+#ifndef CSNGF_TPI
+#define CSNGF_TPI 512
+#endif
+#ifndef CSNGF_TZ
+#define CSNGF_TZ 512
+#endif
+#ifndef CSNGF_WPF
+#define CSNGF_WPF 16
+#endif
+#ifndef CSNGF_WPI
+#define CSNGF_WPI 16
+#endif
+constexpr int kThreadsF = CSNGF_TF;  // field stage (x pass)
+constexpr int kThreadsZ = CSNGF_TZ;  // z pass
+template <bool INV>
+constexpr int kThreadsP = INV ? CSNGF_TPI : CSNGF_TPF;  // y pencil passes (forward, inverse)
+template <bool INV>
+constexpr int kTileP = INV ? CSNGF_WPI : CSNGF_WPF;     // x-bins per y pencil tile
+static_assert(kTileW % CSNGF_WPF == 0 && kTileW % CSNGF_WPI == 0, "y tiles must divide the row pitch unit");
 constexpr int kRowsX = 8;    // rows per workgroup in the x passes
 
 struct RotResultDev {        // identical layout to csngf_rot_result
@@ -123,7 +152,7 @@ template <int LC>
 constexpr int xrow_stride() { return LC > 0 ? kRowsX + 1 : kRowsX; }
 
 template <bool MOVING, int LC>
-__global__ __launch_bounds__(kThreads) void k_fields_x(
+__global__ __launch_bounds__(kThreadsF) void k_fields_x(
     const float* __restrict__ vol, const uint8_t* __restrict__ umask, int nx, int ny, int nz, int tz, int nslots,
     int nf, const int* __restrict__ rotq, float eps, FftPlan pl, const float2* __restrict__ twtab,
     float2* __restrict__ out, int H, int Hp, long long out_slot_stride,
@@ -160,12 +189,12 @@ __global__ __launch_bounds__(kThreads) void k_fields_x(
     float* pv = val + ring * plane;
     uint8_t* po = ok + ring * plane;
     constexpr int HU = 4;
-    for (int base = 0; base < plane; base += HU * kThreads) {
+    for (int base = 0; base < plane; base += HU * kThreadsF) {
       float v[HU];
       bool good[HU];
 #pragma unroll
       for (int u = 0; u < HU; ++u) {
-        const int e = base + u * kThreads + (int)threadIdx.x;
+        const int e = base + u * kThreadsF + (int)threadIdx.x;
         v[u] = 0.f;
         good[u] = false;
         if (e < plane) {
@@ -184,7 +213,7 @@ __global__ __launch_bounds__(kThreads) void k_fields_x(
       }
 #pragma unroll
       for (int u = 0; u < HU; ++u) {
-        const int e = base + u * kThreads + (int)threadIdx.x;
+        const int e = base + u * kThreadsF + (int)threadIdx.x;
         if (e < plane) {
           pv[e] = v[u];
           po[e] = good[u] ? 1 : 0;
@@ -209,7 +238,7 @@ __global__ __launch_bounds__(kThreads) void k_fields_x(
       const uint8_t* om = ok + ((zi + 0) % 3) * plane;
       const uint8_t* oc = ok + ((zi + 1) % 3) * plane;
       const uint8_t* op = ok + ((zi + 2) % 3) * plane;
-      for (int e = threadIdx.x; e < TY * nx; e += kThreads) {
+      for (int e = threadIdx.x; e < TY * nx; e += kThreadsF) {
         const int x = e % nx, r = e / nx;
         const int c = (r + 1) * nx + x;
         const bool m = x >= 1 && x <= nx - 2 && oc[c] && oc[c - 1] && oc[c + 1] && oc[c - nx] && oc[c + nx] &&
@@ -257,10 +286,10 @@ __global__ __launch_bounds__(kThreads) void k_fields_x(
         return make_float2(fa, fb);
       };
       auto none = [](int, int, int, float2, int) {};
-      fft_io<LC, TY, kThreads, false, false, true, WS>(buf, tw, pl, products, none);
+      fft_io<LC, TY, kThreadsF, false, false, true, WS>(buf, tw, pl, products, none);
       __syncthreads();
       // split the packed transform: Fa = (Z_k + conj Z_{P-k}) / 2, Fb = -i (Z_k - conj Z_{P-k}) / 2
-      for (int e = threadIdx.x; e < TY * H; e += kThreads) {
+      for (int e = threadIdx.x; e < TY * H; e += kThreadsF) {
         const int r = e / H, k = e % H;
         const int yy = y0 + r;
         if (yy >= ny) continue;
@@ -282,12 +311,12 @@ __global__ __launch_bounds__(kThreads) void k_fields_x(
 // Pencils along the middle axis.  Workgroup (x-tile, group g, slot): input rows i < n_in of
 // in[g], zero beyond; output row c takes transform row (c + out_off) mod L.
 template <bool INV, int LC>
-__global__ __launch_bounds__(kThreads) void k_pencil(
+__global__ __launch_bounds__(kThreadsP<INV>) void k_pencil(
     const float2* __restrict__ in, float2* __restrict__ out, int n_in, int n_out, int out_off,
     FftPlan pl, const float2* __restrict__ twtab, int H, int Hp, long long in_gstride,
     long long out_gstride, long long in_sstride, long long out_sstride, const uint8_t* __restrict__ flags,
     long long flag_sstride, int ngroups) {
-  constexpr int W = kTileW;
+  constexpr int W = kTileP<INV>;
   extern __shared__ __align__(16) unsigned char smem[];
   const int L = pl.L;
   // flags (inverse pass only): group g is skipped when flags[g] == 0; output row c of group g
@@ -308,7 +337,7 @@ __global__ __launch_bounds__(kThreads) void k_pencil(
   if (LC == 0) __syncthreads();
   // rows i >= n_in lie past the input view and load zero; rows c >= n_out past the output
   // view (and its flag view) and are dropped; columns >= H are masked by kNoOff
-  fft_io<LC, W, kThreads, INV, false, false>(
+  fft_io<LC, W, kThreadsP<INV>, INV, false, false>(
       buf, tw, pl,
       [&](int i0, int i1, int p) -> float2 {
         const uint32_t b = kx0 + p < H ? off2(i0, rs8, p) : kNoOff;
@@ -329,13 +358,13 @@ __global__ __launch_bounds__(kThreads) void k_pencil(
 // registers; then the sum goes through LDS once for the z inverse, whose last stage
 // stores the kept displacement rows.
 template <int LC>
-__global__ __launch_bounds__(kThreads) void k_zpass(
+__global__ __launch_bounds__(kThreadsZ) void k_zpass(
     const float2* __restrict__ X2, const float2* __restrict__ spec, float2* __restrict__ Y3,
     int nz, int Py, int H, int Hp, int Wz, int out_off, FftPlan pl, const float2* __restrict__ twtab,
     long long x2_sstride, long long y3_sstride, int ntiles, int nslots, int nreal,
     const uint8_t* __restrict__ flags, long long flag_sstride, int nf) {
   constexpr int W = kTileW;
-  constexpr int NSLOT = consumer_slots<LC, W, kThreads>();
+  constexpr int NSLOT = consumer_slots<LC, W, kThreadsZ>();
   extern __shared__ __align__(16) unsigned char smem[];
   const int Pz = pl.L;
   float2* tw = reinterpret_cast<float2*>(smem);
@@ -362,14 +391,13 @@ __global__ __launch_bounds__(kThreads) void k_zpass(
   const uint32_t zs8 = 8u * (uint32_t)zs;
 #pragma unroll 1
   for (int f = 0; f < nf; ++f) {
-    // views from this pencil tile to the end of field f (moving input, resp. A's spectrum)
+    // views from this pencil tile to the end of field f: moving input (rows i >= nz lie past
+    // it and load zero) and A's spectrum; masked columns load zero and are never stored
     const RView src(X2 + slot * x2_sstride + f * fstride_x2 + col0, 8 * (fstride_x2 - col0));
     const RView a(spec + f * fstride_sp + col0, 8 * (fstride_sp - col0));
-    fft_io<LC, W, kThreads, false, false, false>(
+    fft_io<LC, W, kThreadsZ, false, false, false>(
         buf, tw, pl,
         [&](int i0, int i1, int p) -> float2 {
-          // rows i >= nz lie past the view and load zero; masked columns read zero and
-          // are never stored
           const uint32_t b = kx0 + p < H ? off2(i0, zs8, p) : kNoOff;
           return src.ld2(b + (uint32_t)i1 * zs8);
         },
@@ -382,15 +410,15 @@ __global__ __launch_bounds__(kThreads) void k_zpass(
     __syncthreads();
   }
   if constexpr (LC > 0) {
-    for_each_last_slot<LC, W, kThreads>([&](int k, int p, int sl) { buf[k * W + p] = acc[sl]; });
+    for_each_last_slot<LC, W, kThreadsZ>([&](int k, int p, int sl) { buf[k * W + p] = acc[sl]; });
   } else {
     int sl = 0;
-    for (int e = threadIdx.x; e < Pz * W; e += kThreads, ++sl) buf[e] = acc[sl];
+    for (int e = threadIdx.x; e < Pz * W; e += kThreadsZ, ++sl) buf[e] = acc[sl];
   }
   __syncthreads();
   const RView dst(Y3 + slot * y3_sstride + col0, 8 * ((long long)Wz * zs - col0));
   const RView zflag(flags + slot * flag_sstride, Wz);  // rows c >= Wz read flag 0
-  fft_io<LC, W, kThreads, true, true, false>(
+  fft_io<LC, W, kThreadsZ, true, true, false>(
       buf, tw, pl, [](int, int, int) { return make_float2(0.f, 0.f); },
       [&](int k0, int k1, int p, float2 v, int) {
         int c = k0 + k1 - out_off;
@@ -748,7 +776,7 @@ __global__ __launch_bounds__(kThreads) void k_blur_axis(const float* __restrict_
 
 // Batched C2C along a contiguous axis: in/out [batch][L]; 16 batch rows per workgroup.
 template <bool INV, int LC>
-__global__ __launch_bounds__(kThreads) void k_debug_fft(const float2* __restrict__ in, float2* __restrict__ out,
+__global__ __launch_bounds__(kThreadsP<INV>) void k_debug_fft(const float2* __restrict__ in, float2* __restrict__ out,
                                                         int batch, FftPlan pl, const float2* __restrict__ twtab) {
   constexpr int W = kTileW;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -758,7 +786,7 @@ __global__ __launch_bounds__(kThreads) void k_debug_fft(const float2* __restrict
   const int b0 = blockIdx.x * W;
   load_twiddles(tw, twtab, pl);
   if (LC == 0) __syncthreads();
-  fft_io<LC, W, kThreads, INV, false, false>(
+  fft_io<LC, W, kThreadsP<INV>, INV, false, false>(
       buf, tw, pl,
       [&](int i0, int i1, int p) -> float2 {
         return (b0 + p < batch) ? in[(long long)(b0 + p) * L + i0 + i1] : make_float2(0.f, 0.f);

@@ -91,9 +91,11 @@ void twiddles(int L, std::vector<float2>& out) {
 
 size_t a16(size_t b) { return (b + 15) & ~size_t(15); }
 
+// twiddles, transform rows, ring of 3 halo planes, NGF of one slice (+ Px floats of padding
+// for the producer's reads past the last row)
 size_t lds_fields(int Px, int nx) {
   return a16(sizeof(float2) * Px) + a16(sizeof(float2) * Px * (kRowsX + 1)) + a16(sizeof(float) * 3 * (kRowsX + 2) * nx) +
-         a16(sizeof(float) * 3 * kRowsX * nx) + a16((size_t)3 * (kRowsX + 2) * nx);
+         a16(sizeof(float) * (3 * kRowsX * nx + Px));
 }
 
 // slices per field-stage workgroup (z march); each new slice costs one resampled halo plane

@@ -64,44 +64,6 @@ __device__ __forceinline__ float lerp_exact(float a, float b, float f) {
   return fmaf(f, b - a, a);
 }
 
-// Trilinear sample of B at p = R (x - c) + c with R in Q16 fixed point.  Coordinates are
-// exact integers in units of 2^-17:  p_i 2^17 = sum_j k_ij (2 x_j - (n_j - 1)) + (n_i - 1) 2^16.
-// Returns false (value 0) when p leaves the closed box [0, n-1]^3 or, with a mask, when a
-// corner of the source cell lies outside the mask.
-__device__ __forceinline__ bool resample_q16(const float* __restrict__ B, const uint8_t* __restrict__ mB,
-                                             int nx, int ny, int nz, const int* __restrict__ k,
-                                             int x, int y, int z, float& out) {
-  const int dx = 2 * x - (nx - 1), dy = 2 * y - (ny - 1), dz = 2 * z - (nz - 1);
-  const int px = k[0] * dx + k[1] * dy + k[2] * dz + (nx - 1) * 65536;
-  const int py = k[3] * dx + k[4] * dy + k[5] * dz + (ny - 1) * 65536;
-  const int pz = k[6] * dx + k[7] * dy + k[8] * dz + (nz - 1) * 65536;
-  out = 0.f;
-  if (px < 0 || py < 0 || pz < 0 || px > ((nx - 1) << 17) || py > ((ny - 1) << 17) ||
-      pz > ((nz - 1) << 17))
-    return false;
-  int ix = px >> 17, iy = py >> 17, iz = pz >> 17;
-  const float q = 1.0f / 131072.0f;
-  float fx = (float)(px & 0x1FFFF) * q, fy = (float)(py & 0x1FFFF) * q, fz = (float)(pz & 0x1FFFF) * q;
-  if (ix == nx - 1) { ix = nx - 2; fx = 1.0f; }
-  if (iy == ny - 1) { iy = ny - 2; fy = 1.0f; }
-  if (iz == nz - 1) { iz = nz - 2; fz = 1.0f; }
-  const long sy = nx, sz = (long)nx * ny;
-  const long o = iz * sz + iy * sy + ix;
-  if (mB) {
-    if (!(mB[o] && mB[o + 1] && mB[o + sy] && mB[o + sy + 1] && mB[o + sz] && mB[o + sz + 1] &&
-          mB[o + sz + sy] && mB[o + sz + sy + 1]))
-      return false;
-  }
-  const float c00 = lerp_exact(B[o], B[o + 1], fx);
-  const float c10 = lerp_exact(B[o + sy], B[o + sy + 1], fx);
-  const float c01 = lerp_exact(B[o + sz], B[o + sz + 1], fx);
-  const float c11 = lerp_exact(B[o + sz + sy], B[o + sz + sy + 1], fx);
-  const float c0 = lerp_exact(c00, c10, fy);
-  const float c1 = lerp_exact(c01, c11, fy);
-  out = lerp_exact(c0, c1, fz);
-  return true;
-}
-
 __device__ __forceinline__ size_t align16(size_t b) { return (b + 15) & ~size_t(15); }
 
 // ------------------------------------------------------------------------- buffer views
@@ -119,8 +81,8 @@ struct RView {
       : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000)) {}
   // (whole-object copies: a bit cast of a single vector element is miscompiled by this
   // compiler into a read of element 0)
-  __device__ __forceinline__ float2 ld2(uint32_t off) const {
-    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0);
+  __device__ __forceinline__ float2 ld2(uint32_t off, uint32_t soff = 0) const {
+    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, (int)soff, 0);
     float2 x;
     __builtin_memcpy(&x, &v, 8);
     return x;
@@ -130,8 +92,18 @@ struct RView {
     __builtin_memcpy(&v, &x, 8);
     __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)off, 0, 0);
   }
-  __device__ __forceinline__ unsigned ld1(uint32_t off) const {
-    return __builtin_amdgcn_raw_buffer_load_b8(r, (int)off, 0, 0);
+  __device__ __forceinline__ unsigned ld1(uint32_t off, uint32_t soff = 0) const {
+    return __builtin_amdgcn_raw_buffer_load_b8(r, (int)off, (int)soff, 0);
+  }
+  __device__ __forceinline__ void st1(uint32_t off, unsigned char x) const {
+    __builtin_amdgcn_raw_buffer_store_b8(x, r, (int)off, 0, 0);
+  }
+  // float at byte offset off + soff (soff: a workgroup-uniform offset held in a scalar register)
+  __device__ __forceinline__ float ldf(uint32_t off, uint32_t soff = 0) const {
+    const unsigned v = __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, (int)soff, 0);
+    float x;
+    __builtin_memcpy(&x, &v, 4);
+    return x;
   }
 };
 
@@ -143,11 +115,17 @@ __device__ __forceinline__ uint32_t off2(int row, uint32_t rs8, int col) {
 
 // ------------------------------------------------------------------------------ x pass
 // One workgroup: rows y0 .. y0+kRowsX-1 of slices z0 .. z0+tz-1 of one rotation slot,
-// marching along z with a ring of 3 resampled halo planes (rows y0-1 .. y0+kRowsX) in LDS,
-// so each new slice costs one new plane.  Per slice: mask and NGF once per voxel into LDS;
-// then for each of the 3 field pairs (xx,yy), (zz,xy), (xz,yz) the first FFT stage forms
-// the pair's products (re = first field, im = second), the transform runs along x (length
-// Px, zero padded from nx) and the result is split into two half spectra.
+// marching along z with a ring of 3 sampled halo planes (rows y0-1 .. y0+kRowsX) in LDS, so
+// each new slice costs one new plane.  A sample that is not valid (outside the grid or the
+// box, or a mask corner unset) is stored as NaN, so one NaN test on the gradient stencil
+// gives the eroded mask.  Per slice: mask and NGF once per voxel into LDS; then for each of
+// the 3 field pairs (xx,yy), (zz,xy), (xz,yz) the first FFT stage forms the pair's products
+// (re = first field, im = second), the transform runs along x (length Px, zero padded from
+// nx) and the result is split into two half spectra.
+//
+// Every strided loop visits the same elements in every plane, so each thread decodes its
+// elements' (x, row) once; for the moving side it also keeps the z-independent part of each
+// element's source coordinate, so a plane costs 3 integer adds per sample before the gather.
 template <int LC>
 constexpr int xrow_stride() { return LC > 0 ? kRowsX + 1 : kRowsX; }
 
@@ -157,9 +135,13 @@ __global__ __launch_bounds__(kThreadsF) void k_fields_x(
     int nf, const int* __restrict__ rotq, float eps, FftPlan pl, const float2* __restrict__ twtab,
     float2* __restrict__ out, int H, int Hp, long long out_slot_stride,
     uint8_t* __restrict__ mask_out, long long mask_slot_stride, float* __restrict__ dbg_prod) {
+  constexpr int T = kThreadsF;
   constexpr int TY = kRowsX;
   constexpr int WS = xrow_stride<LC>();
   constexpr int HR = TY + 2;
+  constexpr int ME = (HR * kMaxLen + T - 1) / T;              // halo-plane samples per thread
+  constexpr int MN = (TY * kMaxLen + T - 1) / T;              // slice voxels per thread
+  constexpr int MU = (TY * (kMaxLen / 2 + 1) + T - 1) / T;    // half-spectrum bins per thread
   extern __shared__ __align__(16) unsigned char smem[];
   const int Px = pl.L;
   const int plane = HR * nx;
@@ -167,7 +149,6 @@ __global__ __launch_bounds__(kThreadsF) void k_fields_x(
   float2* buf = reinterpret_cast<float2*>(smem + align16(sizeof(float2) * Px));
   float* val = reinterpret_cast<float*>(smem + align16(sizeof(float2) * Px) + align16(sizeof(float2) * Px * (TY + 1)));
   float* ng = reinterpret_cast<float*>(reinterpret_cast<unsigned char*>(val) + align16(sizeof(float) * 3 * plane));
-  uint8_t* ok = reinterpret_cast<uint8_t*>(reinterpret_cast<unsigned char*>(ng) + align16(sizeof(float) * 3 * TY * nx));
   // XCD-aware order (hardware deals block b to XCD b % 8): each XCD walks a contiguous run
   // of (y tile, z chunk, slot) with the y tile fastest, so neighbouring tiles' source
   // footprints in B meet in the same L2.
@@ -178,86 +159,198 @@ __global__ __launch_bounds__(kThreadsF) void k_fields_x(
   const int y0 = (logical % nyt) * TY;
   const int z0 = ((logical / nyt) % nzc) * tz;
   const int slot = logical / (nyt * nzc);
-  const int* kq = MOVING ? rotq + 9 * slot : nullptr;
   load_twiddles(tw, twtab, pl);
   const float eps2 = eps * eps;
   const long nv = (long)nx * ny * nz;
+  const unsigned tid = threadIdx.x;
+  const float qnan = __builtin_nanf("");
 
-  // sample halo plane zz (rows y0-1 .. y0+TY) into ring slot (zz - z0 + 1) mod 3
-  auto fill_plane = [&](int zz) {
-    const int ring = (zz - z0 + 1) % 3;
-    float* pv = val + ring * plane;
-    uint8_t* po = ok + ring * plane;
-    constexpr int HU = 4;
-    for (int base = 0; base < plane; base += HU * kThreadsF) {
-      float v[HU];
-      bool good[HU];
+  const RView src(vol, 4LL * nv);   // the volume (its mask and the mask output: where used)
+
+  // ---- per-thread decode of the halo-plane samples
+  // moving: source coordinate p 2^17 = k (2 x - (n - 1)) + (n - 1) 2^16 per axis (Q16 matrix k),
+  // split into the part fixed by (x, row) and the part of the plane's z; rows outside the
+  // grid get a coordinate far below 0, so the box test rejects them.
+  // fixed: the voxel's offset within a plane, -1 outside the grid.
+  const int* kq = MOVING ? rotq + 9 * slot : nullptr;
+  int cx[ME], cy[ME], cz[ME];
 #pragma unroll
-      for (int u = 0; u < HU; ++u) {
-        const int e = base + u * kThreadsF + (int)threadIdx.x;
-        v[u] = 0.f;
-        good[u] = false;
-        if (e < plane) {
-          const int x = e % nx, r = e / nx;
-          const int yy = y0 + r - 1;
-          if (yy >= 0 && yy < ny && zz >= 0 && zz < nz) {
-            if (MOVING) {
-              good[u] = resample_q16(vol, umask, nx, ny, nz, kq, x, yy, zz, v[u]);
-            } else {
-              const long o = ((long)zz * ny + yy) * nx + x;
-              v[u] = vol[o];
-              good[u] = umask ? (umask[o] != 0) : true;
-            }
+  for (int u = 0; u < ME; ++u) {
+    const int e = (int)tid + u * T;
+    const int x = e % nx, r = e / nx;
+    const int yy = y0 + r - 1;
+    const bool in = e < plane && yy >= 0 && yy < ny;
+    if (MOVING) {
+      const int dx = 2 * x - (nx - 1), dy = 2 * yy - (ny - 1);
+      cx[u] = in ? kq[0] * dx + kq[1] * dy + (nx - 1) * 65536 : -(1 << 30);
+      cy[u] = kq[3] * dx + kq[4] * dy + (ny - 1) * 65536;
+      cz[u] = kq[6] * dx + kq[7] * dy + (nz - 1) * 65536;
+    } else {
+      cx[u] = in ? yy * nx + x : -1;
+      cy[u] = cz[u] = 0;
+    }
+  }
+
+  // sample halo plane zz (rows y0-1 .. y0+TY) into ring slot (zz - z0 + 1) mod 3; HU samples
+  // at a time, all their gathers issued before any is used
+  auto fill_plane = [&](int zz) {
+    float* pv = val + ((zz - z0 + 1) % 3) * plane;
+    const bool zin = zz >= 0 && zz < nz;
+    const int dz = 2 * zz - (nz - 1);
+    const int ax = MOVING ? kq[2] * dz : 0, ay = MOVING ? kq[5] * dz : 0, az = MOVING ? kq[8] * dz : 0;
+    const int limx = (nx - 1) << 17, limy = (ny - 1) << 17, limz = (nz - 1) << 17;
+    const uint32_t sy4 = 4u * nx, sz4 = 4u * nx * ny;   // byte strides of B along y and z
+    constexpr int HU = 4;
+#pragma unroll
+    for (int u0 = 0; u0 < ME; u0 += HU) {
+      if (u0 * T >= plane) break;
+      float v[HU];
+      if constexpr (MOVING) {
+        float2 c[HU][4];
+        float fx[HU], fy[HU], fz[HU];
+        bool good[HU];
+#pragma unroll
+        for (int h = 0; h < HU; ++h) {
+          const int u = u0 + h < ME ? u0 + h : ME - 1;
+          const int px = cx[u] + ax, py = cy[u] + ay, pz = cz[u] + az;
+          const bool ok = zin & ((unsigned)px <= (unsigned)limx) & ((unsigned)py <= (unsigned)limy) &
+                          ((unsigned)pz <= (unsigned)limz);
+          int ix = px >> 17, iy = py >> 17, iz = pz >> 17;
+          const float q = 1.0f / 131072.0f;
+          fx[h] = (float)(px & 0x1FFFF) * q;
+          fy[h] = (float)(py & 0x1FFFF) * q;
+          fz[h] = (float)(pz & 0x1FFFF) * q;
+          // p on the upper face: use the last cell with weight 1 on its far corner
+          if (ix == nx - 1) { ix = nx - 2; fx[h] = 1.0f; }
+          if (iy == ny - 1) { iy = ny - 2; fy[h] = 1.0f; }
+          if (iz == nz - 1) { iz = nz - 2; fz[h] = 1.0f; }
+          const unsigned o = (unsigned)((iz * ny + iy) * nx + ix);
+          const unsigned o4 = ok ? 4u * o : kNoOff;
+          c[h][0] = src.ld2(o4, 0);          // corners (x, x+1) of the 4 (y, z) edges
+          c[h][1] = src.ld2(o4, sy4);
+          c[h][2] = src.ld2(o4, sz4);
+          c[h][3] = src.ld2(o4, sz4 + sy4);
+          good[h] = ok;
+          if (umask) {
+            // all 8 corners inside the mask: the smallest of the 8 bytes is nonzero
+            const RView srcm(umask, nv);
+            const unsigned om = ok ? o : kNoOff;
+            unsigned mn = min(srcm.ld1(om, 0), srcm.ld1(om + 1, 0));
+            mn = min(mn, min(srcm.ld1(om, sy4 / 4), srcm.ld1(om + 1, sy4 / 4)));
+            mn = min(mn, min(srcm.ld1(om, sz4 / 4), srcm.ld1(om + 1, sz4 / 4)));
+            mn = min(mn, min(srcm.ld1(om, (sz4 + sy4) / 4), srcm.ld1(om + 1, (sz4 + sy4) / 4)));
+            good[h] = ok && mn != 0;
           }
+        }
+#pragma unroll
+        for (int h = 0; h < HU; ++h) {
+          const float c00 = lerp_exact(c[h][0].x, c[h][0].y, fx[h]);
+          const float c10 = lerp_exact(c[h][1].x, c[h][1].y, fx[h]);
+          const float c01 = lerp_exact(c[h][2].x, c[h][2].y, fx[h]);
+          const float c11 = lerp_exact(c[h][3].x, c[h][3].y, fx[h]);
+          const float c0 = lerp_exact(c00, c10, fy[h]);
+          const float c1 = lerp_exact(c01, c11, fy[h]);
+          v[h] = good[h] ? lerp_exact(c0, c1, fz[h]) : qnan;
+        }
+      } else {
+#pragma unroll
+        for (int h = 0; h < HU; ++h) {
+          const int u = u0 + h < ME ? u0 + h : ME - 1;
+          const bool ok = zin && cx[u] >= 0;
+          const unsigned o = ok ? (unsigned)(zz * ny * nx + cx[u]) : kNoOff / 4;
+          const float s = src.ldf(ok ? 4u * o : kNoOff);
+          const bool good = ok && (!umask || RView(umask, nv).ld1(o) != 0);
+          v[h] = good ? s : qnan;
         }
       }
 #pragma unroll
-      for (int u = 0; u < HU; ++u) {
-        const int e = base + u * kThreadsF + (int)threadIdx.x;
-        if (e < plane) {
-          pv[e] = v[u];
-          po[e] = good[u] ? 1 : 0;
-        }
+      for (int h = 0; h < HU; ++h) {
+        const int e = (int)tid + (u0 + h) * T;
+        if (u0 + h < ME && e < plane) pv[e] = v[h];
       }
     }
   };
 
-  fill_plane(z0 - 1);
-  fill_plane(z0);
+  // ---- per-thread decode of the slice voxels and of the half-spectrum bins
+  int sx[MN], sr[MN];
+#pragma unroll
+  for (int u = 0; u < MN; ++u) {
+    const int e = (int)tid + u * T;
+    sx[u] = e % nx;
+    sr[u] = e / nx;
+  }
+  int bk[MU], br[MU];
+#pragma unroll
+  for (int u = 0; u < MU; ++u) {
+    const int e = (int)tid + u * T;
+    bk[u] = e % H;
+    br[u] = e / H;
+  }
+  const uint32_t hp8 = 8u * (uint32_t)Hp;
+
+  // zi = -2, -1 only sample the first two halo planes (z0 - 1, z0)
 #pragma unroll 1
-  for (int zi = 0; zi < tz; ++zi) {
+  for (int zi = -2; zi < tz; ++zi) {
     const int z = z0 + zi;
     if (z >= nz) break;
+    // keep the decoded values opaque per iteration: otherwise the compiler hoists every
+    // per-element predicate out of the loop as a 64-bit lane mask and runs out of scalar
+    // registers
+#pragma unroll
+    for (int u = 0; u < ME; ++u) {
+      cx[u] = (int)opaque_idx((unsigned)cx[u]);
+      if (MOVING) {
+        cy[u] = (int)opaque_idx((unsigned)cy[u]);
+        cz[u] = (int)opaque_idx((unsigned)cz[u]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < MN; ++u) {
+      sx[u] = (int)opaque_idx((unsigned)sx[u]);
+      sr[u] = (int)opaque_idx((unsigned)sr[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < MU; ++u) {
+      bk[u] = (int)opaque_idx((unsigned)bk[u]);
+      br[u] = (int)opaque_idx((unsigned)br[u]);
+    }
     fill_plane(z + 1);
+    if (zi < 0) continue;
     __syncthreads();
-    // mask and NGF of slice z (n = 0 where the eroded mask is 0)
+    // mask and NGF of slice z (n = 0 where the eroded mask is 0): the voxel and its six
+    // neighbours must be valid samples, i.e. no NaN among the stencil's values
     {
       const float* vm = val + ((zi + 0) % 3) * plane;  // slice z - 1
       const float* vc = val + ((zi + 1) % 3) * plane;  // slice z
       const float* vp = val + ((zi + 2) % 3) * plane;  // slice z + 1
-      const uint8_t* om = ok + ((zi + 0) % 3) * plane;
-      const uint8_t* oc = ok + ((zi + 1) % 3) * plane;
-      const uint8_t* op = ok + ((zi + 2) % 3) * plane;
-      for (int e = threadIdx.x; e < TY * nx; e += kThreadsF) {
-        const int x = e % nx, r = e / nx;
-        const int c = (r + 1) * nx + x;
-        const bool m = x >= 1 && x <= nx - 2 && oc[c] && oc[c - 1] && oc[c + 1] && oc[c - nx] && oc[c + nx] &&
-                       om[c] && op[c];
-        float n0 = 0.f, n1 = 0.f, n2 = 0.f;
-        if (m) {
+#pragma unroll
+      for (int u = 0; u < MN; ++u) {
+        const int e = (int)tid + u * T;
+        if (u * T >= TY * nx) break;
+        if (e < TY * nx) {
+          const int x = sx[u], r = sr[u];
+          const int c = e + nx;   // (r + 1) * nx + x
           const float gx = 0.5f * (vc[c + 1] - vc[c - 1]);
           const float gy = 0.5f * (vc[c + nx] - vc[c - nx]);
           const float gz = 0.5f * (vp[c] - vm[c]);
-          const float inv = 1.0f / sqrtf(gx * gx + gy * gy + gz * gz + eps2);
-          n0 = gx * inv;
-          n1 = gy * inv;
-          n2 = gz * inv;
+          const bool m = x >= 1 && x <= nx - 2 && !__builtin_isnan(vc[c]) && !__builtin_isnan(gx) &&
+                         !__builtin_isnan(gy) && !__builtin_isnan(gz);
+          float n0 = 0.f, n1 = 0.f, n2 = 0.f;
+          if (m) {
+            const float inv = 1.0f / sqrtf(gx * gx + gy * gy + gz * gz + eps2);
+            n0 = gx * inv;
+            n1 = gy * inv;
+            n2 = gz * inv;
+          }
+          ng[e] = n0;
+          ng[TY * nx + e] = n1;
+          ng[2 * TY * nx + e] = n2;
+          if (mask_out) {
+            const int yy = y0 + r;
+            RView(mask_out + slot * mask_slot_stride, nv).st1(yy < ny ? (unsigned)((z * ny + yy) * nx + x) : kNoOff,
+                                                              m ? 1 : 0);
+          }
         }
-        ng[e] = n0;
-        ng[TY * nx + e] = n1;
-        ng[2 * TY * nx + e] = n2;
-        const int yy = y0 + r;
-        if (yy < ny && mask_out) mask_out[slot * mask_slot_stride + ((long)z * ny + yy) * nx + x] = m ? 1 : 0;
       }
     }
     __syncthreads();
@@ -267,9 +360,10 @@ __global__ __launch_bounds__(kThreadsF) void k_fields_x(
     for (int pair = 0; pair < npairs; ++pair) {
       auto products = [&](int x0, int x1, int r) -> float2 {
         const int x = x0 + x1;
-        if (x >= nx) return make_float2(0.f, 0.f);
-        const int e = r * nx + x;
-        const float n0 = ng[e], n1 = ng[TY * nx + e], n2 = ng[2 * TY * nx + e];
+        // x >= nx reads past the row (at most Px floats past ng: the LDS layout pads it) and
+        // is replaced by zero below
+        const unsigned b = opaque_idx((unsigned)(r * nx + x0));
+        const float n0 = ng[b + x1], n1 = ng[TY * nx + b + x1], n2 = ng[2 * TY * nx + b + x1];
         float fa, fb;
         if (nf == 3) {
           fa = pair == 0 ? n0 : n2;
@@ -277,29 +371,35 @@ __global__ __launch_bounds__(kThreadsF) void k_fields_x(
         } else if (pair == 0) { fa = n0 * n0; fb = n1 * n1; }
         else if (pair == 1) { fa = n2 * n2; fb = n0 * n1; }
         else { fa = n0 * n2; fb = n1 * n2; }
-        const int yy = y0 + r;
-        if (dbg_prod && slot == 0 && yy < ny) {
-          const long vox = ((long)z * ny + yy) * nx + x;
-          dbg_prod[(2 * pair) * nv + vox] = fa;
-          if (2 * pair + 1 < nf) dbg_prod[(2 * pair + 1) * nv + vox] = fb;
+        if (dbg_prod) {
+          const int yy = y0 + r;
+          if (slot == 0 && yy < ny && x < nx) {
+            const long vox = ((long)z * ny + yy) * nx + x;
+            dbg_prod[(2 * pair) * nv + vox] = fa;
+            if (2 * pair + 1 < nf) dbg_prod[(2 * pair + 1) * nv + vox] = fb;
+          }
         }
-        return make_float2(fa, fb);
+        return x < nx ? make_float2(fa, fb) : make_float2(0.f, 0.f);
       };
       auto none = [](int, int, int, float2, int) {};
-      fft_io<LC, TY, kThreadsF, false, false, true, WS>(buf, tw, pl, products, none);
+      fft_io<LC, TY, T, false, false, true, WS>(buf, tw, pl, products, none);
       __syncthreads();
       // split the packed transform: Fa = (Z_k + conj Z_{P-k}) / 2, Fb = -i (Z_k - conj Z_{P-k}) / 2
-      for (int e = threadIdx.x; e < TY * H; e += kThreadsF) {
-        const int r = e / H, k = e % H;
-        const int yy = y0 + r;
-        if (yy >= ny) continue;
-        const float2 zk = buf[k * WS + r];
-        const float2 zc = buf[((Px - k) % Px) * WS + r];
-        float2* oa = out + slot * out_slot_stride + (((long)(2 * pair) * nz + z) * ny + yy) * Hp;
-        oa[k] = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y - zc.y));
-        if (2 * pair + 1 < nf) {
-          float2* ob = out + slot * out_slot_stride + (((long)(2 * pair + 1) * nz + z) * ny + yy) * Hp;
-          ob[k] = make_float2(0.5f * (zk.y + zc.y), 0.5f * (zc.x - zk.x));
+      const long long fbase = (long long)nz * ny * Hp;   // elements per field
+      const RView oa(out + slot * out_slot_stride + (2 * pair) * fbase, 8 * fbase);
+      const RView ob(out + slot * out_slot_stride + (2 * pair + 1) * fbase, 2 * pair + 1 < nf ? 8 * fbase : 0);
+      const int row0 = z * ny + y0;
+#pragma unroll
+      for (int u = 0; u < MU; ++u) {
+        const int e = (int)tid + u * T;
+        if (u * T >= TY * H) break;
+        if (e < TY * H) {
+          const int k = bk[u], r = br[u];
+          const float2 zk = buf[k * WS + r];
+          const float2 zc = buf[(k ? Px - k : 0) * WS + r];
+          const uint32_t off = y0 + r < ny ? off2(row0 + r, hp8, k) : kNoOff;
+          oa.st2(off, make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y - zc.y)));
+          if (2 * pair + 1 < nf) ob.st2(off, make_float2(0.5f * (zk.y + zc.y), 0.5f * (zc.x - zk.x)));
         }
       }
       __syncthreads();

@@ -441,13 +441,13 @@ int run_batch(csngf_ctx* c, const float* dB, const uint8_t* dmB, const int* rotq
       if (cmap) {
         ae = allow_lds(k_final_x<true, LC>, lds);
         if (ae == hipSuccess)
-          hipLaunchKernelGGL((k_final_x<true, LC>), grid, dim3(kThreads), lds, c->stream, c->d_buf2, c->d_sat,
+          hipLaunchKernelGGL((k_final_x<true, LC>), grid, dim3(kThreadsC), lds, c->stream, c->d_buf2, c->d_sat,
                              c->d_keys, g, c->Wd[0], c->Wd[1], c->Wd[2], c->H, c->Hp, c->plx, c->d_tw, c->buf2_slot,
                              c->sat_slot, c->count_a, c->gamma, cmap, nmap, c->d_flags, c->flag_slot);
       } else {
         ae = allow_lds(k_final_x<false, LC>, lds);
         if (ae == hipSuccess)
-          hipLaunchKernelGGL((k_final_x<false, LC>), grid, dim3(kThreads), lds, c->stream, c->d_buf2, c->d_sat,
+          hipLaunchKernelGGL((k_final_x<false, LC>), grid, dim3(kThreadsC), lds, c->stream, c->d_buf2, c->d_sat,
                              c->d_keys, g, c->Wd[0], c->Wd[1], c->Wd[2], c->H, c->Hp, c->plx, c->d_tw, c->buf2_slot,
                              c->sat_slot, c->count_a, c->gamma, cmap, nmap, c->d_flags, c->flag_slot);
       }

@@ -36,6 +36,9 @@ constexpr int kTileW = 16;     // adjacent x-bins per pencil tile in the z pass 
 #ifndef CSNGF_TZ
 #define CSNGF_TZ 512
 #endif
+#ifndef CSNGF_TC
+#define CSNGF_TC 512
+#endif
 #ifndef CSNGF_WPF
 #define CSNGF_WPF 16
 #endif
@@ -44,6 +47,8 @@ constexpr int kTileW = 16;     // adjacent x-bins per pencil tile in the z pass 
 #endif
 constexpr int kThreadsF = CSNGF_TF;  // field stage (x pass)
 constexpr int kThreadsZ = CSNGF_TZ;  // z pass
+constexpr int kThreadsC = CSNGF_TC;  // final x pass (C2R, normalisation, argmax)
+static_assert(kThreadsC % 256 == 0, "the final pass maps 256 threads per D row");
 template <bool INV>
 constexpr int kThreadsP = INV ? CSNGF_TPI : CSNGF_TPF;  // y pencil passes (forward, inverse)
 template <bool INV>
@@ -97,6 +102,9 @@ struct RView {
   }
   __device__ __forceinline__ void st1(uint32_t off, unsigned char x) const {
     __builtin_amdgcn_raw_buffer_store_b8(x, r, (int)off, 0, 0);
+  }
+  __device__ __forceinline__ int ldi(uint32_t off) const {
+    return (int)__builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0);
   }
   // float at byte offset off + soff (soff: a workgroup-uniform offset held in a scalar register)
   __device__ __forceinline__ float ldf(uint32_t off, uint32_t soff = 0) const {
@@ -691,16 +699,17 @@ __global__ __launch_bounds__(kThreads) void k_bounds(const int* __restrict__ sat
 // Overlaps: for a fixed-side box, N(chi) = D(hx + 1) - D(lx) where D(x) is the 4-corner
 // combination of the SAT over the row's z and y ranges; D rows are built in LDS first.
 template <bool WRITE_MAP, int LC>
-__global__ __launch_bounds__(kThreads) void k_final_x(
+__global__ __launch_bounds__(kThreadsC) void k_final_x(
     const float2* __restrict__ Y4, const int* __restrict__ sat, unsigned long long* __restrict__ keys,
     OverlapGeom g, int Wx, int Wy, int Wz, int H, int Hp, FftPlan pl, const float2* __restrict__ twtab,
     long long y4_sstride, long long sat_sstride, long long count_a, float gamma,
     float* __restrict__ cmap, long long* __restrict__ nmap, const uint8_t* __restrict__ flags,
     long long flag_sstride) {
+  constexpr int T = kThreadsC;
   constexpr int WP = kRowsX;  // packed pencils
   constexpr int NR = 2 * WP;  // output rows
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ unsigned long long red[kThreads / 64];
+  __shared__ unsigned long long red[T / 64];
   const int Px = pl.L;
   const int X1 = g.nB[0] + 1;
   float2* tw = reinterpret_cast<float2*>(smem);
@@ -719,51 +728,51 @@ __global__ __launch_bounds__(kThreads) void k_final_x(
     if (!any) return;
   }
   load_twiddles(tw, twtab, pl);
-  const float2* rows = Y4 + slot * y4_sstride + ((long long)zc * Wy) * Hp;
   const int half = Px / 2;
   // D rows: for row rr (yc = yc0 + rr), D(x) = sum of the SAT over the row's z and y ranges
-  // up to column x (x = 0 .. nB_x); empty ranges give D = 0.
-  const int X = X1, Y = g.nB[1] + 1;
-  const int cz = zc - (g.nA[2] - 1);
-  const int lz = max(1 + cz, 0), hz = min(g.nA[2] - 2 + cz, g.nB[2] - 1);
-  for (int base = 0; base < NR * X1; base += 4 * kThreads) {
-    int d[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = base + u * kThreads + (int)threadIdx.x;
-      d[u] = 0;
-      if (e < NR * X1) {
-        const int rr = e / X1, x = e % X1;
-        const int cy = yc0 + rr - (g.nA[1] - 1);
-        const int ly = max(1 + cy, 0), hy = min(g.nA[1] - 2 + cy, g.nB[1] - 1);
-        if (lz <= hz && ly <= hy && yc0 + rr < Wy) {
-          const long long zh = (long long)(hz + 1) * Y, zl = (long long)lz * Y;
-          d[u] = s[(zh + hy + 1) * X + x] - s[(zl + hy + 1) * X + x] - s[(zh + ly) * X + x] + s[(zl + ly) * X + x];
-        }
+  // up to column x (x = 0 .. nB_x); empty ranges give D = 0.  Rows go to groups of 256
+  // threads, columns to the threads of a group.
+  {
+    const int X = X1, Y = g.nB[1] + 1;
+    const int cz = zc - (g.nA[2] - 1);
+    const int lz = max(1 + cz, 0), hz = min(g.nA[2] - 2 + cz, g.nB[2] - 1);
+    const RView sv(s, 4LL * (g.nB[2] + 1) * Y * X);
+    for (int rr = (int)threadIdx.x / 256; rr < NR; rr += T / 256) {
+      const int cy = yc0 + rr - (g.nA[1] - 1);
+      const int ly = max(1 + cy, 0), hy = min(g.nA[1] - 2 + cy, g.nB[1] - 1);
+      const bool any = lz <= hz && ly <= hy && yc0 + rr < Wy;
+      // byte offsets of the 4 SAT rows (the SAT of one slot is far below 2 GiB)
+      const uint32_t a = any ? 4u * (uint32_t)(((hz + 1) * Y + hy + 1) * X) : kNoOff;
+      const uint32_t b = any ? 4u * (uint32_t)((lz * Y + hy + 1) * X) : kNoOff;
+      const uint32_t c = any ? 4u * (uint32_t)(((hz + 1) * Y + ly) * X) : kNoOff;
+      const uint32_t d = any ? 4u * (uint32_t)((lz * Y + ly) * X) : kNoOff;
+      for (int x = (int)threadIdx.x % 256; x < X1; x += 256) {
+        const uint32_t x4 = 4u * x;
+        const int v = sv.ldi(a + x4) - sv.ldi(b + x4) - sv.ldi(c + x4) + sv.ldi(d + x4);
+        drow[rr * X1 + x] = any ? v : 0;
       }
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = base + u * kThreads + (int)threadIdx.x;
-      if (e < NR * X1) drow[e] = d[u];
     }
   }
   const long long count_b = s[(long long)(g.nB[2] + 1) * (g.nB[1] + 1) * (g.nB[0] + 1) - 1];
   const long long thr = threshold(count_a, count_b, gamma);
   if (LC == 0) __syncthreads();
   unsigned long long best = 0ull;
+  const RView rows(Y4 + slot * y4_sstride + ((long long)zc * Wy) * Hp, 8LL * Wy * Hp);  // rows >= Wy load zero
+  const RView rflag(rowfl, Wy);
+  const uint32_t hp8 = 8u * (uint32_t)Hp;
   auto pack = [&](int k0, int k1, int p) -> float2 {
     const int k = k0 + k1;
     const int r0 = yc0 + 2 * p, r1 = r0 + 1;
     const int kk = k <= half ? k : Px - k;
-    const float2 a = (r0 < Wy && rowfl[r0]) ? rows[(long long)r0 * Hp + kk] : make_float2(0.f, 0.f);
-    const float2 c = (r1 < Wy && rowfl[r1]) ? rows[(long long)r1 * Hp + kk] : make_float2(0.f, 0.f);
+    const float2 a = rows.ld2(rflag.ld1(r0) ? off2(r0, hp8, kk) : kNoOff);
+    const float2 c = rows.ld2(rflag.ld1(r1) ? off2(r1, hp8, kk) : kNoOff);
     if (k == 0 || k == half) return make_float2(a.x, c.x);
     if (k < half) return make_float2(a.x - c.y, a.y + c.x);  // S1 + i S2
     return make_float2(a.x + c.y, c.x - a.y);                // conj(S1) + i conj(S2)
   };
   auto emit = [&](int j0, int j1, int p, float2 zv, int) {
-    const int cx = (j0 + j1 + g.nA[0] - 1) % Px;
+    int cx = j0 + j1 + g.nA[0] - 1;   // < 2 Px
+    if (cx >= Px) cx -= Px;
     if (cx >= Wx) return;
     const int chx = cx - (g.nA[0] - 1);
     const int lx = max(1 + chx, 0), hx = min(g.nA[0] - 2 + chx, g.nB[0] - 1);
@@ -788,7 +797,7 @@ __global__ __launch_bounds__(kThreads) void k_final_x(
       }
     }
   };
-  fft_io<LC, WP, kThreads, true, false, false>(buf, tw, pl, pack, emit);
+  fft_io<LC, WP, T, true, false, false>(buf, tw, pl, pack, emit);
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) {
     const unsigned long long o = __shfl_xor(best, d, 64);
@@ -798,7 +807,7 @@ __global__ __launch_bounds__(kThreads) void k_final_x(
   __syncthreads();
   if (threadIdx.x == 0) {
     unsigned long long m = red[0];
-    for (int w = 1; w < kThreads / 64; ++w) m = red[w] > m ? red[w] : m;
+    for (int w = 1; w < T / 64; ++w) m = red[w] > m ? red[w] : m;
     if (m) atomicMax(keys + slot, m);
   }
 }

@@ -348,18 +348,22 @@ int launch_fields(csngf_ctx* c, bool moving, const float* vol, const uint8_t* um
   if (lds > kLdsMax) return fail(CSNGF_E_UNSUPPORTED, "x extent too large for the field stage");
   hipError_t ae = hipSuccess;
   hipEvent_t ev = prof_begin(c);
+  // inputs x >= Px/2 are zero when nx <= Px/2: the transform's first stage is pruned
+  const bool half = 2 * n3[0] <= c->plx.L;
   with_len(c->plx.L, [&](auto lc) {
     constexpr int LC = decltype(lc)::value;
+    auto go = [&](auto kern) {
+      ae = allow_lds(kern, lds);
+      if (ae == hipSuccess)
+        hipLaunchKernelGGL(kern, grid, dim3(kThreadsF), lds, c->stream, vol, um, n3[0], n3[1], n3[2], tz, slots, c->nf,
+                           rotq, c->eps, c->plx, c->d_tw, out, c->H, c->Hp, out_slot, mask_out, mask_slot, dbg);
+    };
     if (moving) {
-      ae = allow_lds(k_fields_x<true, LC>, lds);
-      if (ae == hipSuccess)
-        hipLaunchKernelGGL((k_fields_x<true, LC>), grid, dim3(kThreadsF), lds, c->stream, vol, um, n3[0], n3[1], n3[2],
-                           tz, slots, c->nf, rotq, c->eps, c->plx, c->d_tw, out, c->H, c->Hp, out_slot, mask_out, mask_slot, dbg);
+      if (half) go(k_fields_x<true, LC, true>);
+      else go(k_fields_x<true, LC, false>);
     } else {
-      ae = allow_lds(k_fields_x<false, LC>, lds);
-      if (ae == hipSuccess)
-        hipLaunchKernelGGL((k_fields_x<false, LC>), grid, dim3(kThreadsF), lds, c->stream, vol, um, n3[0], n3[1], n3[2],
-                           tz, slots, c->nf, rotq, c->eps, c->plx, c->d_tw, out, c->H, c->Hp, out_slot, mask_out, mask_slot, dbg);
+      if (half) go(k_fields_x<false, LC, true>);
+      else go(k_fields_x<false, LC, false>);
     }
   });
   prof_end(c, KT_FIELDS, ev);
@@ -412,11 +416,17 @@ int run_batch(csngf_ctx* c, const float* dB, const uint8_t* dmB, const int* rotq
     const size_t lds = lds_pencil(c->plz.L);
     const int out_off = c->P[2] - (c->nA[2] - 1);
     ev = prof_begin(c);
+    // inputs z >= Pz/2 are zero when nz <= Pz/2: the forward transforms' first stage is pruned
+    const bool half = 2 * c->nB[2] <= c->plz.L;
     with_len(c->plz.L, [&](auto lc) {
       constexpr int LC = decltype(lc)::value;
-      hipLaunchKernelGGL((k_zpass<LC>), dim3(nb8), dim3(kThreadsZ), lds, c->stream, c->d_buf2, c->d_spec, c->d_buf1,
-                         c->nB[2], c->P[1], c->H, c->Hp, c->Wd[2], out_off, c->plz, c->d_tw, c->buf2_slot,
-                         c->buf1_slot, c->tiles, slots, nreal, c->d_flags, c->flag_slot, c->nf);
+      auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(nb8), dim3(kThreadsZ), lds, c->stream, c->d_buf2, c->d_spec, c->d_buf1, c->nB[2],
+                           c->P[1], c->H, c->Hp, c->Wd[2], out_off, c->plz, c->d_tw, c->buf2_slot, c->buf1_slot,
+                           c->tiles, slots, nreal, c->d_flags, c->flag_slot, c->nf);
+      };
+      if (half) go(k_zpass<LC, true>);
+      else go(k_zpass<LC, false>);
     });
     prof_end(c, KT_ZPASS, ev);
     LAUNCHCHK("k_zpass");

@@ -39,32 +39,49 @@ __device__ __forceinline__ float2 rot_i(float2 a) {
 }
 
 // ---------------------------------------------------------------- small DFTs
-template <bool INV>
-__device__ __forceinline__ void dft2(float2* x) {
-  float2 a = x[0], b = x[1];
-  x[0] = cadd(a, b);
-  x[1] = csub(a, b);
+// NZ: inputs x[m] with m >= NZ are known to be zero (the first stage of a zero-padded
+// transform), so the sums and differences that involve them are skipped.
+template <int NZ, int M>
+__device__ __forceinline__ float2 add_nz(const float2* x, int a) {  // x[a] + x[M] with x[M] maybe zero
+  return M >= NZ ? x[a] : cadd(x[a], x[M]);
+}
+template <int NZ, int M>
+__device__ __forceinline__ float2 sub_nz(const float2* x, int a) {  // x[a] - x[M] with x[M] maybe zero
+  return M >= NZ ? x[a] : csub(x[a], x[M]);
 }
 
-template <bool INV>
+template <bool INV, int NZ = 2>
+__device__ __forceinline__ void dft2(float2* x) {
+  float2 a = x[0];
+  x[0] = add_nz<NZ, 1>(x, 0);
+  x[1] = NZ > 1 ? csub(a, x[1]) : a;
+}
+
+template <bool INV, int NZ = 4>
 __device__ __forceinline__ void dft4(float2* x) {
-  float2 t0 = cadd(x[0], x[2]), t1 = csub(x[0], x[2]);
-  float2 t2 = cadd(x[1], x[3]), t3 = rot_i<INV>(csub(x[1], x[3]));
+  float2 t0 = add_nz<NZ, 2>(x, 0), t1 = sub_nz<NZ, 2>(x, 0);
+  float2 t2, t3;
+  if constexpr (NZ > 1) {
+    t2 = add_nz<NZ, 3>(x, 1);
+    t3 = rot_i<INV>(sub_nz<NZ, 3>(x, 1));
+  } else {
+    t2 = t3 = make_float2(0.f, 0.f);
+  }
   x[0] = cadd(t0, t2);
   x[2] = csub(t0, t2);
   x[1] = cadd(t1, t3);
   x[3] = csub(t1, t3);
 }
 
-template <bool INV>
+template <bool INV, int NZ = 8>
 __device__ __forceinline__ void dft8(float2* x) {
+  static_assert(NZ >= 4, "dft8 prunes at most its upper half");
   constexpr float h = 0.70710678118654752f;
   float2 a[4], b[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    a[k] = cadd(x[k], x[k + 4]);
-    b[k] = csub(x[k], x[k + 4]);
-  }
+  a[0] = add_nz<NZ, 4>(x, 0); b[0] = sub_nz<NZ, 4>(x, 0);
+  a[1] = add_nz<NZ, 5>(x, 1); b[1] = sub_nz<NZ, 5>(x, 1);
+  a[2] = add_nz<NZ, 6>(x, 2); b[2] = sub_nz<NZ, 6>(x, 2);
+  a[3] = add_nz<NZ, 7>(x, 3); b[3] = sub_nz<NZ, 7>(x, 3);
   // b[k] *= W8^k  (W8 = exp(-i pi/4) forward, conjugate inverse)
   b[1] = INV ? make_float2(h * (b[1].x - b[1].y), h * (b[1].x + b[1].y))
              : make_float2(h * (b[1].x + b[1].y), h * (b[1].y - b[1].x));
@@ -103,15 +120,17 @@ template <> struct OddRoots<11> {
 
 // Odd prime R: pair x_m with x_{R-m}; y_k = A_k -+ i B_k, y_{R-k} = A_k +- i B_k with
 // A_k = x_0 + sum_m (x_m + x_{R-m}) cos(2 pi k m / R), B_k = sum_m (x_m - x_{R-m}) sin(..).
-template <int R, bool INV>
+template <int R, bool INV, int NZ = R>
 __device__ __forceinline__ void dft_odd(float2* x) {
   constexpr int h = (R - 1) / 2;
+  static_assert(NZ > h, "dft_odd prunes at most its upper half");
   float2 a[h + 1], b[h + 1];
   float2 y0 = x[0];
 #pragma unroll
   for (int m = 1; m <= h; ++m) {
-    a[m] = cadd(x[m], x[R - m]);
-    b[m] = csub(x[m], x[R - m]);
+    const bool upper_zero = R - m >= NZ;   // compile time after unrolling
+    a[m] = upper_zero ? x[m] : cadd(x[m], x[R - m]);
+    b[m] = upper_zero ? x[m] : csub(x[m], x[R - m]);
     y0 = cadd(y0, a[m]);
   }
   float2 out[R];
@@ -142,12 +161,12 @@ __device__ __forceinline__ void dft_odd(float2* x) {
   for (int k = 0; k < R; ++k) x[k] = out[k];
 }
 
-template <int R, bool INV>
+template <int R, bool INV, int NZ = R>
 __device__ __forceinline__ void dft(float2* x) {
-  if constexpr (R == 2) dft2<INV>(x);
-  else if constexpr (R == 4) dft4<INV>(x);
-  else if constexpr (R == 8) dft8<INV>(x);
-  else dft_odd<R, INV>(x);
+  if constexpr (R == 2) dft2<INV, NZ>(x);
+  else if constexpr (R == 4) dft4<INV, NZ>(x);
+  else if constexpr (R == 8) dft8<INV, NZ>(x);
+  else dft_odd<R, INV, NZ>(x);
 }
 
 // ---------------------------------------------------------------- one Stockham stage
@@ -336,7 +355,8 @@ __device__ __forceinline__ unsigned opaque_idx(unsigned x) {
   return x;
 }
 
-template <int L, int R, int NS, int W, int WS, int WSO, int T, bool INV, bool FROM_LD, bool TO_ST, typename LD, typename ST>
+template <int L, int R, int NS, int W, int WS, int WSO, int T, bool INV, bool FROM_LD, bool TO_ST, int NZ, typename LD,
+          typename ST>
 __device__ __forceinline__ void fft_stage_io(float2* __restrict__ buf, const float2* __restrict__ tw, LD& ld, ST& st) {
   const unsigned tx = opaque_tid();
   constexpr int LR = L / R;
@@ -353,7 +373,7 @@ __device__ __forceinline__ void fft_stage_io(float2* __restrict__ buf, const flo
         v[t] = cmul(v[t], w);
       }
     }
-    dft<R, INV>(v);
+    dft<R, INV, NZ>(v);
     const unsigned base = q * NS * R + k;
     if constexpr (TO_ST) {
 #pragma unroll
@@ -375,7 +395,7 @@ __device__ __forceinline__ void fft_stage_io(float2* __restrict__ buf, const flo
         float2 v[R];
         if constexpr (FROM_LD) {
 #pragma unroll
-          for (int t = 0; t < R; ++t) v[t] = ld(j, t * LR, p);
+          for (int t = 0; t < R; ++t) v[t] = t < NZ ? ld(j, t * LR, p) : make_float2(0.f, 0.f);
         } else {
           const unsigned rb = opaque_idx(j * WS + p);
 #pragma unroll
@@ -407,15 +427,18 @@ __device__ __forceinline__ void fft_stage_io(float2* __restrict__ buf, const flo
   if constexpr (!TO_ST) __syncthreads();
 }
 
-template <int L, int S, int W, int WS, int WSO, int T, bool INV, bool IN_LDS, bool OUT_LDS, typename LD, typename ST>
+template <int L, int S, int W, int WS, int WSO, int T, bool INV, bool IN_LDS, bool OUT_LDS, bool HALF, typename LD,
+          typename ST>
 __device__ __forceinline__ void fft_io_stages(float2* __restrict__ buf, const float2* __restrict__ tw, LD& ld, ST& st) {
   constexpr CPlan P = make_cplan(L);
   if constexpr (S < P.nst) {
     constexpr bool first = (S == 0), last = (S + 1 == P.nst);
+    // HALF: inputs i >= L/2 are zero, so the first stage's inputs t >= ceil(R/2) vanish
+    constexpr int NZ = (first && HALF) ? (P.r[S] + 1) / 2 : P.r[S];
     // the last stage writes its LDS output with row stride WSO, every other write uses WS
-    fft_stage_io<L, P.r[S], P.ns[S], W, WS, (last ? WSO : WS), T, INV, first && !IN_LDS, last && !OUT_LDS>(buf, tw,
-                                                                                                           ld, st);
-    fft_io_stages<L, S + 1, W, WS, WSO, T, INV, IN_LDS, OUT_LDS>(buf, tw, ld, st);
+    fft_stage_io<L, P.r[S], P.ns[S], W, WS, (last ? WSO : WS), T, INV, first && !IN_LDS, last && !OUT_LDS, NZ>(
+        buf, tw, ld, st);
+    fft_io_stages<L, S + 1, W, WS, WSO, T, INV, IN_LDS, OUT_LDS, HALF>(buf, tw, ld, st);
   }
 }
 
@@ -458,12 +481,15 @@ constexpr int consumer_slots() {
 // LC > 0: compile-time plan with fused I/O.  LC == 0: run-time plan: the producer fills buf,
 // the LDS transform runs, and the consumer reads buf (slot = position in the thread's loop).
 // WSO: row stride of the final LDS result (OUT_LDS), e.g. padded for a transposing reader.
-template <int LC, int W, int T, bool INV, bool IN_LDS, bool OUT_LDS, int WSO = W, typename LD, typename ST>
+// HALF (compile-time plans, producer input): the producer's inputs i >= L/2 are zero and
+// are neither requested nor added.
+template <int LC, int W, int T, bool INV, bool IN_LDS, bool OUT_LDS, int WSO = W, bool HALF = false, typename LD,
+          typename ST>
 __device__ __forceinline__ void fft_io(float2* __restrict__ buf, const float2* __restrict__ tw, const FftPlan& pl,
                                        LD&& ld, ST&& st) {
   static_assert(LC > 0 || WSO == W, "a padded result needs a compile-time plan");
   if constexpr (LC > 0) {
-    fft_io_stages<LC, 0, W, W, WSO, T, INV, IN_LDS, OUT_LDS>(buf, tw, ld, st);
+    fft_io_stages<LC, 0, W, W, WSO, T, INV, IN_LDS, OUT_LDS, HALF && !IN_LDS>(buf, tw, ld, st);
   } else {
     const int L = pl.L;
     if constexpr (!IN_LDS) {

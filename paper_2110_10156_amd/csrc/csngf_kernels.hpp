@@ -131,13 +131,14 @@ __device__ __forceinline__ uint32_t off2(int row, uint32_t rs8, int col) {
 // (re = first field, im = second), the transform runs along x (length Px, zero padded from
 // nx) and the result is split into two half spectra.
 //
+// HALF: nx <= Px / 2, so the transform's inputs x >= Px / 2 are known zero (first stage pruned).
 // Every strided loop visits the same elements in every plane, so each thread decodes its
 // elements' (x, row) once; for the moving side it also keeps the z-independent part of each
 // element's source coordinate, so a plane costs 3 integer adds per sample before the gather.
 template <int LC>
 constexpr int xrow_stride() { return LC > 0 ? kRowsX + 1 : kRowsX; }
 
-template <bool MOVING, int LC>
+template <bool MOVING, int LC, bool HALF>
 __global__ __launch_bounds__(kThreadsF) void k_fields_x(
     const float* __restrict__ vol, const uint8_t* __restrict__ umask, int nx, int ny, int nz, int tz, int nslots,
     int nf, const int* __restrict__ rotq, float eps, FftPlan pl, const float2* __restrict__ twtab,
@@ -390,7 +391,7 @@ __global__ __launch_bounds__(kThreadsF) void k_fields_x(
         return x < nx ? make_float2(fa, fb) : make_float2(0.f, 0.f);
       };
       auto none = [](int, int, int, float2, int) {};
-      fft_io<LC, TY, T, false, false, true, WS>(buf, tw, pl, products, none);
+      fft_io<LC, TY, T, false, false, true, WS, HALF>(buf, tw, pl, products, none);
       __syncthreads();
       // split the packed transform: Fa = (Z_k + conj Z_{P-k}) / 2, Fb = -i (Z_k - conj Z_{P-k}) / 2
       const long long fbase = (long long)nz * ny * Hp;   // elements per field
@@ -465,7 +466,7 @@ __global__ __launch_bounds__(kThreadsP<INV>) void k_pencil(
 // the multiply-accumulate against A's conjugate spectrum done on the last stage's
 // registers; then the sum goes through LDS once for the z inverse, whose last stage
 // stores the kept displacement rows.
-template <int LC>
+template <int LC, bool HALF>
 __global__ __launch_bounds__(kThreadsZ) void k_zpass(
     const float2* __restrict__ X2, const float2* __restrict__ spec, float2* __restrict__ Y3,
     int nz, int Py, int H, int Hp, int Wz, int out_off, FftPlan pl, const float2* __restrict__ twtab,
@@ -503,7 +504,7 @@ __global__ __launch_bounds__(kThreadsZ) void k_zpass(
     // it and load zero) and A's spectrum; masked columns load zero and are never stored
     const RView src(X2 + slot * x2_sstride + f * fstride_x2 + col0, 8 * (fstride_x2 - col0));
     const RView a(spec + f * fstride_sp + col0, 8 * (fstride_sp - col0));
-    fft_io<LC, W, kThreadsZ, false, false, false>(
+    fft_io<LC, W, kThreadsZ, false, false, false, W, HALF>(
         buf, tw, pl,
         [&](int i0, int i1, int p) -> float2 {
           const uint32_t b = kx0 + p < H ? off2(i0, zs8, p) : kNoOff;

@@ -325,14 +325,16 @@ int launch_pencil(csngf_ctx* c, bool inv, const float2* in, float2* out, int n_i
   const dim3 grid((c->H + W - 1) / W, groups, slots);
   const size_t lds = lds_pencil(pl.L, W);
   hipEvent_t ev = prof_begin(c);
+  const bool half = 2 * n_in <= pl.L;  // inputs i >= L/2 are zero: first stage pruned
   with_len(pl.L, [&](auto lc) {
     constexpr int LC = decltype(lc)::value;
-    if (!inv)
-      hipLaunchKernelGGL((k_pencil<false, LC>), grid, dim3(kThreadsP<false>), lds, c->stream, in, out, n_in, n_out, out_off,
-                         pl, c->d_tw, c->H, c->Hp, in_g, out_g, in_s, out_s, flags, flag_s, groups);
-    else
-      hipLaunchKernelGGL((k_pencil<true, LC>), grid, dim3(kThreadsP<true>), lds, c->stream, in, out, n_in, n_out, out_off,
-                         pl, c->d_tw, c->H, c->Hp, in_g, out_g, in_s, out_s, flags, flag_s, groups);
+    auto go = [&](auto kern, int threads) {
+      hipLaunchKernelGGL(kern, grid, dim3(threads), lds, c->stream, in, out, n_in, n_out, out_off, pl, c->d_tw, c->H,
+                         c->Hp, in_g, out_g, in_s, out_s, flags, flag_s, groups);
+    };
+    if (inv) go(k_pencil<true, LC, false>, kThreadsP<true>);
+    else if (half) go(k_pencil<false, LC, true>, kThreadsP<false>);
+    else go(k_pencil<false, LC, false>, kThreadsP<false>);
   });
   prof_end(c, inv ? KT_YINV : KT_YFWD, ev);
   LAUNCHCHK(inv ? "k_pencil<inverse>" : "k_pencil<forward>");

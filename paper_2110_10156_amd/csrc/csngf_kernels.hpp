@@ -418,8 +418,9 @@ __global__ __launch_bounds__(kThreadsF) void k_fields_x(
 
 // ------------------------------------------------------------------------------ y passes
 // Pencils along the middle axis.  Workgroup (x-tile, group g, slot): input rows i < n_in of
-// in[g], zero beyond; output row c takes transform row (c + out_off) mod L.
-template <bool INV, int LC>
+// in[g], zero beyond; output row c takes transform row (c + out_off) mod L.  HALF: n_in <= L/2
+// (first stage pruned).
+template <bool INV, int LC, bool HALF>
 __global__ __launch_bounds__(kThreadsP<INV>) void k_pencil(
     const float2* __restrict__ in, float2* __restrict__ out, int n_in, int n_out, int out_off,
     FftPlan pl, const float2* __restrict__ twtab, int H, int Hp, long long in_gstride,
@@ -446,7 +447,7 @@ __global__ __launch_bounds__(kThreadsP<INV>) void k_pencil(
   if (LC == 0) __syncthreads();
   // rows i >= n_in lie past the input view and load zero; rows c >= n_out past the output
   // view (and its flag view) and are dropped; columns >= H are masked by kNoOff
-  fft_io<LC, W, kThreadsP<INV>, INV, false, false>(
+  fft_io<LC, W, kThreadsP<INV>, INV, false, false, W, HALF>(
       buf, tw, pl,
       [&](int i0, int i1, int p) -> float2 {
         const uint32_t b = kx0 + p < H ? off2(i0, rs8, p) : kNoOff;

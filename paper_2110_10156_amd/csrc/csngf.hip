@@ -99,7 +99,10 @@ size_t lds_fields(int Px, int nx) {
 }
 
 // slices per field-stage workgroup (z march); each new slice costs one resampled halo plane
-constexpr int kSlicesX = 8;
+#ifndef CSNGF_SLICES
+#define CSNGF_SLICES 8
+#endif
+constexpr int kSlicesX = CSNGF_SLICES;
 size_t lds_pencil(int L, int W = kTileW) { return a16(sizeof(float2) * L) + a16(sizeof(float2) * L * W); }
 size_t lds_final(int Px, int nxB) {
   return a16(sizeof(float2) * Px) + a16(sizeof(float2) * Px * (kRowsX + 1)) + a16(sizeof(int) * 2 * kRowsX * (nxB + 1));
@@ -185,6 +188,10 @@ struct csngf_ctx {
   long long mask_slot = 0;
   int* d_sat = nullptr;
   long long sat_slot = 0;
+  // per-slice 2-D prefix sums of the mask (SAT step 1): lives in buf2, which is free
+  // between the field stage and the y forward pass
+  uint32_t* d_plane = nullptr;
+  long long plane_slot = 0;
   uint8_t* d_flags = nullptr;
   long long flag_slot = 0;
   unsigned long long* d_keys = nullptr;
@@ -390,13 +397,10 @@ int run_batch(csngf_ctx* c, const float* dB, const uint8_t* dmB, const int* rotq
   {
     const int nx = c->nB[0], ny = c->nB[1], nz = c->nB[2];
     ev = prof_begin(c);
-    const int rows = (nz + 1) * (ny + 1);
-    hipLaunchKernelGGL(k_sat_rows, dim3((rows + 3) / 4, slots), dim3(kThreads), 0, c->stream, c->d_mask, c->d_sat,
-                       nx, ny, nz, c->mask_slot, c->sat_slot);
-    hipLaunchKernelGGL(k_sat_cols, dim3((nz * nx + kThreads - 1) / kThreads, slots), dim3(kThreads), 0, c->stream,
-                       c->d_sat, nx, ny, nz, c->sat_slot, 0);
-    hipLaunchKernelGGL(k_sat_cols, dim3((ny * nx + kThreads - 1) / kThreads, slots), dim3(kThreads), 0, c->stream,
-                       c->d_sat, nx, ny, nz, c->sat_slot, 1);
+    hipLaunchKernelGGL(k_sat_planes, dim3(nz, slots), dim3(kSatThreads), 0, c->stream, c->d_mask, c->d_plane, nx, ny,
+                       c->mask_slot, c->plane_slot);
+    hipLaunchKernelGGL(k_sat_z, dim3(((nx + 1) * (ny + 1) + kThreads - 1) / kThreads, slots), dim3(kThreads), 0,
+                       c->stream, c->d_plane, c->d_sat, nx, ny, nz, c->plane_slot, c->sat_slot);
     OverlapGeom g;
     for (int i = 0; i < 3; ++i) {
       g.nA[i] = c->nA[i];
@@ -752,6 +756,8 @@ int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims
     c->batch = batch;
     if ((rc = dalloc(&c->d_buf1, sizeof(float2) * c->buf1_slot * batch))) return bail(rc);
     if ((rc = dalloc(&c->d_buf2, sizeof(float2) * c->buf2_slot * batch))) return bail(rc);
+    c->d_plane = reinterpret_cast<uint32_t*>(c->d_buf2);
+    c->plane_slot = 2 * c->buf2_slot;   // >= nz * ny * nx uint32 per slot
     if ((rc = dalloc(&c->d_mask, (size_t)c->mask_slot * batch))) return bail(rc);
     if ((rc = dalloc(&c->d_sat, 4 * (size_t)c->sat_slot * batch))) return bail(rc);
     if ((rc = dalloc(&c->d_flags, (size_t)c->flag_slot * batch))) return bail(rc);

@@ -572,61 +572,78 @@ __global__ __launch_bounds__(kThreads) void k_zstore(
 // ------------------------------------------------------------------------------ overlap SAT
 // sat[slot][(nz+1)][(ny+1)][(nx+1)], zero on index 0 of every axis:
 // sat[z+1][y+1][x+1] = sum of mask over [0..z] x [0..y] x [0..x].
-// Step 1: one wave per row of the padded table, prefix over x (zero rows for index 0).
-__global__ __launch_bounds__(kThreads) void k_sat_rows(const uint8_t* __restrict__ mask, int* __restrict__ sat,
-                                                       int nx, int ny, int nz, long long mask_sstride,
-                                                       long long sat_sstride) {
-  const int lane = threadIdx.x & 63;
-  const int row = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
-  const int slot = blockIdx.y;
-  const int rows = (nz + 1) * (ny + 1);
-  if (row >= rows) return;
-  const int zz = row / (ny + 1), yy = row % (ny + 1);
-  int* dst = sat + slot * sat_sstride + (long long)row * (nx + 1);
-  if (zz == 0 || yy == 0) {
-    for (int x = lane; x <= nx; x += 64) dst[x] = 0;
-    return;
-  }
-  const uint8_t* src = mask + slot * mask_sstride + ((long long)(zz - 1) * ny + (yy - 1)) * nx;
-  if (lane == 0) dst[0] = 0;
-  int carry = 0;
-  for (int x0 = 0; x0 < nx; x0 += 64) {
-    const int x = x0 + lane;
-    int v = (x < nx) ? (int)src[x] : 0;
+// Step 1 (one workgroup per z slice): the slice's 2-D inclusive prefix over (y, x),
+// plane[slot][z][y][x].  Rows go to the waves (a wave scan per row), then each thread walks
+// its column down a group of rows.
+constexpr int kSatThreads = 512;
+__global__ __launch_bounds__(kSatThreads) void k_sat_planes(const uint8_t* __restrict__ mask,
+                                                            uint32_t* __restrict__ plane, int nx, int ny,
+                                                            long long mask_sstride, long long plane_sstride) {
+  constexpr int NW = kSatThreads / 64;  // rows per group
+  __shared__ uint32_t rows[NW][kMaxLen];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int z = blockIdx.x, slot = blockIdx.y;
+  const long long off = (long long)z * ny * nx;
+  const RView m(mask + slot * mask_sstride + off, (long long)ny * nx);
+  uint32_t* out = plane + slot * plane_sstride + off;
+  uint32_t col = 0;  // running column sum of thread x = threadIdx.x (nx <= kMaxLen = kSatThreads)
+  for (int y0 = 0; y0 < ny; y0 += NW) {
+    const int y = y0 + wave;
+    if (y < ny) {
+      uint32_t carry = 0;
+      for (int x0 = 0; x0 < nx; x0 += 64) {
+        const int x = x0 + lane;
+        uint32_t v = m.ld1(x < nx ? (unsigned)(y * nx + x) : kNoOff);  // 0 past the row
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const int t = __shfl_up(v, d, 64);
-      if (lane >= d) v += t;
+        for (int d = 1; d < 64; d <<= 1) {
+          const uint32_t t = __shfl_up(v, d, 64);
+          if (lane >= d) v += t;
+        }
+        if (x < nx) rows[wave][x] = carry + v;
+        carry += __shfl(v, 63, 64);
+      }
     }
-    if (x < nx) dst[x + 1] = carry + v;
-    carry += __shfl(v, 63, 64);
+    __syncthreads();
+    const int x = threadIdx.x;
+    if (x < nx) {
+      for (int r = 0; r < NW && y0 + r < ny; ++r) {
+        col += rows[r][x];
+        out[(long long)(y0 + r) * nx + x] = col;
+      }
+    }
+    __syncthreads();
   }
 }
 
-// Step 2: prefix over y for every (z, x) column; step 3: prefix over z for every (y, x).
-__global__ __launch_bounds__(kThreads) void k_sat_cols(int* __restrict__ sat, int nx, int ny, int nz,
-                                                       long long sat_sstride, int along_z) {
+// Step 2: prefix over z for every (y, x), written with the zero borders.  Each column is read
+// SU planes at a time, all loads issued before the running sum stores them.
+__global__ __launch_bounds__(kThreads) void k_sat_z(const uint32_t* __restrict__ plane, int* __restrict__ sat,
+                                                    int nx, int ny, int nz, long long plane_sstride,
+                                                    long long sat_sstride) {
+  constexpr int SU = 16;
   const int slot = blockIdx.y;
-  const int t = blockIdx.x * kThreads + threadIdx.x;
   const int X = nx + 1, Y = ny + 1;
-  int* s = sat + slot * sat_sstride;
-  if (!along_z) {
-    if (t >= nz * nx) return;
-    const int zz = 1 + t / nx, x = 1 + t % nx;
-    int* p = s + (long long)zz * Y * X + x;
-    int run = 0;
-    for (int yy = 1; yy <= ny; ++yy) {
-      run += p[(long long)yy * X];
-      p[(long long)yy * X] = run;
-    }
-  } else {
-    if (t >= ny * nx) return;
-    const int yy = 1 + t / nx, x = 1 + t % nx;
-    int* p = s + (long long)yy * X + x;
-    int run = 0;
-    for (int zz = 1; zz <= nz; ++zz) {
-      run += p[(long long)zz * Y * X];
-      p[(long long)zz * Y * X] = run;
+  const int t = blockIdx.x * kThreads + threadIdx.x;
+  if (t >= X * Y) return;
+  const int yy = t / X, xx = t % X;
+  int* s = sat + slot * sat_sstride + t;
+  const long long zstep = (long long)Y * X;
+  s[0] = 0;
+  if (yy == 0 || xx == 0) {
+    for (int z = 1; z <= nz; ++z) s[z * zstep] = 0;
+    return;
+  }
+  const uint32_t* p = plane + slot * plane_sstride + (long long)(yy - 1) * nx + (xx - 1);
+  const long long pstep = (long long)ny * nx;
+  int run = 0;
+  for (int z0 = 0; z0 < nz; z0 += SU) {
+    uint32_t v[SU];
+#pragma unroll
+    for (int u = 0; u < SU; ++u) v[u] = z0 + u < nz ? p[(z0 + u) * pstep] : 0u;
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+      run += (int)v[u];
+      if (z0 + u < nz) s[(z0 + u + 1) * zstep] = run;
     }
   }
 }

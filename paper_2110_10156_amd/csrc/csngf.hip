@@ -397,10 +397,19 @@ int run_batch(csngf_ctx* c, const float* dB, const uint8_t* dmB, const int* rotq
   {
     const int nx = c->nB[0], ny = c->nB[1], nz = c->nB[2];
     ev = prof_begin(c);
-    hipLaunchKernelGGL(k_sat_planes, dim3(nz, slots), dim3(kSatThreads), 0, c->stream, c->d_mask, c->d_plane, nx, ny,
-                       c->mask_slot, c->plane_slot);
-    hipLaunchKernelGGL(k_sat_z, dim3(((nx + 1) * (ny + 1) + kThreads - 1) / kThreads, slots), dim3(kThreads), 0,
-                       c->stream, c->d_plane, c->d_sat, nx, ny, nz, c->plane_slot, c->sat_slot);
+    const dim3 gz(((nx + 1) * (ny + 1) + kThreads - 1) / kThreads, slots);
+    if ((long long)nx * ny < 65536) {   // 2-D prefix sums fit 16 bits
+      uint16_t* pl16 = reinterpret_cast<uint16_t*>(c->d_plane);
+      hipLaunchKernelGGL(k_sat_planes<uint16_t>, dim3(nz, slots), dim3(kSatThreads), 0, c->stream, c->d_mask, pl16, nx,
+                         ny, c->mask_slot, 2 * c->plane_slot);
+      hipLaunchKernelGGL(k_sat_z<uint16_t>, gz, dim3(kThreads), 0, c->stream, pl16, c->d_sat, nx, ny, nz,
+                         2 * c->plane_slot, c->sat_slot);
+    } else {
+      hipLaunchKernelGGL(k_sat_planes<uint32_t>, dim3(nz, slots), dim3(kSatThreads), 0, c->stream, c->d_mask,
+                         c->d_plane, nx, ny, c->mask_slot, c->plane_slot);
+      hipLaunchKernelGGL(k_sat_z<uint32_t>, gz, dim3(kThreads), 0, c->stream, c->d_plane, c->d_sat, nx, ny, nz,
+                         c->plane_slot, c->sat_slot);
+    }
     OverlapGeom g;
     for (int i = 0; i < 3; ++i) {
       g.nA[i] = c->nA[i];

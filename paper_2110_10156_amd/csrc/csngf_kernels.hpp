@@ -573,11 +573,13 @@ __global__ __launch_bounds__(kThreads) void k_zstore(
 // sat[slot][(nz+1)][(ny+1)][(nx+1)], zero on index 0 of every axis:
 // sat[z+1][y+1][x+1] = sum of mask over [0..z] x [0..y] x [0..x].
 // Step 1 (one workgroup per z slice): the slice's 2-D inclusive prefix over (y, x),
-// plane[slot][z][y][x].  Rows go to the waves (a wave scan per row), then each thread walks
-// its column down a group of rows.
+// plane[slot][z][y][x] (PT = uint16_t when nx * ny < 65536, which halves the pass's bytes).
+// Rows go to the waves (a wave scan per row), then each thread walks its column down a
+// group of rows.
 constexpr int kSatThreads = 512;
+template <typename PT>
 __global__ __launch_bounds__(kSatThreads) void k_sat_planes(const uint8_t* __restrict__ mask,
-                                                            uint32_t* __restrict__ plane, int nx, int ny,
+                                                            PT* __restrict__ plane, int nx, int ny,
                                                             long long mask_sstride, long long plane_sstride) {
   constexpr int NW = kSatThreads / 64;  // rows per group
   __shared__ uint32_t rows[NW][kMaxLen];
@@ -585,7 +587,7 @@ __global__ __launch_bounds__(kSatThreads) void k_sat_planes(const uint8_t* __res
   const int z = blockIdx.x, slot = blockIdx.y;
   const long long off = (long long)z * ny * nx;
   const RView m(mask + slot * mask_sstride + off, (long long)ny * nx);
-  uint32_t* out = plane + slot * plane_sstride + off;
+  PT* out = plane + slot * plane_sstride + off;
   uint32_t col = 0;  // running column sum of thread x = threadIdx.x (nx <= kMaxLen = kSatThreads)
   for (int y0 = 0; y0 < ny; y0 += NW) {
     const int y = y0 + wave;
@@ -608,7 +610,7 @@ __global__ __launch_bounds__(kSatThreads) void k_sat_planes(const uint8_t* __res
     if (x < nx) {
       for (int r = 0; r < NW && y0 + r < ny; ++r) {
         col += rows[r][x];
-        out[(long long)(y0 + r) * nx + x] = col;
+        out[(long long)(y0 + r) * nx + x] = (PT)col;
       }
     }
     __syncthreads();
@@ -617,7 +619,8 @@ __global__ __launch_bounds__(kSatThreads) void k_sat_planes(const uint8_t* __res
 
 // Step 2: prefix over z for every (y, x), written with the zero borders.  Each column is read
 // SU planes at a time, all loads issued before the running sum stores them.
-__global__ __launch_bounds__(kThreads) void k_sat_z(const uint32_t* __restrict__ plane, int* __restrict__ sat,
+template <typename PT>
+__global__ __launch_bounds__(kThreads) void k_sat_z(const PT* __restrict__ plane, int* __restrict__ sat,
                                                     int nx, int ny, int nz, long long plane_sstride,
                                                     long long sat_sstride) {
   constexpr int SU = 16;
@@ -633,13 +636,13 @@ __global__ __launch_bounds__(kThreads) void k_sat_z(const uint32_t* __restrict__
     for (int z = 1; z <= nz; ++z) s[z * zstep] = 0;
     return;
   }
-  const uint32_t* p = plane + slot * plane_sstride + (long long)(yy - 1) * nx + (xx - 1);
+  const PT* p = plane + slot * plane_sstride + (long long)(yy - 1) * nx + (xx - 1);
   const long long pstep = (long long)ny * nx;
   int run = 0;
   for (int z0 = 0; z0 < nz; z0 += SU) {
     uint32_t v[SU];
 #pragma unroll
-    for (int u = 0; u < SU; ++u) v[u] = z0 + u < nz ? p[(z0 + u) * pstep] : 0u;
+    for (int u = 0; u < SU; ++u) v[u] = z0 + u < nz ? (uint32_t)p[(z0 + u) * pstep] : 0u;
 #pragma unroll
     for (int u = 0; u < SU; ++u) {
       run += (int)v[u];

@@ -176,6 +176,24 @@ def test_random_small_pairs_full_maps(case):
         assert per[0].score == Cg.flat[flat] and per[0].overlap == Ng.flat[flat]
 
 
+def test_large_xy_extent_full_maps():
+    """A 256 x 256 cross-section: FFT length 512 along x and y (the largest supported; run-time
+    plans), slice prefix sums above 16 bits, and the field stage's widest rows."""
+    from scipy.ndimage import gaussian_filter
+    rng = np.random.default_rng(77)
+    sa, sb = (4, 256, 256), (5, 256, 256)   # (nz, ny, nx)
+    A = gaussian_filter(rng.random(sa), 1.5).astype(np.float32)
+    B = gaussian_filter(rng.random(sb), 1.5).astype(np.float32)
+    R = synth.axis_angle_matrix(np.array([0.0, 0.0, 1.0]), math.radians(20.0))   # in-plane: the thin slab stays valid
+    _say("large xy extent", sa, sb)
+    with bd.Context(A, bd.dims_of(B)) as ctx:
+        P = tuple(ctx.info().pad)
+        assert P[0] == 512 and P[1] == 512
+        Cg, Ng = ctx.evaluate_map(B, R)
+    Co, No, _ = _oracle_maps(A, B, R, None, 0.5, P)
+    _compare_maps(Cg, Ng, Co, No, "large-xy")
+
+
 def test_padding_invariance_and_minimum_extent():
     rng = np.random.default_rng(9)
     A = rng.random((3, 4, 5)).astype(np.float32)

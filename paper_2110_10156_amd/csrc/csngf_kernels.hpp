@@ -776,7 +776,8 @@ __global__ __launch_bounds__(kThreadsC) void k_final_x(
     }
   }
   const long long count_b = s[(long long)(g.nB[2] + 1) * (g.nB[1] + 1) * (g.nB[0] + 1) - 1];
-  const long long thr = threshold(count_a, count_b, gamma);
+  // counts and canonical indices fit 32 bits: N <= |M_B| < 2^31, W_x W_y W_z < 2^31
+  const int thr = (int)threshold(count_a, count_b, gamma);
   if (LC == 0) __syncthreads();
   unsigned long long best = 0ull;
   const RView rows(Y4 + slot * y4_sstride + ((long long)zc * Wy) * Hp, 8LL * Wy * Hp);  // rows >= Wy load zero
@@ -804,10 +805,10 @@ __global__ __launch_bounds__(kThreadsC) void k_final_x(
       const int yc = yc0 + rr;
       if (yc >= Wy) continue;
       const float sv = h ? zv.y : zv.x;
-      const long long n = (lx <= hx) ? (long long)(drow[rr * X1 + hx + 1] - drow[rr * X1 + lx]) : 0;
+      const int n = (lx <= hx) ? drow[rr * X1 + hx + 1] - drow[rr * X1 + lx] : 0;
       const bool valid = n >= thr;
       const float c = valid ? sv / (float)n : -INFINITY;
-      const unsigned int canon = (unsigned int)(((long long)zc * Wy + yc) * Wx + cx);
+      const unsigned int canon = (unsigned)((zc * Wy + yc) * Wx + cx);
       if (valid) {
         const unsigned long long key = ((unsigned long long)ordered_bits(c) << 32) | (0xFFFFFFFFu - canon);
         best = key > best ? key : best;

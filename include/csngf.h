@@ -76,7 +76,9 @@ typedef struct {
   uint32_t struct_size; /* sizeof(csngf_params) */
   float eps;            /* NGF regulariser, Eq. (1); default 1e-5 */
   float gamma;          /* minimum overlap fraction in [0, 1], Sec. 3.2; default 0.5 */
-  int32_t pad[3];       /* FFT size (Px, Py, Pz); 0 = smallest supported >= n_A + n_B - 1 */
+  int32_t pad[3];       /* FFT size (Px, Py, Pz); 0 = automatic: the smallest supported length
+                           >= n_A + n_B - 1, or the smallest one with a compile-time plan when
+                           that is at most 1.5x as long (see csngf_footprint for the result) */
   int32_t batch;        /* rotations in flight per launch sequence; 0 = automatic */
   uint32_t flags;       /* CSNGF_DEVICE_PTRS | CSNGF_UNSQUARED | CSNGF_GRAPHS */
 } csngf_params;

@@ -82,6 +82,23 @@ int smallest_supported_at_least(int need) {
   return -1;
 }
 
+bool fast_length(int L) {
+  for (int f : kFastLengths)
+    if (f == L) return true;
+  return false;
+}
+
+// Automatic FFT size: the smallest supported length >= need, unless it has no compile-time
+// plan and one with a plan is at most 1.5x as long (the run-time-plan kernels are several
+// times slower than the fixed-length ones, more than the extra padding costs).
+int auto_pad(int need) {
+  const int s0 = smallest_supported_at_least(need);
+  if (s0 < 0 || fast_length(s0)) return s0;
+  for (int L = s0 + 1; L <= kMaxLen && 2 * L <= 3 * s0; ++L)
+    if (fast_length(L)) return L;
+  return s0;
+}
+
 void twiddles(int L, std::vector<float2>& out) {
   for (int j = 0; j < L; ++j) {
     const double a = -2.0 * M_PI * (double)j / (double)L;
@@ -119,6 +136,7 @@ void with_len(int L, Fn&& fn) {
     return;
     CSNGF_CASE(16) CSNGF_CASE(32) CSNGF_CASE(48) CSNGF_CASE(56) CSNGF_CASE(64) CSNGF_CASE(88) CSNGF_CASE(96)
     CSNGF_CASE(110) CSNGF_CASE(128) CSNGF_CASE(176) CSNGF_CASE(192) CSNGF_CASE(220) CSNGF_CASE(256) CSNGF_CASE(352)
+    CSNGF_CASE(440) CSNGF_CASE(512)
 #undef CSNGF_CASE
     default:
       fn(std::integral_constant<int, 0>{});
@@ -639,7 +657,7 @@ int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims
   for (int i = 0; i < 3; ++i) {
     const int need = nA[i] + nB[i] - 1;
     if (prm.pad[i] == 0) {
-      P[i] = smallest_supported_at_least(need);
+      P[i] = auto_pad(need);
       if (P[i] < 0) return fail(CSNGF_E_UNSUPPORTED, "no supported FFT size >= n_A + n_B - 1 (max 512)");
     } else {
       if (prm.pad[i] < need) return fail(CSNGF_E_INVALID_ARG, "pad smaller than n_A + n_B - 1");
@@ -1037,7 +1055,7 @@ extern "C" int csngf_footprint(csngf_dims dA, csngf_dims dB, const csngf_params*
   int P[3], Wd[3];
   for (int i = 0; i < 3; ++i) {
     const int need = nA[i] + nB[i] - 1;
-    P[i] = prm.pad[i] ? prm.pad[i] : smallest_supported_at_least(need);
+    P[i] = prm.pad[i] ? prm.pad[i] : auto_pad(need);
     if (P[i] < need || !supported(P[i])) return fail(CSNGF_E_UNSUPPORTED, "FFT size not available");
     Wd[i] = need;
   }
@@ -1058,11 +1076,6 @@ extern "C" int csngf_footprint(csngf_dims dA, csngf_dims dB, const csngf_params*
 
 // ---------------------------------------------------------------------------- autotuner
 namespace {
-bool fast_length(int L) {
-  for (int f : kFastLengths)
-    if (f == L) return true;
-  return false;
-}
 
 // Deterministic probe rotations: normalised Gaussian quaternions from a fixed seed.
 std::vector<double> probe_rotations(int n) {

@@ -505,7 +505,7 @@ __device__ __forceinline__ void fft_io(float2* __restrict__ buf, const float2* _
 }
 
 // Lengths with a compile-time instance; every other supported length uses the run-time plan.
-constexpr int kFastLengths[] = {16, 32, 48, 56, 64, 88, 96, 110, 128, 176, 192, 220, 256, 352};
+constexpr int kFastLengths[] = {16, 32, 48, 56, 64, 88, 96, 110, 128, 176, 192, 220, 256, 352, 440, 512};
 
 // Copy this length's twiddle table into LDS (caller synchronises before use).
 __device__ __forceinline__ void load_twiddles(float2* __restrict__ dst, const float2* __restrict__ table,

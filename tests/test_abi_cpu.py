@@ -119,3 +119,20 @@ def test_no_device_is_reported():
     with pytest.raises(bd.CsngfError) as ei:
         bd.Context(A, (8, 8, 8))
     assert ei.value.code == bd.E_NO_DEVICE
+
+
+def test_automatic_fft_size_prefers_fixed_length_plans():
+    """pad = 0: the smallest supported length >= n_A + n_B - 1, or the smallest one with a
+    compile-time plan when that is at most 1.5x as long (csngf_footprint reports the choice)."""
+    cases = {(32, 32, 32): 64,       # 63 -> 64 (planned)
+             (100, 100, 100): 220,   # 199 -> 200 has no fixed plan; 220 does
+             (129, 129, 129): 352,   # 257 -> 264 unplanned; 352 <= 1.5 * 264
+             (201, 201, 201): 440,   # 401 -> 420 unplanned; 440
+             (96, 96, 64): 192}      # x, y: 191 -> 192; z below
+    for dims, want in cases.items():
+        P = bd.footprint(dims, dims)[2]
+        assert P[0] == want, (dims, P)
+    assert bd.footprint((96, 96, 64), (96, 96, 64))[2][2] == 128
+    assert bd.footprint((176, 176, 110), (176, 176, 110))[2] == (352, 352, 220)
+    # an explicit pad is kept as given
+    assert bd.footprint((100, 100, 100), (100, 100, 100), pad=(200, 200, 200))[2] == (200, 200, 200)

@@ -122,7 +122,7 @@ size_t lds_fields(int Px, int nx) {
 constexpr int kSlicesX = CSNGF_SLICES;
 size_t lds_pencil(int L, int W = kTileW) { return a16(sizeof(float2) * L) + a16(sizeof(float2) * L * W); }
 size_t lds_final(int Px, int nxB) {
-  return a16(sizeof(float2) * Px) + a16(sizeof(float2) * Px * (kRowsX + 1)) + a16(sizeof(int) * 2 * kRowsX * (nxB + 1));
+  return a16(sizeof(float2) * Px) + a16(sizeof(float2) * Px * (kRowsC + 1)) + a16(sizeof(int) * 2 * kRowsC * (nxB + 1));
 }
 
 // Call fn with std::integral_constant<int, L> for lengths that have a compile-time instance
@@ -475,7 +475,7 @@ int run_batch(csngf_ctx* c, const float* dB, const uint8_t* dmB, const int* rotq
       g.nA[i] = c->nA[i];
       g.nB[i] = c->nB[i];
     }
-    const dim3 grid((c->Wd[1] + 2 * kRowsX - 1) / (2 * kRowsX), c->Wd[2], slots);
+    const dim3 grid((c->Wd[1] + 2 * kRowsC - 1) / (2 * kRowsC), c->Wd[2], slots);
     const size_t lds = lds_final(c->plx.L, c->nB[0]);
     hipError_t ae = hipSuccess;
     ev = prof_begin(c);

@@ -37,7 +37,7 @@ constexpr int kTileW = 16;     // adjacent x-bins per pencil tile in the z pass 
 #define CSNGF_TZ 512
 #endif
 #ifndef CSNGF_TC
-#define CSNGF_TC 512
+#define CSNGF_TC 256
 #endif
 #ifndef CSNGF_WPF
 #define CSNGF_WPF 16
@@ -48,13 +48,17 @@ constexpr int kTileW = 16;     // adjacent x-bins per pencil tile in the z pass 
 constexpr int kThreadsF = CSNGF_TF;  // field stage (x pass)
 constexpr int kThreadsZ = CSNGF_TZ;  // z pass
 constexpr int kThreadsC = CSNGF_TC;  // final x pass (C2R, normalisation, argmax)
-static_assert(kThreadsC % 256 == 0, "the final pass maps 256 threads per D row");
+static_assert(kThreadsC % 64 == 0 && (kThreadsC <= 256 || kThreadsC % 256 == 0), "the final pass maps min(T, 256) threads per D row");
 template <bool INV>
 constexpr int kThreadsP = INV ? CSNGF_TPI : CSNGF_TPF;  // y pencil passes (forward, inverse)
 template <bool INV>
 constexpr int kTileP = INV ? CSNGF_WPI : CSNGF_WPF;     // x-bins per y pencil tile
 static_assert(kTileW % CSNGF_WPF == 0 && kTileW % CSNGF_WPI == 0, "y tiles must divide the row pitch unit");
-constexpr int kRowsX = 8;    // rows per workgroup in the x passes
+constexpr int kRowsX = 8;    // rows per workgroup in the field stage
+#ifndef CSNGF_ROWSC
+#define CSNGF_ROWSC 4
+#endif
+constexpr int kRowsC = CSNGF_ROWSC;  // packed row pairs per workgroup in the final pass
 
 struct RotResultDev {        // identical layout to csngf_rot_result
   float score;
@@ -728,7 +732,7 @@ __global__ __launch_bounds__(kThreadsC) void k_final_x(
     float* __restrict__ cmap, long long* __restrict__ nmap, const uint8_t* __restrict__ flags,
     long long flag_sstride) {
   constexpr int T = kThreadsC;
-  constexpr int WP = kRowsX;  // packed pencils
+  constexpr int WP = kRowsC;  // packed pencils
   constexpr int NR = 2 * WP;  // output rows
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ unsigned long long red[T / 64];
@@ -752,14 +756,15 @@ __global__ __launch_bounds__(kThreadsC) void k_final_x(
   load_twiddles(tw, twtab, pl);
   const int half = Px / 2;
   // D rows: for row rr (yc = yc0 + rr), D(x) = sum of the SAT over the row's z and y ranges
-  // up to column x (x = 0 .. nB_x); empty ranges give D = 0.  Rows go to groups of 256
+  // up to column x (x = 0 .. nB_x); empty ranges give D = 0.  Rows go to groups of DG
   // threads, columns to the threads of a group.
   {
+    constexpr int DG = T < 256 ? T : 256;
     const int X = X1, Y = g.nB[1] + 1;
     const int cz = zc - (g.nA[2] - 1);
     const int lz = max(1 + cz, 0), hz = min(g.nA[2] - 2 + cz, g.nB[2] - 1);
     const RView sv(s, 4LL * (g.nB[2] + 1) * Y * X);
-    for (int rr = (int)threadIdx.x / 256; rr < NR; rr += T / 256) {
+    for (int rr = (int)threadIdx.x / DG; rr < NR; rr += T / DG) {
       const int cy = yc0 + rr - (g.nA[1] - 1);
       const int ly = max(1 + cy, 0), hy = min(g.nA[1] - 2 + cy, g.nB[1] - 1);
       const bool any = lz <= hz && ly <= hy && yc0 + rr < Wy;
@@ -768,7 +773,7 @@ __global__ __launch_bounds__(kThreadsC) void k_final_x(
       const uint32_t b = any ? 4u * (uint32_t)((lz * Y + hy + 1) * X) : kNoOff;
       const uint32_t c = any ? 4u * (uint32_t)(((hz + 1) * Y + ly) * X) : kNoOff;
       const uint32_t d = any ? 4u * (uint32_t)((lz * Y + ly) * X) : kNoOff;
-      for (int x = (int)threadIdx.x % 256; x < X1; x += 256) {
+      for (int x = (int)threadIdx.x % DG; x < X1; x += DG) {
         const uint32_t x4 = 4u * x;
         const int v = sv.ldi(a + x4) - sv.ldi(b + x4) - sv.ldi(c + x4) + sv.ldi(d + x4);
         drow[rr * X1 + x] = any ? v : 0;

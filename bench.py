@@ -32,13 +32,14 @@ METRIC = "rotations/s at 3.4 Mvoxel (full displacement map); p50/p99 alignment l
 def kernel_bytes(nA, nB, P):
     """Algorithmic HBM bytes per rotation of each kernel family (complex64 = 8 B).
 
-    Pruned pencils: only nonzero input rows are read, H = Px/2 + 1 bins per row, only the
-    kept displacement rows are written; A's six conjugate spectra are read once per rotation.
+    Pruned pencils: only nonzero input rows are read, H = Px/2 bins per row (the real DC and
+    Nyquist bins share one complex value), only the kept displacement rows are written; A's
+    six conjugate spectra are read once per rotation.
     """
     nxA, nyA, nzA = nA
     nxB, nyB, nzB = nB
     Px, Py, Pz = P
-    H = Px // 2 + 1
+    H = Px // 2
     Wx, Wy, Wz = (nA[i] + nB[i] - 1 for i in range(3))
     vox = nxB * nyB * nzB
     x1 = 6 * nzB * nyB * H * 8          # after the x pass

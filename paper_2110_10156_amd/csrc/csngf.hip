@@ -345,7 +345,8 @@ int check_dims(const csngf_dims& d, const char* what) {
 int launch_pencil(csngf_ctx* c, bool inv, const float2* in, float2* out, int n_in, int n_out, int out_off,
                   const FftPlan& pl, long long in_g, long long out_g, int groups, long long in_s,
                   long long out_s, int slots, const uint8_t* flags = nullptr, long long flag_s = 0) {
-  // tiles cover the H = Px/2 + 1 bins; the padding columns up to Hp are never touched
+  // tiles cover the H = Px/2 stored bins (bin 0 = DC + i Nyquist); the padding columns up to
+  // Hp are never touched
   const int W = inv ? kTileP<true> : kTileP<false>;
   const dim3 grid((c->H + W - 1) / W, groups, slots);
   const size_t lds = lds_pencil(pl.L, W);
@@ -453,13 +454,19 @@ int run_batch(csngf_ctx* c, const float* dB, const uint8_t* dmB, const int* rotq
     const bool half = 2 * c->nB[2] <= c->plz.L;
     with_len(c->plz.L, [&](auto lc) {
       constexpr int LC = decltype(lc)::value;
-      auto go = [&](auto kern) {
-        hipLaunchKernelGGL(kern, dim3(nb8), dim3(kThreadsZ), lds, c->stream, c->d_buf2, c->d_spec, c->d_buf1, c->nB[2],
-                           c->P[1], c->H, c->Hp, c->Wd[2], out_off, c->plz, c->d_tw, c->buf2_slot, c->buf1_slot,
-                           c->tiles, slots, nreal, c->d_flags, c->flag_slot, c->nf);
+      auto go = [&](auto kern, int nblocks) {
+        hipLaunchKernelGGL(kern, dim3(nblocks), dim3(kThreadsZ), lds, c->stream, c->d_buf2, c->d_spec, c->d_buf1,
+                           c->nB[2], c->P[1], c->H, c->Hp, c->Wd[2], out_off, c->plz, c->d_tw, c->buf2_slot,
+                           c->buf1_slot, c->tiles, slots, nreal, c->d_flags, c->flag_slot, c->nf);
       };
-      if (half) go(k_zpass<LC, true>);
-      else go(k_zpass<LC, false>);
+      // all tiles but the packed DC/Nyquist ones, then those (tile 0 at ky = 0 and Py/2)
+      if (half) {
+        go(k_zpass<LC, true, false>, nb8);
+        go(k_zpass<LC, true, true>, 2 * slots);
+      } else {
+        go(k_zpass<LC, false, false>, nb8);
+        go(k_zpass<LC, false, true>, 2 * slots);
+      }
     });
     prof_end(c, KT_ZPASS, ev);
     LAUNCHCHK("k_zpass");
@@ -692,7 +699,7 @@ int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims
   c->gamma = prm.gamma;
   c->flags = prm.flags;
   c->nf = (prm.flags & CSNGF_UNSQUARED) ? 3 : 6;
-  c->H = P[0] / 2 + 1;
+  c->H = P[0] / 2;   // bins 0 .. Px/2 - 1, bin 0 packing DC + i Nyquist
   c->Hp = (c->H + kTileW - 1) / kTileW * kTileW;
   c->tiles = c->Hp / kTileW;
   factor_plan(P[0], c->plx);
@@ -1060,7 +1067,7 @@ extern "C" int csngf_footprint(csngf_dims dA, csngf_dims dB, const csngf_params*
     Wd[i] = need;
   }
   const int nf = (prm.flags & CSNGF_UNSQUARED) ? 3 : 6;
-  const long long H = P[0] / 2 + 1, Hp = (H + kTileW - 1) / kTileW * kTileW;
+  const long long H = P[0] / 2, Hp = (H + kTileW - 1) / kTileW * kTileW;
   const long long nvB = (long long)nB[0] * nB[1] * nB[2];
   const long long buf1 = std::max((long long)nf * nB[2] * nB[1], (long long)Wd[2] * P[1]) * Hp;
   const long long buf2 = std::max((long long)nf * nB[2] * P[1], (long long)Wd[2] * Wd[1]) * Hp;
@@ -1219,7 +1226,7 @@ int csngf_debug_fields(const float* vol, const uint8_t* vmask, csngf_dims d, con
   tmp.nf = (flags & CSNGF_UNSQUARED) ? 3 : 6;
   factor_plan(Px, tmp.plx);
   tmp.plx.tw_off = 0;
-  tmp.H = Px / 2 + 1;
+  tmp.H = Px / 2;
   tmp.Hp = (tmp.H + kTileW - 1) / kTileW * kTileW;
   std::vector<float2> tw;
   twiddles(Px, tw);

@@ -1,6 +1,6 @@
 // HIP kernels of the CSNGF hot path (gfx950).
 //
-// Data flow for one rotation slot (H = Px/2 + 1 half-spectrum bins along x, row pitch Hp):
+// Data flow for one rotation slot (H = Px/2 stored half-spectrum bins along x, row pitch Hp):
 //   k_fields_x   B -> resample -> NGF -> mask -> 6 products -> x R2C    X1 [6][nz][ny][Hp]
 //   k_sat_*      eroded mask of B^ -> zero-bordered 3-D summed-area table (exact overlaps)
 //   k_pencil<F>  y forward, ny nonzero rows -> Py                        X2 [6][nz][Py][Hp]
@@ -10,6 +10,19 @@
 //   k_final_x    x C2R -> S(chi); N(chi) from the SAT; gamma; C = S/N; per-slot argmax key
 // Fixed side (once per context): k_fields_x<direct>, k_pencil<F>, k_zstore (conjugate,
 // cross-term weight 2, 1/(Px Py Pz)).
+//
+// Packed DC/Nyquist column.  The x R2C of a real row has Px/2 + 1 bins, of which bin 0 (DC)
+// and bin Px/2 (Nyquist) are real.  Bin 0 carries both, as DC + i Nyquist, so a row holds
+// Px/2 bins and the pencil passes run Px/2 / 16 tiles instead of one more, nearly empty one.
+// Along the pencil passes that column (x-bin 0, the first pencil of tile 0) is kept as:
+//   after the y forward, rows ky in (0, Py/2) hold the DC plane's D(ky), rows Py - ky its
+//   Nyquist plane's N(ky) (both planes are FFTs of real data, so D(-ky) = conj D(ky) and
+//   likewise N); rows 0 and Py/2 hold D + i N, both real there;
+//   A's spectra and the z pass keep the same rows; at ky = 0 and Py/2 the same split is made
+//   once more along kz (k_zstore, the packed branch of k_zpass), so the products summed there
+//   are again D-plane + i Nyquist-plane, whose z inverse is real + i real;
+//   the y inverse rebuilds S_D(ky) + i S_N(ky) from rows ky and Py - ky, so the x C2R finds
+//   DC + i Nyquist of every displacement row in bin 0.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -398,6 +411,8 @@ __global__ __launch_bounds__(kThreadsF) void k_fields_x(
       fft_io<LC, TY, T, false, false, true, WS, HALF>(buf, tw, pl, products, none);
       __syncthreads();
       // split the packed transform: Fa = (Z_k + conj Z_{P-k}) / 2, Fb = -i (Z_k - conj Z_{P-k}) / 2
+      // for bins 1 .. Px/2 - 1; bin 0 stores DC + i Nyquist of each field (Fa: Z_0.x + i Z_h.x,
+      // Fb: Z_0.y + i Z_h.y with h = Px/2)
       const long long fbase = (long long)nz * ny * Hp;   // elements per field
       const RView oa(out + slot * out_slot_stride + (2 * pair) * fbase, 8 * fbase);
       const RView ob(out + slot * out_slot_stride + (2 * pair + 1) * fbase, 2 * pair + 1 < nf ? 8 * fbase : 0);
@@ -409,10 +424,11 @@ __global__ __launch_bounds__(kThreadsF) void k_fields_x(
         if (e < TY * H) {
           const int k = bk[u], r = br[u];
           const float2 zk = buf[k * WS + r];
-          const float2 zc = buf[(k ? Px - k : 0) * WS + r];
+          const float2 zc = buf[(k ? Px - k : Px / 2) * WS + r];
           const uint32_t off = y0 + r < ny ? off2(row0 + r, hp8, k) : kNoOff;
-          oa.st2(off, make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y - zc.y)));
-          if (2 * pair + 1 < nf) ob.st2(off, make_float2(0.5f * (zk.y + zc.y), 0.5f * (zc.x - zk.x)));
+          oa.st2(off, k ? make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y - zc.y)) : make_float2(zk.x, zc.x));
+          if (2 * pair + 1 < nf)
+            ob.st2(off, k ? make_float2(0.5f * (zk.y + zc.y), 0.5f * (zc.x - zk.x)) : make_float2(zk.y, zc.y));
         }
       }
       __syncthreads();
@@ -451,18 +467,54 @@ __global__ __launch_bounds__(kThreadsP<INV>) void k_pencil(
   if (LC == 0) __syncthreads();
   // rows i >= n_in lie past the input view and load zero; rows c >= n_out past the output
   // view (and its flag view) and are dropped; columns >= H are masked by kNoOff
-  fft_io<LC, W, kThreadsP<INV>, INV, false, false, W, HALF>(
-      buf, tw, pl,
-      [&](int i0, int i1, int p) -> float2 {
-        const uint32_t b = kx0 + p < H ? off2(i0, rs8, p) : kNoOff;
-        return src.ld2(b + (uint32_t)i1 * rs8);
-      },
-      [&](int k0, int k1, int p, float2 v, int) {
-        int c = k0 + k1 - out_off;
-        if (c < 0) c += L;
-        const bool keep = kx0 + p < H && (!rowfl || rflag.ld1(c));
-        dst.st2(keep ? off2(c, rs8, p) : kNoOff, v);
-      });
+  constexpr int T = kThreadsP<INV>;
+  auto load = [&](int i0, int i1, int p) -> float2 {
+    const uint32_t b = kx0 + p < H ? off2(i0, rs8, p) : kNoOff;
+    return src.ld2(b + (uint32_t)i1 * rs8);
+  };
+  auto store = [&](int k0, int k1, int p, float2 v, int) {
+    int c = k0 + k1 - out_off;
+    if (c < 0) c += L;
+    const bool keep = kx0 + p < H && (!rowfl || rflag.ld1(c));
+    dst.st2(keep ? off2(c, rs8, p) : kNoOff, v);
+  };
+  if (kx0 != 0) {
+    fft_io<LC, W, T, INV, false, false, W, HALF>(buf, tw, pl, load, store);
+    return;
+  }
+  // tile 0: its first pencil is the packed DC/Nyquist column
+  const int half = L / 2;
+  if constexpr (!INV) {
+    // forward (out_off = 0, all rows kept): transform into LDS, then split the packed pencil,
+    // Y = D + i N: row c < L/2 takes D(c) = (Y(c) + conj Y(-c)) / 2, row L - c takes
+    // N(c) = -i (Y(c) - conj Y(-c)) / 2; rows 0 and L/2 keep Y
+    fft_io<LC, W, T, false, false, true, W, HALF>(buf, tw, pl, load, [](int, int, int, float2, int) {});
+    __syncthreads();
+    for (int e = threadIdx.x; e < L * W; e += T) {
+      const int c = e / W, p = e - c * W;
+      float2 v = buf[e];
+      if (p == 0 && c != 0 && c != half) {
+        const float2 m = buf[(L - c) * W];
+        v = c < half ? make_float2(0.5f * (v.x + m.x), 0.5f * (v.y - m.y))
+                     : make_float2(0.5f * (v.y + m.y), 0.5f * (v.x - m.x));
+      }
+      dst.st2(kx0 + p < H ? off2(c, rs8, p) : kNoOff, v);
+    }
+  } else {
+    // inverse: the input rows are S_D(ky) for ky < L/2 and S_N(L - ky) above (rows 0 and
+    // L/2: S_D + i S_N); transform G(ky) = S_D(ky) + i S_N(ky), using the Hermitian symmetry
+    // of both planes for the rows that are not stored
+    fft_io<LC, W, T, true, false, false, W, false>(
+        buf, tw, pl,
+        [&](int i0, int i1, int p) -> float2 {
+          const float2 s = load(i0, i1, p);
+          const int i = i0 + i1;
+          if (p != 0 || i == 0 || i == half) return s;
+          const float2 m = src.ld2(off2(L - i, rs8, 0));
+          return i < half ? make_float2(s.x - m.y, s.y + m.x) : make_float2(m.x + s.y, s.x - m.y);
+        },
+        store);
+  }
 }
 
 // ------------------------------------------------------------------------------ z pass
@@ -471,7 +523,10 @@ __global__ __launch_bounds__(kThreadsP<INV>) void k_pencil(
 // the multiply-accumulate against A's conjugate spectrum done on the last stage's
 // registers; then the sum goes through LDS once for the z inverse, whose last stage
 // stores the kept displacement rows.
-template <int LC, bool HALF>
+// PACKED: a separate launch of 2 workgroups per slot for tile 0 at ky = 0 and Py/2, whose
+// first pencil is the packed DC/Nyquist column (see the top of this file); the main launch
+// skips those two tiles.  Kept apart so the main kernel's register budget is unchanged.
+template <int LC, bool HALF, bool PACKED>
 __global__ __launch_bounds__(kThreadsZ) void k_zpass(
     const float2* __restrict__ X2, const float2* __restrict__ spec, float2* __restrict__ Y3,
     int nz, int Py, int H, int Hp, int Wz, int out_off, FftPlan pl, const float2* __restrict__ twtab,
@@ -483,51 +538,124 @@ __global__ __launch_bounds__(kThreadsZ) void k_zpass(
   const int Pz = pl.L;
   float2* tw = reinterpret_cast<float2*>(smem);
   float2* buf = reinterpret_cast<float2*>(smem + align16(sizeof(float2) * Pz));
-  // XCD-aware order: hardware deals block b to XCD b % 8; give each XCD a contiguous run.
-  const int nb8 = gridDim.x;
-  const int b = blockIdx.x;
-  const int logical = (b % 8) * (nb8 / 8) + b / 8;
-  if (logical >= nreal) return;
-  const int slot = logical % nslots;
-  const int rest = logical / nslots;
-  const int tile = rest % ntiles;
-  const int ky = rest / ntiles;
-  const int kx0 = tile * W;
+  int slot, ky, kx0;
+  if constexpr (PACKED) {
+    if ((int)blockIdx.x >= 2 * nslots) return;
+    slot = blockIdx.x % nslots;
+    ky = blockIdx.x < nslots ? 0 : Py / 2;
+    kx0 = 0;
+  } else {
+    // XCD-aware order: hardware deals block b to XCD b % 8; give each XCD a contiguous run.
+    const int nb8 = gridDim.x;
+    const int b = blockIdx.x;
+    const int logical = (b % 8) * (nb8 / 8) + b / 8;
+    if (logical >= nreal) return;
+    slot = logical % nslots;
+    const int rest = logical / nslots;
+    const int tile = rest % ntiles;
+    ky = rest / ntiles;
+    kx0 = tile * W;
+    if (kx0 == 0 && (ky == 0 || 2 * ky == Py)) return;   // done by the PACKED launch
+  }
   load_twiddles(tw, twtab, pl);
   if (LC == 0) __syncthreads();
-  float2 acc[NSLOT];
-#pragma unroll
-  for (int u = 0; u < NSLOT; ++u) acc[u] = make_float2(0.f, 0.f);
   const long long fstride_x2 = (long long)nz * Py * Hp;
   const long long fstride_sp = (long long)Pz * Py * Hp;
   const long long zs = (long long)Py * Hp;
   const long long col0 = (long long)ky * Hp + kx0;
   const uint32_t zs8 = 8u * (uint32_t)zs;
+  // views from this pencil tile to the end of field f: moving input (rows i >= nz lie past
+  // it and load zero) and A's spectrum; masked columns load zero and are never stored
+  auto src_view = [&](int f) { return RView(X2 + slot * x2_sstride + f * fstride_x2 + col0, 8 * (fstride_x2 - col0)); };
+  auto spec_view = [&](int f) { return RView(spec + f * fstride_sp + col0, 8 * (fstride_sp - col0)); };
+  auto loader = [&](const RView& src) {
+    return [&src, kx0, H, zs8](int i0, int i1, int p) -> float2 {
+      const uint32_t b = kx0 + p < H ? off2(i0, zs8, p) : kNoOff;
+      return src.ld2(b + (uint32_t)i1 * zs8);
+    };
+  };
+  if constexpr (!PACKED) {
+    float2 acc[NSLOT];
+#pragma unroll
+    for (int u = 0; u < NSLOT; ++u) acc[u] = make_float2(0.f, 0.f);
 #pragma unroll 1
-  for (int f = 0; f < nf; ++f) {
-    // views from this pencil tile to the end of field f: moving input (rows i >= nz lie past
-    // it and load zero) and A's spectrum; masked columns load zero and are never stored
-    const RView src(X2 + slot * x2_sstride + f * fstride_x2 + col0, 8 * (fstride_x2 - col0));
-    const RView a(spec + f * fstride_sp + col0, 8 * (fstride_sp - col0));
-    fft_io<LC, W, kThreadsZ, false, false, false, W, HALF>(
-        buf, tw, pl,
-        [&](int i0, int i1, int p) -> float2 {
-          const uint32_t b = kx0 + p < H ? off2(i0, zs8, p) : kNoOff;
-          return src.ld2(b + (uint32_t)i1 * zs8);
-        },
-        [&](int k0, int k1, int p, float2 v, int sl) {
-          const uint32_t b = kx0 + p < H ? off2(k0, zs8, p) : kNoOff;
-          const float2 sv = a.ld2(b + (uint32_t)k1 * zs8);
-          acc[sl].x = fmaf(v.x, sv.x, fmaf(-v.y, sv.y, acc[sl].x));
-          acc[sl].y = fmaf(v.x, sv.y, fmaf(v.y, sv.x, acc[sl].y));
-        });
-    __syncthreads();
-  }
-  if constexpr (LC > 0) {
-    for_each_last_slot<LC, W, kThreadsZ>([&](int k, int p, int sl) { buf[k * W + p] = acc[sl]; });
+    for (int f = 0; f < nf; ++f) {
+      const RView src = src_view(f);
+      const RView a = spec_view(f);
+      fft_io<LC, W, kThreadsZ, false, false, false, W, HALF>(
+          buf, tw, pl, loader(src),
+          [&](int k0, int k1, int p, float2 v, int sl) {
+            const uint32_t b = kx0 + p < H ? off2(k0, zs8, p) : kNoOff;
+            const float2 sv = a.ld2(b + (uint32_t)k1 * zs8);
+            acc[sl].x = fmaf(v.x, sv.x, fmaf(-v.y, sv.y, acc[sl].x));
+            acc[sl].y = fmaf(v.x, sv.y, fmaf(v.y, sv.x, acc[sl].y));
+          });
+      __syncthreads();
+    }
+    if constexpr (LC > 0) {
+      for_each_last_slot<LC, W, kThreadsZ>([&](int k, int p, int sl) { buf[k * W + p] = acc[sl]; });
+    } else {
+      int sl = 0;
+      for (int e = threadIdx.x; e < Pz * W; e += kThreadsZ, ++sl) buf[e] = acc[sl];
+    }
   } else {
-    int sl = 0;
-    for (int e = threadIdx.x; e < Pz * W; e += kThreadsZ, ++sl) buf[e] = acc[sl];
+    // tile 0 at ky = 0 or Py/2: its first pencil holds D + i N with D, N real along z, so its
+    // z transform is Z = D^ + i N^ with both parts Hermitian in kz.  Split Z with Z(-kz), take
+    // A's D and N spectra from the same split stored by k_zstore, and accumulate
+    // conj(A_D) B_D + i conj(A_N) B_N, whose z inverse is (D-plane sum) + i (Nyquist-plane sum).
+    constexpr int NE = ((LC > 0 ? LC : kMaxLen) * W + kThreadsZ - 1) / kThreadsZ;
+    float2 acc[NE];
+#pragma unroll
+    for (int u = 0; u < NE; ++u) acc[u] = make_float2(0.f, 0.f);
+    const int hz = Pz / 2;
+#pragma unroll 1
+    for (int f = 0; f < nf; ++f) {
+      const RView src = src_view(f);
+      const RView a = spec_view(f);
+      fft_io<LC, W, kThreadsZ, false, false, true, W, HALF>(buf, tw, pl, loader(src),
+                                                          [](int, int, int, float2, int) {});
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < NE; ++u) {
+        const int e = (int)threadIdx.x + u * kThreadsZ;
+        if (e < Pz * W) {
+          const int kz = e / W, p = e - kz * W;
+          const float2 v = buf[e];
+          const float2 sk = a.ld2(kx0 + p < H ? off2(kz, zs8, p) : kNoOff);
+          if (p != 0) {
+            acc[u].x = fmaf(v.x, sk.x, fmaf(-v.y, sk.y, acc[u].x));
+            acc[u].y = fmaf(v.x, sk.y, fmaf(v.y, sk.x, acc[u].y));
+          } else {
+            const int m = kz ? Pz - kz : 0;
+            const float2 vm = buf[m * W];
+            const float2 sm = a.ld2(off2(m, zs8, 0));
+            const float2 bd = make_float2(0.5f * (v.x + vm.x), 0.5f * (v.y - vm.y));   // B_D(kz)
+            const float2 bn = make_float2(0.5f * (v.y + vm.y), 0.5f * (vm.x - v.x));   // B_N(kz)
+            float2 ad, an;   // w conj(A_D(kz)), w conj(A_N(kz))
+            if (kz == 0 || kz == hz) {
+              ad = make_float2(sk.x, 0.f);
+              an = make_float2(-sk.y, 0.f);
+            } else if (kz < hz) {
+              ad = sk;
+              an = sm;
+            } else {
+              ad = make_float2(sm.x, -sm.y);
+              an = make_float2(sk.x, -sk.y);
+            }
+            const float2 t1 = make_float2(ad.x * bd.x - ad.y * bd.y, ad.x * bd.y + ad.y * bd.x);
+            const float2 t2 = make_float2(an.x * bn.x - an.y * bn.y, an.x * bn.y + an.y * bn.x);
+            acc[u].x += t1.x - t2.y;
+            acc[u].y += t1.y + t2.x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < NE; ++u) {
+      const int e = (int)threadIdx.x + u * kThreadsZ;
+      if (e < Pz * W) buf[e] = acc[u];
+    }
   }
   __syncthreads();
   const RView dst(Y3 + slot * y3_sstride + col0, 8 * ((long long)Wz * zs - col0));
@@ -562,15 +690,31 @@ __global__ __launch_bounds__(kThreads) void k_zstore(
   const float2* src = X2 + (long long)f * nz * zs + (long long)ky * Hp + kx0;
   const float w = (nf == 6 && f >= 3 ? 2.0f : 1.0f) * scale;  // Eq. (6) cross terms x2
   float2* dst = spec + (long long)f * Pz * zs + (long long)ky * Hp + kx0;
-  fft_io<LC, W, kThreads, false, false, false>(
-      buf, tw, pl,
-      [&](int i0, int i1, int p) -> float2 {
-        const int i = i0 + i1;
-        return (i < nz && kx0 + p < H) ? src[(long long)i * zs + p] : make_float2(0.f, 0.f);
-      },
-      [&](int k0, int k1, int p, float2 v, int) {
-        if (kx0 + p < H) dst[(long long)(k0 + k1) * zs + p] = make_float2(w * v.x, -w * v.y);
-      });
+  auto load = [&](int i0, int i1, int p) -> float2 {
+    const int i = i0 + i1;
+    return (i < nz && kx0 + p < H) ? src[(long long)i * zs + p] : make_float2(0.f, 0.f);
+  };
+  if (kx0 != 0 || (ky != 0 && 2 * ky != Py)) {
+    fft_io<LC, W, kThreads, false, false, false>(buf, tw, pl, load, [&](int k0, int k1, int p, float2 v, int) {
+      if (kx0 + p < H) dst[(long long)(k0 + k1) * zs + p] = make_float2(w * v.x, -w * v.y);
+    });
+    return;
+  }
+  // tile 0 at ky = 0 or Py/2: the first pencil transforms to Z = D^ + i N^ (both Hermitian in
+  // kz); store D^(kz) at kz in (0, Pz/2), N^(Pz - kz) at kz in (Pz/2, Pz), and Z at 0 and Pz/2
+  fft_io<LC, W, kThreads, false, false, true>(buf, tw, pl, load, [](int, int, int, float2, int) {});
+  __syncthreads();
+  const int hz = Pz / 2;
+  for (int e = threadIdx.x; e < Pz * W; e += kThreads) {
+    const int kz = e / W, p = e - kz * W;
+    float2 v = buf[e];
+    if (p == 0 && kz != 0 && kz != hz) {
+      const float2 m = buf[(Pz - kz) * W];
+      v = kz < hz ? make_float2(0.5f * (v.x + m.x), 0.5f * (v.y - m.y))
+                  : make_float2(0.5f * (v.y + m.y), 0.5f * (v.x - m.x));
+    }
+    if (kx0 + p < H) dst[(long long)kz * zs + p] = make_float2(w * v.x, -w * v.y);
+  }
 }
 
 // ------------------------------------------------------------------------------ overlap SAT
@@ -791,10 +935,12 @@ __global__ __launch_bounds__(kThreadsC) void k_final_x(
   auto pack = [&](int k0, int k1, int p) -> float2 {
     const int k = k0 + k1;
     const int r0 = yc0 + 2 * p, r1 = r0 + 1;
-    const int kk = k <= half ? k : Px - k;
+    // bin 0 holds DC + i Nyquist of each row
+    const int kk = k == half ? 0 : k < half ? k : Px - k;
     const float2 a = rows.ld2(rflag.ld1(r0) ? off2(r0, hp8, kk) : kNoOff);
     const float2 c = rows.ld2(rflag.ld1(r1) ? off2(r1, hp8, kk) : kNoOff);
-    if (k == 0 || k == half) return make_float2(a.x, c.x);
+    if (k == 0) return make_float2(a.x, c.x);
+    if (k == half) return make_float2(a.y, c.y);
     if (k < half) return make_float2(a.x - c.y, a.y + c.x);  // S1 + i S2
     return make_float2(a.x + c.y, c.x - a.y);                // conj(S1) + i conj(S2)
   };

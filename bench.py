@@ -48,9 +48,10 @@ def kernel_bytes(nA, nB, P):
     y3 = Wz * Py * H * 8                # after the z inverse (kept rows)
     y4 = Wz * Wy * H * 8                # after the y inverse (kept rows)
     sat = 4 * (nxB + 1) * (nyB + 1) * (nzB + 1)
+    plane = 2 if nxB * nyB < 65536 else 4   # bytes per slice prefix sum (uint16 / uint32)
     return {
         "fields_x": 4 * vox + x1 + vox,              # B once, X1, eroded mask
-        "overlap_sat": vox + 5 * sat,                # mask in; table written, re-read, re-written twice
+        "overlap_sat": vox + 2 * plane * vox + sat,  # mask in; slice prefixes out and back; table out
         "y_forward": x1 + x2,
         "z_mac_inverse": x2 + spec + y3,
         "y_inverse": y3 + y4,

@@ -701,7 +701,7 @@ int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims
   c->nf = (prm.flags & CSNGF_UNSQUARED) ? 3 : 6;
   c->H = P[0] / 2;   // bins 0 .. Px/2 - 1, bin 0 packing DC + i Nyquist
   c->Hp = (c->H + kTileW - 1) / kTileW * kTileW;
-  c->tiles = c->Hp / kTileW;
+  c->tiles = (c->H + kTileW - 1) / kTileW;
   factor_plan(P[0], c->plx);
   factor_plan(P[1], c->ply);
   factor_plan(P[2], c->plz);

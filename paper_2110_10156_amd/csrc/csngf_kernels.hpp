@@ -878,6 +878,7 @@ __global__ __launch_bounds__(kThreadsC) void k_final_x(
   constexpr int T = kThreadsC;
   constexpr int WP = kRowsC;  // packed pencils
   constexpr int NR = 2 * WP;  // output rows
+  static_assert(NR <= 32, "row flags are kept as a 32-bit mask");
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ unsigned long long red[T / 64];
   const int Px = pl.L;
@@ -892,11 +893,18 @@ __global__ __launch_bounds__(kThreadsC) void k_final_x(
   // rows whose overlap bound is below the threshold hold no valid displacement and were
   // not produced by the inverse passes; without a map to write, skip groups of such rows
   const uint8_t* rowfl = flags + slot * flag_sstride + Wz + (long long)zc * Wy;
-  if (!WRITE_MAP) {
-    bool any = false;
-    for (int rr = 0; rr < NR; ++rr) any |= (yc0 + rr < Wy) && rowfl[yc0 + rr];
-    if (!any) return;
+  // the NR row flags as one bit mask (bit rr: row yc0 + rr was produced); rows past Wy lie
+  // past the flag view and read 0.  All loads are issued before any is used.
+  unsigned fmask = 0;
+  {
+    const RView rf(rowfl, Wy);
+    unsigned fl[NR];
+#pragma unroll
+    for (int rr = 0; rr < NR; ++rr) fl[rr] = rf.ld1((uint32_t)(yc0 + rr));
+#pragma unroll
+    for (int rr = 0; rr < NR; ++rr) fmask |= fl[rr] ? 1u << rr : 0u;
   }
+  if (!WRITE_MAP && !fmask) return;
   load_twiddles(tw, twtab, pl);
   const int half = Px / 2;
   // D rows: for row rr (yc = yc0 + rr), D(x) = sum of the SAT over the row's z and y ranges
@@ -904,23 +912,39 @@ __global__ __launch_bounds__(kThreadsC) void k_final_x(
   // threads, columns to the threads of a group.
   {
     constexpr int DG = T < 256 ? T : 256;
+    constexpr int RG = T / DG;                  // row groups
+    constexpr int RPT = (NR + RG - 1) / RG;     // rows per thread
     const int X = X1, Y = g.nB[1] + 1;
     const int cz = zc - (g.nA[2] - 1);
     const int lz = max(1 + cz, 0), hz = min(g.nA[2] - 2 + cz, g.nB[2] - 1);
     const RView sv(s, 4LL * (g.nB[2] + 1) * Y * X);
-    for (int rr = (int)threadIdx.x / DG; rr < NR; rr += T / DG) {
+    const int rg = (int)threadIdx.x / DG;
+    // byte offsets of the 4 SAT rows of each of this thread's rows (the SAT of one slot is
+    // far below 2 GiB); kNoOff where the row needs no counts
+    uint32_t o[RPT][4];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int rr = rg + i * RG;
       const int cy = yc0 + rr - (g.nA[1] - 1);
       const int ly = max(1 + cy, 0), hy = min(g.nA[1] - 2 + cy, g.nB[1] - 1);
-      const bool any = lz <= hz && ly <= hy && yc0 + rr < Wy;
-      // byte offsets of the 4 SAT rows (the SAT of one slot is far below 2 GiB)
-      const uint32_t a = any ? 4u * (uint32_t)(((hz + 1) * Y + hy + 1) * X) : kNoOff;
-      const uint32_t b = any ? 4u * (uint32_t)((lz * Y + hy + 1) * X) : kNoOff;
-      const uint32_t c = any ? 4u * (uint32_t)(((hz + 1) * Y + ly) * X) : kNoOff;
-      const uint32_t d = any ? 4u * (uint32_t)((lz * Y + ly) * X) : kNoOff;
-      for (int x = (int)threadIdx.x % DG; x < X1; x += DG) {
-        const uint32_t x4 = 4u * x;
-        const int v = sv.ldi(a + x4) - sv.ldi(b + x4) - sv.ldi(c + x4) + sv.ldi(d + x4);
-        drow[rr * X1 + x] = any ? v : 0;
+      // without a map, rows that hold no valid displacement (flag 0) need no counts
+      const bool any = rr < NR && lz <= hz && ly <= hy && yc0 + rr < Wy && (WRITE_MAP || ((fmask >> rr) & 1u));
+      o[i][0] = any ? 4u * (uint32_t)(((hz + 1) * Y + hy + 1) * X) : kNoOff;
+      o[i][1] = any ? 4u * (uint32_t)((lz * Y + hy + 1) * X) : kNoOff;
+      o[i][2] = any ? 4u * (uint32_t)(((hz + 1) * Y + ly) * X) : kNoOff;
+      o[i][3] = any ? 4u * (uint32_t)((lz * Y + ly) * X) : kNoOff;
+    }
+    for (int x = (int)threadIdx.x % DG; x < X1; x += DG) {
+      const uint32_t x4 = 4u * x;
+      int v[RPT][4];
+#pragma unroll
+      for (int i = 0; i < RPT; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[i][q] = sv.ldi(o[i][q] + x4);
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const int rr = rg + i * RG;
+        if (rr < NR) drow[rr * X1 + x] = v[i][0] - v[i][1] - v[i][2] + v[i][3];
       }
     }
   }
@@ -930,19 +954,23 @@ __global__ __launch_bounds__(kThreadsC) void k_final_x(
   if (LC == 0) __syncthreads();
   unsigned long long best = 0ull;
   const RView rows(Y4 + slot * y4_sstride + ((long long)zc * Wy) * Hp, 8LL * Wy * Hp);  // rows >= Wy load zero
-  const RView rflag(rowfl, Wy);
   const uint32_t hp8 = 8u * (uint32_t)Hp;
   auto pack = [&](int k0, int k1, int p) -> float2 {
     const int k = k0 + k1;
-    const int r0 = yc0 + 2 * p, r1 = r0 + 1;
-    // bin 0 holds DC + i Nyquist of each row
-    const int kk = k == half ? 0 : k < half ? k : Px - k;
-    const float2 a = rows.ld2(rflag.ld1(r0) ? off2(r0, hp8, kk) : kNoOff);
-    const float2 c = rows.ld2(rflag.ld1(r1) ? off2(r1, hp8, kk) : kNoOff);
-    if (k == 0) return make_float2(a.x, c.x);
-    if (k == half) return make_float2(a.y, c.y);
-    if (k < half) return make_float2(a.x - c.y, a.y + c.x);  // S1 + i S2
-    return make_float2(a.x + c.y, c.x - a.y);                // conj(S1) + i conj(S2)
+    const int r0 = yc0 + 2 * p;
+    // bin 0 holds DC + i Nyquist of each row.  Branch-free, so the loads of a butterfly's
+    // elements are all in flight together.
+    const bool lo = k < half;
+    const int kk = k == half ? 0 : lo ? k : Px - k;
+    const uint32_t o0 = off2(r0, hp8, kk);
+    const float2 a = rows.ld2((fmask >> (2 * p)) & 1u ? o0 : kNoOff);
+    const float2 c = rows.ld2((fmask >> (2 * p + 1)) & 1u ? o0 + hp8 : kNoOff);
+    // k < half: S1 + i S2; k > half: conj(S1) + i conj(S2); k = 0 / half: DC / Nyquist
+    const float sg = lo ? 1.0f : -1.0f;
+    float2 z = make_float2(fmaf(-sg, c.y, a.x), fmaf(sg, a.y, c.x));
+    z = k == 0 ? make_float2(a.x, c.x) : z;
+    z = k == half ? make_float2(a.y, c.y) : z;
+    return z;
   };
   auto emit = [&](int j0, int j1, int p, float2 zv, int) {
     int cx = j0 + j1 + g.nA[0] - 1;   // < 2 Px

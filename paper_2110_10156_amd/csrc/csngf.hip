@@ -349,7 +349,7 @@ int launch_pencil(csngf_ctx* c, bool inv, const float2* in, float2* out, int n_i
   // Hp are never touched
   const int W = inv ? kTileP<true> : kTileP<false>;
   const dim3 grid((c->H + W - 1) / W, groups, slots);
-  const size_t lds = lds_pencil(pl.L, W);
+  const size_t lds = lds_pencil(pl.L, W) + (inv ? a16(pl.L) : 0);   // + the inverse's row flags
   hipEvent_t ev = prof_begin(c);
   const bool half = 2 * n_in <= pl.L;  // inputs i >= L/2 are zero: first stage pruned
   with_len(pl.L, [&](auto lc) {
@@ -447,7 +447,7 @@ int run_batch(csngf_ctx* c, const float* dB, const uint8_t* dmB, const int* rotq
   {
     const int nreal = c->P[1] * c->tiles * slots;
     const int nb8 = (nreal + 7) / 8 * 8;
-    const size_t lds = lds_pencil(c->plz.L);
+    const size_t lds = lds_pencil(c->plz.L) + a16(c->plz.L);   // + the kept-row flags
     const int out_off = c->P[2] - (c->nA[2] - 1);
     ev = prof_begin(c);
     // inputs z >= Pz/2 are zero when nz <= Pz/2: the forward transforms' first stage is pruned

@@ -461,10 +461,18 @@ __global__ __launch_bounds__(kThreadsP<INV>) void k_pencil(
   const RView src(in + blockIdx.z * in_sstride + blockIdx.y * in_gstride + kx0, 8LL * ((long long)n_in * Hp - kx0));
   const RView dst(out + blockIdx.z * out_sstride + blockIdx.y * out_gstride + kx0,
                   8LL * ((long long)n_out * Hp - kx0));
-  const RView rflag(rowfl, n_out);
   const uint32_t rs8 = 8u * (uint32_t)Hp;
   load_twiddles(tw, twtab, pl);
-  if (LC == 0) __syncthreads();
+  // inverse with flags: the group's row flags go to LDS once (rows c >= n_out read 0), so the
+  // last stage's stores need no global load each
+  uint8_t* rfl = reinterpret_cast<uint8_t*>(smem + align16(sizeof(float2) * L) + align16(sizeof(float2) * L * W));
+  if (INV && rowfl) {
+    const RView rflag(rowfl, n_out);
+    for (int c = threadIdx.x; c < L; c += kThreadsP<INV>) rfl[c] = (uint8_t)rflag.ld1((uint32_t)c);
+    __syncthreads();
+  } else if (LC == 0) {
+    __syncthreads();
+  }
   // rows i >= n_in lie past the input view and load zero; rows c >= n_out past the output
   // view (and its flag view) and are dropped; columns >= H are masked by kNoOff
   constexpr int T = kThreadsP<INV>;
@@ -475,7 +483,7 @@ __global__ __launch_bounds__(kThreadsP<INV>) void k_pencil(
   auto store = [&](int k0, int k1, int p, float2 v, int) {
     int c = k0 + k1 - out_off;
     if (c < 0) c += L;
-    const bool keep = kx0 + p < H && (!rowfl || rflag.ld1(c));
+    const bool keep = kx0 + p < H && (!rowfl || rfl[c]);
     dst.st2(keep ? off2(c, rs8, p) : kNoOff, v);
   };
   if (kx0 != 0) {
@@ -507,11 +515,13 @@ __global__ __launch_bounds__(kThreadsP<INV>) void k_pencil(
     fft_io<LC, W, T, true, false, false, W, false>(
         buf, tw, pl,
         [&](int i0, int i1, int p) -> float2 {
+          // branch-free, so a butterfly's loads are all in flight together
           const float2 s = load(i0, i1, p);
           const int i = i0 + i1;
-          if (p != 0 || i == 0 || i == half) return s;
-          const float2 m = src.ld2(off2(L - i, rs8, 0));
-          return i < half ? make_float2(s.x - m.y, s.y + m.x) : make_float2(m.x + s.y, s.x - m.y);
+          const bool mix = p == 0 && i != 0 && i != half;
+          const float2 m = src.ld2(mix ? off2(L - i, rs8, 0) : kNoOff);
+          const float2 g = i < half ? make_float2(s.x - m.y, s.y + m.x) : make_float2(m.x + s.y, s.x - m.y);
+          return mix ? g : s;
         },
         store);
   }
@@ -659,13 +669,20 @@ __global__ __launch_bounds__(kThreadsZ) void k_zpass(
   }
   __syncthreads();
   const RView dst(Y3 + slot * y3_sstride + col0, 8 * ((long long)Wz * zs - col0));
-  const RView zflag(flags + slot * flag_sstride, Wz);  // rows c >= Wz read flag 0
+  // kept-row flags to LDS (rows c >= Wz read 0); the inverse's stage barriers order these
+  // writes before the last stage reads them
+  uint8_t* zfl = reinterpret_cast<uint8_t*>(smem + align16(sizeof(float2) * Pz) + align16(sizeof(float2) * Pz * W));
+  {
+    const RView zflag(flags + slot * flag_sstride, Wz);
+    for (int c = threadIdx.x; c < Pz; c += kThreadsZ) zfl[c] = (uint8_t)zflag.ld1((uint32_t)c);
+    __syncthreads();
+  }
   fft_io<LC, W, kThreadsZ, true, true, false>(
       buf, tw, pl, [](int, int, int) { return make_float2(0.f, 0.f); },
       [&](int k0, int k1, int p, float2 v, int) {
         int c = k0 + k1 - out_off;
         if (c < 0) c += Pz;
-        const bool keep = kx0 + p < H && zflag.ld1(c);
+        const bool keep = kx0 + p < H && zfl[c];
         dst.st2(keep ? off2(c, zs8, p) : kNoOff, v);
       });
 }

@@ -510,7 +510,15 @@ constexpr int kFastLengths[] = {16, 32, 48, 56, 64, 88, 96, 110, 128, 176, 192, 
 // Copy this length's twiddle table into LDS (caller synchronises before use).
 __device__ __forceinline__ void load_twiddles(float2* __restrict__ dst, const float2* __restrict__ table,
                                               const FftPlan& pl) {
-  for (int i = threadIdx.x; i < pl.L; i += blockDim.x) dst[i] = table[pl.tw_off + i];
+  // two loads in flight per thread before either is stored (L <= 2 * blockDim.x in one pass)
+  const int L = pl.L, T = blockDim.x;
+  const float2* src = table + pl.tw_off;
+  for (int i = threadIdx.x; i < L; i += 2 * T) {
+    const int j = i + T < L ? i + T : i;
+    const float2 a = src[i], b = src[j];
+    dst[i] = a;
+    dst[j] = b;
+  }
 }
 
 }  // namespace csngf

@@ -757,17 +757,27 @@ __global__ __launch_bounds__(kSatThreads) void k_sat_planes(const uint8_t* __res
   for (int y0 = 0; y0 < ny; y0 += NW) {
     const int y = y0 + wave;
     if (y < ny) {
+      // the row's 64-column chunks are all loaded before the first is scanned
+      constexpr int NC = kMaxLen / 64;
+      uint32_t v[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const int x = c * 64 + lane;
+        v[c] = m.ld1(x < nx ? (unsigned)(y * nx + x) : kNoOff);  // 0 past the row (no access)
+      }
       uint32_t carry = 0;
-      for (int x0 = 0; x0 < nx; x0 += 64) {
-        const int x = x0 + lane;
-        uint32_t v = m.ld1(x < nx ? (unsigned)(y * nx + x) : kNoOff);  // 0 past the row
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        if (c * 64 >= nx) break;
+        const int x = c * 64 + lane;
+        uint32_t u = v[c];
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
-          const uint32_t t = __shfl_up(v, d, 64);
-          if (lane >= d) v += t;
+          const uint32_t t = __shfl_up(u, d, 64);
+          if (lane >= d) u += t;
         }
-        if (x < nx) rows[wave][x] = carry + v;
-        carry += __shfl(v, 63, 64);
+        if (x < nx) rows[wave][x] = carry + u;
+        carry += __shfl(u, 63, 64);
       }
     }
     __syncthreads();

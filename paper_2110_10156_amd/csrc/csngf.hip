@@ -206,10 +206,13 @@ struct csngf_ctx {
   long long mask_slot = 0;
   int* d_sat = nullptr;
   long long sat_slot = 0;
-  // per-slice 2-D prefix sums of the mask (SAT step 1): lives in buf2, which is free
-  // between the field stage and the y forward pass
+  // per-slice 2-D prefix sums of the mask (SAT step 1), uint16 or uint32 per voxel
   uint32_t* d_plane = nullptr;
-  long long plane_slot = 0;
+  long long plane_slot = 0;   // in uint32 units
+  // the overlap table is built on a side stream, beside the y forward pass (both need only
+  // the field stage's output); fork after the field stage, join before the z pass
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   uint8_t* d_flags = nullptr;
   long long flag_slot = 0;
   unsigned long long* d_keys = nullptr;
@@ -255,19 +258,19 @@ hipError_t ev_get(csngf_ctx* c, hipEvent_t* e) {
 }
 
 // Record a start event (profiling) before a launch; returns the event or nullptr.
-hipEvent_t prof_begin(csngf_ctx* c) {
+hipEvent_t prof_begin(csngf_ctx* c, hipStream_t st = nullptr) {
   if (!c->prof) return nullptr;
   hipEvent_t e = nullptr;
   if (ev_get(c, &e) != hipSuccess) return nullptr;
-  hipEventRecord(e, c->stream);
+  hipEventRecord(e, st ? st : c->stream);
   return e;
 }
 
-void prof_end(csngf_ctx* c, int type, hipEvent_t start) {
+void prof_end(csngf_ctx* c, int type, hipEvent_t start, hipStream_t st = nullptr) {
   if (!start) return;
   hipEvent_t e = nullptr;
   if (ev_get(c, &e) != hipSuccess) return;
-  hipEventRecord(e, c->stream);
+  hipEventRecord(e, st ? st : c->stream);
   c->prof_pending.push_back({type, start, e});
 }
 
@@ -294,12 +297,14 @@ void release(csngf_ctx* c) {
   if (!c) return;
   hipSetDevice(c->dev);
   if (c->stream) hipStreamSynchronize(c->stream);
+  if (c->side) hipStreamSynchronize(c->side);
   dfree(c->d_tw);
   dfree(c->d_spec);
   dfree(c->d_buf1);
   dfree(c->d_buf2);
   dfree(c->d_mask);
   dfree(c->d_sat);
+  dfree(c->d_plane);
   dfree(c->d_flags);
   dfree(c->d_keys);
   dfree(c->d_res);
@@ -318,6 +323,9 @@ void release(csngf_ctx* c) {
     hipEventDestroy(p.b);
   }
   for (auto e : c->ev_pool) hipEventDestroy(e);
+  if (c->ev_fork) hipEventDestroy(c->ev_fork);
+  if (c->ev_join) hipEventDestroy(c->ev_join);
+  if (c->side) hipStreamDestroy(c->side);
   if (c->own_stream) hipStreamDestroy(c->own_stream);
   delete c;
 }
@@ -413,20 +421,24 @@ int run_batch(csngf_ctx* c, const float* dB, const uint8_t* dmB, const int* rotq
   }
   rc = launch_fields(c, true, dB, dmB, c->nB, rotq, c->d_buf1, c->buf1_slot, c->d_mask, c->mask_slot, nullptr, slots);
   if (rc) return rc;
+  // overlap table on the side stream, concurrent with the y forward pass
+  HIPCHK(hipEventRecord(c->ev_fork, c->stream));
+  HIPCHK(hipStreamWaitEvent(c->side, c->ev_fork, 0));
   {
     const int nx = c->nB[0], ny = c->nB[1], nz = c->nB[2];
-    ev = prof_begin(c);
+    hipStream_t st = c->side;
+    ev = prof_begin(c, st);
     const dim3 gz(((nx + 1) * (ny + 1) + kThreads - 1) / kThreads, slots);
     if ((long long)nx * ny < 65536) {   // 2-D prefix sums fit 16 bits
       uint16_t* pl16 = reinterpret_cast<uint16_t*>(c->d_plane);
-      hipLaunchKernelGGL(k_sat_planes<uint16_t>, dim3(nz, slots), dim3(kSatThreads), 0, c->stream, c->d_mask, pl16, nx,
-                         ny, c->mask_slot, 2 * c->plane_slot);
-      hipLaunchKernelGGL(k_sat_z<uint16_t>, gz, dim3(kThreads), 0, c->stream, pl16, c->d_sat, nx, ny, nz,
-                         2 * c->plane_slot, c->sat_slot);
+      hipLaunchKernelGGL(k_sat_planes<uint16_t>, dim3(nz, slots), dim3(kSatThreads), 0, st, c->d_mask, pl16, nx, ny,
+                         c->mask_slot, 2 * c->plane_slot);
+      hipLaunchKernelGGL(k_sat_z<uint16_t>, gz, dim3(kThreads), 0, st, pl16, c->d_sat, nx, ny, nz, 2 * c->plane_slot,
+                         c->sat_slot);
     } else {
-      hipLaunchKernelGGL(k_sat_planes<uint32_t>, dim3(nz, slots), dim3(kSatThreads), 0, c->stream, c->d_mask,
-                         c->d_plane, nx, ny, c->mask_slot, c->plane_slot);
-      hipLaunchKernelGGL(k_sat_z<uint32_t>, gz, dim3(kThreads), 0, c->stream, c->d_plane, c->d_sat, nx, ny, nz,
+      hipLaunchKernelGGL(k_sat_planes<uint32_t>, dim3(nz, slots), dim3(kSatThreads), 0, st, c->d_mask, c->d_plane, nx,
+                         ny, c->mask_slot, c->plane_slot);
+      hipLaunchKernelGGL(k_sat_z<uint32_t>, gz, dim3(kThreads), 0, st, c->d_plane, c->d_sat, nx, ny, nz,
                          c->plane_slot, c->sat_slot);
     }
     OverlapGeom g;
@@ -435,15 +447,18 @@ int run_batch(csngf_ctx* c, const float* dB, const uint8_t* dmB, const int* rotq
       g.nB[i] = c->nB[i];
     }
     hipLaunchKernelGGL(k_bounds, dim3((c->Wd[2] * c->Wd[1] + kThreads - 1) / kThreads, slots), dim3(kThreads), 0,
-                       c->stream, c->d_sat, g, c->Wd[1], c->Wd[2], c->sat_slot, c->count_a, c->gamma, c->d_flags,
+                       st, c->d_sat, g, c->Wd[1], c->Wd[2], c->sat_slot, c->count_a, c->gamma, c->d_flags,
                        c->flag_slot);
-    prof_end(c, KT_SAT, ev);
+    prof_end(c, KT_SAT, ev, st);
     LAUNCHCHK("k_sat");
+    HIPCHK(hipEventRecord(c->ev_join, st));
   }
   // y forward: X1 [slot][f][z][y] -> X2 [slot][f][z][ky]
   rc = launch_pencil(c, false, c->d_buf1, c->d_buf2, c->nB[1], c->P[1], 0, c->ply, (long long)c->nB[1] * c->Hp,
                      (long long)c->P[1] * c->Hp, c->nf * c->nB[2], c->buf1_slot, c->buf2_slot, slots);
   if (rc) return rc;
+  // the z pass reads the kept-row flags: join the side stream
+  HIPCHK(hipStreamWaitEvent(c->stream, c->ev_join, 0));
   {
     const int nreal = c->P[1] * c->tiles * slots;
     const int nb8 = (nreal + 7) / 8 * 8;
@@ -778,8 +793,10 @@ int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims
     c->mask_slot = (nvB + 255) / 256 * 256;
     c->sat_slot = ((long long)(nB[0] + 1) * (nB[1] + 1) * (nB[2] + 1) + 63) / 64 * 64;
     c->flag_slot = ((long long)c->Wd[2] * (1 + c->Wd[1]) + 255) / 256 * 256;
-    const long long per =
-        sizeof(float2) * (c->buf1_slot + c->buf2_slot) + c->mask_slot + 4 * c->sat_slot + c->flag_slot;
+    const int plane_bytes = (long long)nB[0] * nB[1] < 65536 ? 2 : 4;   // per voxel, as the SAT kernels use
+    c->plane_slot = ((nvB * plane_bytes + 3) / 4 + 63) / 64 * 64;
+    const long long per = sizeof(float2) * (c->buf1_slot + c->buf2_slot) + c->mask_slot + 4 * c->sat_slot +
+                          4 * c->plane_slot + c->flag_slot;
     int batch = prm.batch;
     if (batch == 0) {
       size_t fr = 0, tot = 0;
@@ -790,8 +807,11 @@ int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims
     c->batch = batch;
     if ((rc = dalloc(&c->d_buf1, sizeof(float2) * c->buf1_slot * batch))) return bail(rc);
     if ((rc = dalloc(&c->d_buf2, sizeof(float2) * c->buf2_slot * batch))) return bail(rc);
-    c->d_plane = reinterpret_cast<uint32_t*>(c->d_buf2);
-    c->plane_slot = 2 * c->buf2_slot;   // >= nz * ny * nx uint32 per slot
+    if ((rc = dalloc(&c->d_plane, 4 * (size_t)c->plane_slot * batch))) return bail(rc);
+    if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess)
+      return bail(hip_fail(hipGetLastError(), "side stream"));
     if ((rc = dalloc(&c->d_mask, (size_t)c->mask_slot * batch))) return bail(rc);
     if ((rc = dalloc(&c->d_sat, 4 * (size_t)c->sat_slot * batch))) return bail(rc);
     if ((rc = dalloc(&c->d_flags, (size_t)c->flag_slot * batch))) return bail(rc);
@@ -1071,8 +1091,10 @@ extern "C" int csngf_footprint(csngf_dims dA, csngf_dims dB, const csngf_params*
   const long long nvB = (long long)nB[0] * nB[1] * nB[2];
   const long long buf1 = std::max((long long)nf * nB[2] * nB[1], (long long)Wd[2] * P[1]) * Hp;
   const long long buf2 = std::max((long long)nf * nB[2] * P[1], (long long)Wd[2] * Wd[1]) * Hp;
+  const int plane_bytes = (long long)nB[0] * nB[1] < 65536 ? 2 : 4;
   const long long per = (long long)sizeof(float2) * (buf1 + buf2) + (nvB + 255) / 256 * 256 +
                         4 * (((long long)(nB[0] + 1) * (nB[1] + 1) * (nB[2] + 1) + 63) / 64 * 64) +
+                        4 * (((nvB * plane_bytes + 3) / 4 + 63) / 64 * 64) +
                         ((long long)Wd[2] * (1 + Wd[1]) + 255) / 256 * 256;
   if (spectra_bytes) *spectra_bytes = (long long)sizeof(float2) * nf * P[2] * P[1] * Hp;
   if (slot_bytes) *slot_bytes = per;

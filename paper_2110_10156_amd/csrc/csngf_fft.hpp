@@ -355,6 +355,15 @@ __device__ __forceinline__ unsigned opaque_idx(unsigned x) {
   return x;
 }
 
+// The same without volatile: still opaque to constant folding, but the compiler may merge
+// identical ones and schedule memory accesses across it (a volatile asm is a scheduling
+// boundary, which serialises the LDS reads of consecutive butterflies).  For indices that
+// derive from opaque_tid() or from loop variables, so nothing is hoisted out of loops.
+__device__ __forceinline__ unsigned opaque_base(unsigned x) {
+  asm("" : "+v"(x));
+  return x;
+}
+
 template <int L, int R, int NS, int W, int WS, int WSO, int T, bool INV, bool FROM_LD, bool TO_ST, int NZ, typename LD,
           typename ST>
 __device__ __forceinline__ void fft_stage_io(float2* __restrict__ buf, const float2* __restrict__ tw, LD& ld, ST& st) {
@@ -379,7 +388,7 @@ __device__ __forceinline__ void fft_stage_io(float2* __restrict__ buf, const flo
 #pragma unroll
       for (int t = 0; t < R; ++t) st(base, t * NS, p, v[t], u * R + t);
     } else {
-      const unsigned wb = opaque_idx(base * WSO + p);
+      const unsigned wb = opaque_base(base * WSO + p);
 #pragma unroll
       for (int t = 0; t < R; ++t) buf[wb + t * NS * WSO] = v[t];
     }
@@ -397,7 +406,7 @@ __device__ __forceinline__ void fft_stage_io(float2* __restrict__ buf, const flo
 #pragma unroll
           for (int t = 0; t < R; ++t) v[t] = t < NZ ? ld(j, t * LR, p) : make_float2(0.f, 0.f);
         } else {
-          const unsigned rb = opaque_idx(j * WS + p);
+          const unsigned rb = opaque_base(j * WS + p);
 #pragma unroll
           for (int t = 0; t < R; ++t) v[t] = buf[rb + t * LR * WS];
         }
@@ -412,7 +421,7 @@ __device__ __forceinline__ void fft_stage_io(float2* __restrict__ buf, const flo
       const unsigned bf = tx + u * T;
       if (NBF % T == 0 || bf < NBF) {
         const unsigned p = bf % W, j = bf / W;
-        const unsigned rb = opaque_idx(j * WS + p);
+        const unsigned rb = opaque_base(j * WS + p);
 #pragma unroll
         for (int t = 0; t < R; ++t) v[u][t] = buf[rb + t * LR * WS];
       }

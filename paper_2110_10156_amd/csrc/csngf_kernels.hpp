@@ -380,31 +380,43 @@ __global__ __launch_bounds__(kThreadsF) void k_fields_x(
       }
     }
     __syncthreads();
+    const bool sq = nf != 3;
+    if (dbg_prod && slot == 0) {
+      // debug copy of the product fields of slot 0 (same arithmetic as the transform's inputs)
+      for (int e = tid; e < TY * nx; e += T) {
+        const int r = e / nx, x = e - r * nx, yy = y0 + r;
+        if (yy >= ny) continue;
+        const float n0 = ng[e], n1 = ng[TY * nx + e], n2 = ng[2 * TY * nx + e];
+        const long vox = ((long)z * ny + yy) * nx + x;
+        if (sq) {
+          const float f[6] = {n0 * n0, n1 * n1, n2 * n2, n0 * n1, n0 * n2, n1 * n2};
+          for (int k = 0; k < 6; ++k) dbg_prod[k * nv + vox] = f[k];
+        } else {
+          dbg_prod[vox] = n0;
+          dbg_prod[nv + vox] = n1;
+          dbg_prod[2 * nv + vox] = n2;
+        }
+      }
+    }
     // 6 fields (squared measure): (xx,yy), (zz,xy), (xz,yz); 3 fields (unsquared): (x,y), (z,-)
     const int npairs = (nf + 1) / 2;
 #pragma unroll 1
     for (int pair = 0; pair < npairs; ++pair) {
+      // field selection by workgroup-uniform selects, not branches, so the LDS reads of all
+      // of a butterfly's elements are in flight together:
+      //   squared:   fa = (p1 ? n2 : n0) (p0 ? n0 : n2),  fb = n1 (p0 ? n1 : p1 ? n0 : n2)
+      //   unsquared: fa = (p1 ? n2 : n0),                 fb = n1 (p0 ? 1 : 0)
+      const bool p0 = pair == 0, p1 = pair == 1;
       auto products = [&](int x0, int x1, int r) -> float2 {
         const int x = x0 + x1;
         // x >= nx reads past the row (at most Px floats past ng: the LDS layout pads it) and
         // is replaced by zero below
-        const unsigned b = opaque_idx((unsigned)(r * nx + x0));
+        const unsigned b = opaque_base((unsigned)(r * nx + x0));
         const float n0 = ng[b + x1], n1 = ng[TY * nx + b + x1], n2 = ng[2 * TY * nx + b + x1];
-        float fa, fb;
-        if (nf == 3) {
-          fa = pair == 0 ? n0 : n2;
-          fb = pair == 0 ? n1 : 0.f;
-        } else if (pair == 0) { fa = n0 * n0; fb = n1 * n1; }
-        else if (pair == 1) { fa = n2 * n2; fb = n0 * n1; }
-        else { fa = n0 * n2; fb = n1 * n2; }
-        if (dbg_prod) {
-          const int yy = y0 + r;
-          if (slot == 0 && yy < ny && x < nx) {
-            const long vox = ((long)z * ny + yy) * nx + x;
-            dbg_prod[(2 * pair) * nv + vox] = fa;
-            if (2 * pair + 1 < nf) dbg_prod[(2 * pair + 1) * nv + vox] = fb;
-          }
-        }
+        const float a1 = p1 ? n2 : n0;
+        const float a2 = sq ? (p0 ? n0 : n2) : 1.0f;
+        const float b2 = sq ? (p0 ? n1 : p1 ? n0 : n2) : (p0 ? 1.0f : 0.0f);
+        const float fa = a1 * a2, fb = n1 * b2;
         return x < nx ? make_float2(fa, fb) : make_float2(0.f, 0.f);
       };
       auto none = [](int, int, int, float2, int) {};
@@ -417,19 +429,19 @@ __global__ __launch_bounds__(kThreadsF) void k_fields_x(
       const RView oa(out + slot * out_slot_stride + (2 * pair) * fbase, 8 * fbase);
       const RView ob(out + slot * out_slot_stride + (2 * pair + 1) * fbase, 2 * pair + 1 < nf ? 8 * fbase : 0);
       const int row0 = z * ny + y0;
+      // predicated rather than branched, so the LDS reads of all of a thread's bins are in
+      // flight together: elements past TY * H read row 0 and store nothing
 #pragma unroll
       for (int u = 0; u < MU; ++u) {
-        const int e = (int)tid + u * T;
         if (u * T >= TY * H) break;
-        if (e < TY * H) {
-          const int k = bk[u], r = br[u];
-          const float2 zk = buf[k * WS + r];
-          const float2 zc = buf[(k ? Px - k : Px / 2) * WS + r];
-          const uint32_t off = y0 + r < ny ? off2(row0 + r, hp8, k) : kNoOff;
-          oa.st2(off, k ? make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y - zc.y)) : make_float2(zk.x, zc.x));
-          if (2 * pair + 1 < nf)
-            ob.st2(off, k ? make_float2(0.5f * (zk.y + zc.y), 0.5f * (zc.x - zk.x)) : make_float2(zk.y, zc.y));
-        }
+        const int e = (int)tid + u * T;
+        const bool ok = e < TY * H;
+        const int k = ok ? bk[u] : 0, r = ok ? br[u] : 0;
+        const float2 zk = buf[k * WS + r];
+        const float2 zc = buf[(k ? Px - k : Px / 2) * WS + r];
+        const uint32_t off = ok && y0 + r < ny ? off2(row0 + r, hp8, k) : kNoOff;
+        oa.st2(off, k ? make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y - zc.y)) : make_float2(zk.x, zc.x));
+        ob.st2(off, k ? make_float2(0.5f * (zk.y + zc.y), 0.5f * (zc.x - zk.x)) : make_float2(zk.y, zc.y));
       }
       __syncthreads();
     }

@@ -495,7 +495,8 @@ __global__ __launch_bounds__(kThreadsP<INV>) void k_pencil(
   auto store = [&](int k0, int k1, int p, float2 v, int) {
     int c = k0 + k1 - out_off;
     if (c < 0) c += L;
-    const bool keep = kx0 + p < H && (!rowfl || rfl[c]);
+    bool keep = kx0 + p < H;
+    if constexpr (INV) keep = keep & (!rowfl | (rfl[c] != 0));   // the flag region exists for the inverse
     dst.st2(keep ? off2(c, rs8, p) : kNoOff, v);
   };
   if (kx0 != 0) {
@@ -694,7 +695,7 @@ __global__ __launch_bounds__(kThreadsZ) void k_zpass(
       [&](int k0, int k1, int p, float2 v, int) {
         int c = k0 + k1 - out_off;
         if (c < 0) c += Pz;
-        const bool keep = kx0 + p < H && zfl[c];
+        const bool keep = (kx0 + p < H) & (zfl[c] != 0);   // no short-circuit: no branch per element
         dst.st2(keep ? off2(c, zs8, p) : kNoOff, v);
       });
 }

@@ -44,8 +44,8 @@ def kernel_bytes(nA, nB, P, rotations_per_launch=1.0):
     H = Px // 2
     Wx, Wy, Wz = (nA[i] + nB[i] - 1 for i in range(3))
     vox = nxB * nyB * nzB
-    x1 = 6 * nzB * nyB * H * 8          # after the x pass
-    x2 = 6 * nzB * Py * H * 8           # after the y forward pass
+    x1 = 6 * (nzB - 2) * (nyB - 2) * H * 8   # after the x pass (interior rows and slices)
+    x2 = 6 * (nzB - 2) * Py * H * 8          # after the y forward pass
     spec = 6 * Pz * Py * H * 8          # A's conjugate spectra
     y3 = Wz * Py * H * 8                # after the z inverse (kept rows)
     y4 = Wz * Wy * H * 8                # after the y inverse (kept rows)

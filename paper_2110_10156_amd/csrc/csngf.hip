@@ -454,8 +454,10 @@ int run_batch(csngf_ctx* c, const float* dB, const uint8_t* dmB, const int* rotq
     HIPCHK(hipEventRecord(c->ev_join, st));
   }
   // y forward: X1 [slot][f][z][y] -> X2 [slot][f][z][ky]
-  rc = launch_pencil(c, false, c->d_buf1, c->d_buf2, c->nB[1], c->P[1], 0, c->ply, (long long)c->nB[1] * c->Hp,
-                     (long long)c->P[1] * c->Hp, c->nf * c->nB[2], c->buf1_slot, c->buf2_slot, slots);
+  // (X1 holds the interior rows and slices only: the fields vanish on the border planes)
+  rc = launch_pencil(c, false, c->d_buf1, c->d_buf2, c->nB[1] - 2, c->P[1], 0, c->ply,
+                     (long long)(c->nB[1] - 2) * c->Hp, (long long)c->P[1] * c->Hp, c->nf * (c->nB[2] - 2),
+                     c->buf1_slot, c->buf2_slot, slots);
   if (rc) return rc;
   // the z pass reads the kept-row flags: join the side stream
   HIPCHK(hipStreamWaitEvent(c->stream, c->ev_join, 0));
@@ -465,13 +467,13 @@ int run_batch(csngf_ctx* c, const float* dB, const uint8_t* dmB, const int* rotq
     const size_t lds = lds_pencil(c->plz.L) + a16(c->plz.L);   // + the kept-row flags
     const int out_off = c->P[2] - (c->nA[2] - 1);
     ev = prof_begin(c);
-    // inputs z >= Pz/2 are zero when nz <= Pz/2: the forward transforms' first stage is pruned
-    const bool half = 2 * c->nB[2] <= c->plz.L;
+    // inputs z >= Pz/2 are zero when nz - 2 <= Pz/2: the forward transforms' first stage is pruned
+    const bool half = 2 * (c->nB[2] - 2) <= c->plz.L;
     with_len(c->plz.L, [&](auto lc) {
       constexpr int LC = decltype(lc)::value;
       auto go = [&](auto kern, int nblocks) {
         hipLaunchKernelGGL(kern, dim3(nblocks), dim3(kThreadsZ), lds, c->stream, c->d_buf2, c->d_spec, c->d_buf1,
-                           c->nB[2], c->P[1], c->H, c->Hp, c->Wd[2], out_off, c->plz, c->d_tw, c->buf2_slot,
+                           c->nB[2] - 2, c->P[1], c->H, c->Hp, c->Wd[2], out_off, c->plz, c->d_tw, c->buf2_slot,
                            c->buf1_slot, c->tiles, slots, nreal, c->d_flags, c->flag_slot, c->nf);
       };
       // all tiles but the packed DC/Nyquist ones, then those (tile 0 at ky = 0 and Py/2)
@@ -760,15 +762,15 @@ int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims
     }
     if (!rc) rc = launch_fields(c, false, dA_ptr, nullptr, nA, nullptr, x1, 0, nullptr, 0, nullptr, 1);
     if (!rc)
-      rc = launch_pencil(c, false, x1, x2, nA[1], P[1], 0, c->ply, (long long)nA[1] * Hp, (long long)P[1] * Hp,
-                         c->nf * nA[2], 0, 0, 1);
+      rc = launch_pencil(c, false, x1, x2, nA[1] - 2, P[1], 0, c->ply, (long long)(nA[1] - 2) * Hp,
+                         (long long)P[1] * Hp, c->nf * (nA[2] - 2), 0, 0, 1);
     if (!rc) {
       const float scale = (float)(1.0 / ((double)P[0] * (double)P[1] * (double)P[2]));
       const dim3 grid(c->tiles, P[1], c->nf);
       const size_t lds = lds_pencil(P[2]);
       with_len(P[2], [&](auto lc) {
         constexpr int LC = decltype(lc)::value;
-        hipLaunchKernelGGL((k_zstore<LC>), grid, dim3(kThreads), lds, c->stream, x2, c->d_spec, nA[2], P[1], c->H,
+        hipLaunchKernelGGL((k_zstore<LC>), grid, dim3(kThreads), lds, c->stream, x2, c->d_spec, nA[2] - 2, P[1], c->H,
                            c->Hp, c->plz, c->d_tw, scale, c->nf);
       });
       hipError_t e = hipGetLastError();

@@ -1,10 +1,10 @@
 // HIP kernels of the CSNGF hot path (gfx950).
 //
 // Data flow for one rotation slot (H = Px/2 stored half-spectrum bins along x, row pitch Hp):
-//   k_fields_x   B -> resample -> NGF -> mask -> 6 products -> x R2C    X1 [6][nz][ny][Hp]
+//   k_fields_x   B -> resample -> NGF -> mask -> 6 products -> x R2C    X1 [6][nz-2][ny-2][Hp]
 //   k_sat_*      eroded mask of B^ -> zero-bordered 3-D summed-area table (exact overlaps)
-//   k_pencil<F>  y forward, ny nonzero rows -> Py                        X2 [6][nz][Py][Hp]
-//   k_zpass      per field: z forward (nz nonzero -> Pz), multiply by A's conjugate spectrum,
+//   k_pencil<F>  y forward, ny-2 nonzero rows -> Py                      X2 [6][nz-2][Py][Hp]
+//   k_zpass      per field: z forward (nz-2 nonzero -> Pz), multiply by A's conjugate spectrum,
 //                sum over fields; then z inverse of the sum              Y3 [Wz][Py][Hp]
 //   k_pencil<I>  y inverse, kept rows = displacement range               Y4 [Wz][Wy][Hp]
 //   k_final_x    x C2R -> S(chi); N(chi) from the SAT; gamma; C = S/N; per-slot argmax key
@@ -398,8 +398,12 @@ __global__ __launch_bounds__(kThreadsF) void k_fields_x(
         }
       }
     }
-    // 6 fields (squared measure): (xx,yy), (zz,xy), (xz,yz); 3 fields (unsquared): (x,y), (z,-)
-    const int npairs = (nf + 1) / 2;
+    // 6 fields (squared measure): (xx,yy), (zz,xy), (xz,yz); 3 fields (unsquared): (x,y), (z,-).
+    // The eroded mask is 0 on the grid's border planes, so the fields vanish there: X1 keeps
+    // only the interior slices 1 .. nz-2 and rows 1 .. ny-2, and border slices skip the
+    // transform.  (A and B are both shifted by one row and slice, which leaves their
+    // correlation unchanged.)
+    const int npairs = (z == 0 || z == nz - 1) ? 0 : (nf + 1) / 2;
 #pragma unroll 1
     for (int pair = 0; pair < npairs; ++pair) {
       // field selection by workgroup-uniform selects, not branches, so the LDS reads of all
@@ -425,10 +429,10 @@ __global__ __launch_bounds__(kThreadsF) void k_fields_x(
       // split the packed transform: Fa = (Z_k + conj Z_{P-k}) / 2, Fb = -i (Z_k - conj Z_{P-k}) / 2
       // for bins 1 .. Px/2 - 1; bin 0 stores DC + i Nyquist of each field (Fa: Z_0.x + i Z_h.x,
       // Fb: Z_0.y + i Z_h.y with h = Px/2)
-      const long long fbase = (long long)nz * ny * Hp;   // elements per field
+      const long long fbase = (long long)(nz - 2) * (ny - 2) * Hp;   // elements per field
       const RView oa(out + slot * out_slot_stride + (2 * pair) * fbase, 8 * fbase);
       const RView ob(out + slot * out_slot_stride + (2 * pair + 1) * fbase, 2 * pair + 1 < nf ? 8 * fbase : 0);
-      const int row0 = z * ny + y0;
+      const int row0 = (z - 1) * (ny - 2) + y0 - 1;   // X1 row of grid row y0 (interior rows)
       // predicated rather than branched, so the LDS reads of all of a thread's bins are in
       // flight together: elements past TY * H read row 0 and store nothing
 #pragma unroll
@@ -439,7 +443,8 @@ __global__ __launch_bounds__(kThreadsF) void k_fields_x(
         const int k = ok ? bk[u] : 0, r = ok ? br[u] : 0;
         const float2 zk = buf[k * WS + r];
         const float2 zc = buf[(k ? Px - k : Px / 2) * WS + r];
-        const uint32_t off = ok && y0 + r < ny ? off2(row0 + r, hp8, k) : kNoOff;
+        const int yy = y0 + r;
+        const uint32_t off = ok && yy >= 1 && yy <= ny - 2 ? off2(row0 + r, hp8, k) : kNoOff;
         oa.st2(off, k ? make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y - zc.y)) : make_float2(zk.x, zc.x));
         ob.st2(off, k ? make_float2(0.5f * (zk.y + zc.y), 0.5f * (zc.x - zk.x)) : make_float2(zk.y, zc.y));
       }

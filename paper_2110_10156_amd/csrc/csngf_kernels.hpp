@@ -68,6 +68,12 @@ template <bool INV>
 constexpr int kTileP = INV ? CSNGF_WPI : CSNGF_WPF;     // x-bins per y pencil tile
 static_assert(kTileW % CSNGF_WPF == 0 && kTileW % CSNGF_WPI == 0, "y tiles must divide the row pitch unit");
 constexpr int kRowsX = 8;    // rows per workgroup in the field stage
+// halo samples per gather group in the field stage; the group loop is fully unrolled, so
+// the compiler interleaves the groups' gathers itself (1 measured fastest, 4 about 3% slower)
+#ifndef CSNGF_HU
+#define CSNGF_HU 1
+#endif
+constexpr int kGatherGroup = CSNGF_HU;
 #ifndef CSNGF_ROWSC
 #define CSNGF_ROWSC 4
 #endif
@@ -217,8 +223,8 @@ __global__ __launch_bounds__(kThreadsF) void k_fields_x(
     }
   }
 
-  // sample halo plane zz (rows y0-1 .. y0+TY) into ring slot (zz - z0 + 1) mod 3; HU samples
-  // at a time, all their gathers issued before any is used
+  // sample halo plane zz (rows y0-1 .. y0+TY) into ring slot (zz - z0 + 1) mod 3, in groups
+  // of HU samples whose gathers are issued before any is used
   auto fill_plane = [&](int zz) {
     float* pv = val + ((zz - z0 + 1) % 3) * plane;
     const bool zin = zz >= 0 && zz < nz;
@@ -226,7 +232,7 @@ __global__ __launch_bounds__(kThreadsF) void k_fields_x(
     const int ax = MOVING ? kq[2] * dz : 0, ay = MOVING ? kq[5] * dz : 0, az = MOVING ? kq[8] * dz : 0;
     const int limx = (nx - 1) << 17, limy = (ny - 1) << 17, limz = (nz - 1) << 17;
     const uint32_t sy4 = 4u * nx, sz4 = 4u * nx * ny;   // byte strides of B along y and z
-    constexpr int HU = 4;
+    constexpr int HU = kGatherGroup;
 #pragma unroll
     for (int u0 = 0; u0 < ME; u0 += HU) {
       if (u0 * T >= plane) break;

@@ -210,9 +210,10 @@ struct csngf_ctx {
   uint32_t* d_plane = nullptr;
   long long plane_slot = 0;   // in uint32 units
   // the overlap table is built on a side stream, beside the y forward pass (both need only
-  // the field stage's output); fork after the field stage, join before the z pass
+  // the field stage's output), followed there by the packed-column z tiles, beside the main
+  // z pass; fork after the field stage, join before the z pass and before the y inverse
   hipStream_t side = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_yfwd = nullptr, ev_zpack = nullptr;
   uint8_t* d_flags = nullptr;
   long long flag_slot = 0;
   unsigned long long* d_keys = nullptr;
@@ -325,6 +326,8 @@ void release(csngf_ctx* c) {
   for (auto e : c->ev_pool) hipEventDestroy(e);
   if (c->ev_fork) hipEventDestroy(c->ev_fork);
   if (c->ev_join) hipEventDestroy(c->ev_join);
+  if (c->ev_yfwd) hipEventDestroy(c->ev_yfwd);
+  if (c->ev_zpack) hipEventDestroy(c->ev_zpack);
   if (c->side) hipStreamDestroy(c->side);
   if (c->own_stream) hipStreamDestroy(c->own_stream);
   delete c;
@@ -459,7 +462,11 @@ int run_batch(csngf_ctx* c, const float* dB, const uint8_t* dmB, const int* rotq
                      (long long)(c->nB[1] - 2) * c->Hp, (long long)c->P[1] * c->Hp, c->nf * (c->nB[2] - 2),
                      c->buf1_slot, c->buf2_slot, slots);
   if (rc) return rc;
-  // the z pass reads the kept-row flags: join the side stream
+  // the packed-column z tiles (2 workgroups per slot) go to the side stream, after the overlap
+  // table there and the y forward here; the main z pass reads the kept-row flags, so it
+  // waits for the table; the y inverse waits for both z launches
+  HIPCHK(hipEventRecord(c->ev_yfwd, c->stream));
+  HIPCHK(hipStreamWaitEvent(c->side, c->ev_yfwd, 0));
   HIPCHK(hipStreamWaitEvent(c->stream, c->ev_join, 0));
   {
     const int nreal = c->P[1] * c->tiles * slots;
@@ -471,22 +478,25 @@ int run_batch(csngf_ctx* c, const float* dB, const uint8_t* dmB, const int* rotq
     const bool half = 2 * (c->nB[2] - 2) <= c->plz.L;
     with_len(c->plz.L, [&](auto lc) {
       constexpr int LC = decltype(lc)::value;
-      auto go = [&](auto kern, int nblocks) {
-        hipLaunchKernelGGL(kern, dim3(nblocks), dim3(kThreadsZ), lds, c->stream, c->d_buf2, c->d_spec, c->d_buf1,
+      auto go = [&](auto kern, int nblocks, hipStream_t st) {
+        hipLaunchKernelGGL(kern, dim3(nblocks), dim3(kThreadsZ), lds, st, c->d_buf2, c->d_spec, c->d_buf1,
                            c->nB[2] - 2, c->P[1], c->H, c->Hp, c->Wd[2], out_off, c->plz, c->d_tw, c->buf2_slot,
                            c->buf1_slot, c->tiles, slots, nreal, c->d_flags, c->flag_slot, c->nf);
       };
-      // all tiles but the packed DC/Nyquist ones, then those (tile 0 at ky = 0 and Py/2)
+      // the packed DC/Nyquist tiles (tile 0 at ky = 0 and Py/2) on the side stream, all other
+      // tiles here
       if (half) {
-        go(k_zpass<LC, true, false>, nb8);
-        go(k_zpass<LC, true, true>, 2 * slots);
+        go(k_zpass<LC, true, true>, 2 * slots, c->side);
+        go(k_zpass<LC, true, false>, nb8, c->stream);
       } else {
-        go(k_zpass<LC, false, false>, nb8);
-        go(k_zpass<LC, false, true>, 2 * slots);
+        go(k_zpass<LC, false, true>, 2 * slots, c->side);
+        go(k_zpass<LC, false, false>, nb8, c->stream);
       }
     });
     prof_end(c, KT_ZPASS, ev);
     LAUNCHCHK("k_zpass");
+    HIPCHK(hipEventRecord(c->ev_zpack, c->side));
+    HIPCHK(hipStreamWaitEvent(c->stream, c->ev_zpack, 0));
   }
   // y inverse: Y3 [slot][zc][ky] -> Y4 [slot][zc][yc]
   rc = launch_pencil(c, true, c->d_buf1, c->d_buf2, c->P[1], c->Wd[1], c->P[1] - (c->nA[1] - 1), c->ply,
@@ -812,7 +822,9 @@ int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims
     if ((rc = dalloc(&c->d_plane, 4 * (size_t)c->plane_slot * batch))) return bail(rc);
     if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess)
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_yfwd, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_zpack, hipEventDisableTiming) != hipSuccess)
       return bail(hip_fail(hipGetLastError(), "side stream"));
     if ((rc = dalloc(&c->d_mask, (size_t)c->mask_slot * batch))) return bail(rc);
     if ((rc = dalloc(&c->d_sat, 4 * (size_t)c->sat_slot * batch))) return bail(rc);

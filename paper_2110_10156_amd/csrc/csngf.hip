@@ -416,12 +416,7 @@ int run_batch(csngf_ctx* c, const float* dB, const uint8_t* dmB, const int* rotq
               float* cmap, long long* nmap) {
   int rc;
   hipEvent_t ev;
-  {
-    ev = prof_begin(c);
-    hipLaunchKernelGGL(k_fill_u64, dim3((slots + 63) / 64), dim3(64), 0, c->stream, c->d_keys, slots, 0ull);
-    prof_end(c, KT_MISC, ev);
-    LAUNCHCHK("k_fill_u64");
-  }
+  // (the per-slot argmax keys are cleared by k_bounds on the side stream, before the join)
   rc = launch_fields(c, true, dB, dmB, c->nB, rotq, c->d_buf1, c->buf1_slot, c->d_mask, c->mask_slot, nullptr, slots);
   if (rc) return rc;
   // overlap table on the side stream, concurrent with the y forward pass
@@ -451,7 +446,7 @@ int run_batch(csngf_ctx* c, const float* dB, const uint8_t* dmB, const int* rotq
     }
     hipLaunchKernelGGL(k_bounds, dim3((c->Wd[2] * c->Wd[1] + kThreads - 1) / kThreads, slots), dim3(kThreads), 0,
                        st, c->d_sat, g, c->Wd[1], c->Wd[2], c->sat_slot, c->count_a, c->gamma, c->d_flags,
-                       c->flag_slot);
+                       c->flag_slot, c->d_keys);
     prof_end(c, KT_SAT, ev, st);
     LAUNCHCHK("k_sat");
     HIPCHK(hipEventRecord(c->ev_join, st));

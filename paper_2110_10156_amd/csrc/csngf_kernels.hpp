@@ -888,9 +888,11 @@ __device__ __forceinline__ long long threshold(long long count_a, long long coun
 // of that z-row (resp. row) can reach the overlap threshold, so the inverse passes skip it.
 __global__ __launch_bounds__(kThreads) void k_bounds(const int* __restrict__ sat, OverlapGeom g, int Wy, int Wz,
                                                      long long sat_sstride, long long count_a, float gamma,
-                                                     uint8_t* __restrict__ flags, long long flag_sstride) {
+                                                     uint8_t* __restrict__ flags, long long flag_sstride,
+                                                     unsigned long long* __restrict__ keys) {
   const int slot = blockIdx.y;
   const int t = blockIdx.x * kThreads + threadIdx.x;
+  if (t == 0) keys[slot] = 0ull;   // the slot's argmax key, maximised by the final pass
   if (t >= Wz * Wy) return;
   const int zc = t / Wy, yc = t % Wy;
   const int* s = sat + slot * sat_sstride;
@@ -1092,11 +1094,6 @@ __global__ void k_finalize(const unsigned long long* __restrict__ keys, const in
     r.valid = 1;
   }
   res[slot] = r;
-}
-
-__global__ void k_fill_u64(unsigned long long* __restrict__ p, int n, unsigned long long v) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
 }
 
 __global__ void k_fill_f32(float* __restrict__ p, long long n, float v) {

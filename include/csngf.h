@@ -127,7 +127,10 @@ int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims
                  const csngf_params* p, csngf_ctx** out);
 
 /* Use the given hipStream_t (e.g. PyTorch's current stream) for all later work; NULL
- * restores the context's own stream.  The caller keeps ownership of the stream. */
+ * restores the context's own stream.  The caller keeps ownership of the stream.  Part of
+ * each evaluation (the overlap table and a few FFT tiles) runs on a second stream that the
+ * context owns; it forks from and joins back into this stream with events, so all work of a
+ * call is ordered on this stream as seen from outside, also under graph capture. */
 int csngf_set_stream(csngf_ctx* ctx, void* hip_stream);
 
 int csngf_get_info(const csngf_ctx* ctx, csngf_info* out);

@@ -171,9 +171,13 @@ __global__ __launch_bounds__(kThreadsF) void k_fields_x(
   constexpr int TY = kRowsX;
   constexpr int WS = xrow_stride<LC>();
   constexpr int HR = TY + 2;
-  constexpr int ME = (HR * kMaxLen + T - 1) / T;              // halo-plane samples per thread
-  constexpr int MN = (TY * kMaxLen + T - 1) / T;              // slice voxels per thread
-  constexpr int MU = (TY * (kMaxLen / 2 + 1) + T - 1) / T;    // half-spectrum bins per thread
+  // largest row this instance can see: nx <= Px, and nx <= Px / 2 when HALF; Px = LC when
+  // the length is compiled in (the host checks nx against Px before launching)
+  constexpr int NXM = LC > 0 ? (HALF ? LC / 2 : LC) : kMaxLen;
+  constexpr int PXM = LC > 0 ? LC : kMaxLen;
+  constexpr int ME = (HR * NXM + T - 1) / T;          // halo-plane samples per thread
+  constexpr int MN = (TY * NXM + T - 1) / T;          // slice voxels per thread
+  constexpr int MU = (TY * (PXM / 2) + T - 1) / T;    // half-spectrum bins per thread
   extern __shared__ __align__(16) unsigned char smem[];
   const int Px = pl.L;
   const int plane = HR * nx;

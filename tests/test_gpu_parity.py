@@ -194,6 +194,34 @@ def test_large_xy_extent_full_maps():
     _compare_maps(Cg, Ng, Co, No, "large-xy")
 
 
+@pytest.mark.parametrize("seed", [107, 115, 119])
+def test_gamma_zero_small_overlaps(seed):
+    """gamma = 0 admits every displacement with N >= 1.  S comes from an FP32 FFT whose absolute
+    error follows the fields' energy, and C = S / N passes it on undivided where N is tiny, so
+    the 1e-4 bar is checked where N >= 10; below that the absolute error of S (= dC * N) is
+    bounded instead.  N and validity are exact everywhere."""
+    from scipy.ndimage import gaussian_filter
+    rng = np.random.default_rng(seed)
+    sa = tuple(int(v) for v in rng.integers(3, 30, size=3))
+    sb = tuple(int(v) for v in rng.integers(3, 30, size=3))
+    A = gaussian_filter(rng.random(sa), 1.0).astype(np.float32)
+    B = gaussian_filter(rng.random(sb), 1.0).astype(np.float32)
+    R = _rand_rot(rng, 60)
+    _say("gamma 0", seed, sa, sb)
+    with bd.Context(A, bd.dims_of(B), gamma=0.0) as ctx:
+        P = tuple(ctx.info().pad)
+        Cg, Ng = ctx.evaluate_map(B, R)
+    Co, No, _ = _oracle_maps(A, B, R, None, 0.0, P)
+    assert np.array_equal(Ng, No)
+    vg, vo = np.isfinite(Cg), np.isfinite(Co)
+    assert np.array_equal(vg, vo)
+    d = np.abs(Cg[vo].astype(np.float64) - Co[vo])
+    n = No[vo]
+    assert float(d[n >= 10].max()) <= CTOL
+    assert float((d * n).max()) <= 1e-3
+    _say("gamma 0", seed, "max|dC| =", float(d.max()), "max|dS| =", float((d * n).max()))
+
+
 def test_padding_invariance_and_minimum_extent():
     rng = np.random.default_rng(9)
     A = rng.random((3, 4, 5)).astype(np.float32)

@@ -225,15 +225,24 @@ class Context:
         return per[:n], best
 
     def evaluate_map(self, B, R, mask_b=None, with_overlap=True, out=None):
-        """Full C map (-inf invalid) and N map for one rotation, as numpy arrays
-        (or into the given device tensors ``out=(C, N)`` for a device context)."""
+        """Full C map (-inf invalid) and N map for one rotation.  Host context: numpy arrays.
+        Device context: written into ``out=(C, N)`` (float32 and int64 device tensors of the map
+        shape, stream-ordered on the context's stream); without ``out`` they are allocated on
+        B's device and the device is synchronised before they are returned."""
         B, mask_b = self._b(B, mask_b)
         R = np.ascontiguousarray(np.asarray(R, dtype=np.float64).reshape(9))
         i = self.info()
         W = (i.map_dims[2], i.map_dims[1], i.map_dims[0])
         if self.device:
-            Cm, Nm = out
+            if out is None:
+                import torch
+                Cm = torch.empty(W, dtype=torch.float32, device=B.device)
+                Nm = torch.empty(W, dtype=torch.int64, device=B.device) if with_overlap else None
+            else:
+                Cm, Nm = out
             _check(lib().csngf_evaluate_map(self.h, _ptr(B), _ptr(mask_b), R.ctypes.data, _ptr(Cm), _ptr(Nm)))
+            if out is None:
+                torch.cuda.synchronize(B.device)
             return Cm, Nm
         Cm = np.empty(W, dtype=np.float32)
         Nm = np.empty(W, dtype=np.int64) if with_overlap else None

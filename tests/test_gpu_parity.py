@@ -332,6 +332,9 @@ def test_device_pointer_path_with_torch_stream():
         Nm = torch.empty((W[2], W[1], W[0]), dtype=torch.int64, device=dev)
         ctx.evaluate_map(B, np.eye(3), out=(Cm, Nm))
         s.synchronize()
+        Ca, Na = ctx.evaluate_map(B, np.eye(3))   # outputs allocated by the binding
+        assert Ca.device == dev and Na.dtype == torch.int64
+        assert torch.equal(Ca, Cm) and torch.equal(Na, Nm)
         bad = B.clone()
         bad[0, 0, 0] = float("nan")
         with pytest.raises(bd.CsngfError):

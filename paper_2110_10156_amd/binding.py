@@ -95,8 +95,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
-                               "or python -m paper_2110_10156_amd.build")
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_2110_10156_amd.build")
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             f = getattr(L, name)

@@ -103,6 +103,15 @@ __device__ __forceinline__ size_t align16(size_t b) { return (b + 15) & ~size_t(
 constexpr uint32_t kNoOff = 0x80000000u;
 typedef unsigned int u32x2 __attribute__((__vector_size__(8)));
 
+// Cache policy of the intermediates: every pass writes its output once, for the next pass
+// to read once, so stores (bit 0) and those loads (bit 1) are non-temporal.  That keeps them
+// from evicting what is reused: B's neighbourhoods during the gathers and A's spectra tiles
+// in the z pass.  Measured +5% on the whole path.
+#ifndef CSNGF_NT
+#define CSNGF_NT 3
+#endif
+constexpr bool kStreamSt = (CSNGF_NT & 1) != 0;
+constexpr bool kStreamLd = (CSNGF_NT & 2) != 0;
 struct RView {
   __amdgpu_buffer_rsrc_t r;
   __device__ __forceinline__ RView(const void* base, long long bytes)
@@ -115,10 +124,17 @@ struct RView {
     __builtin_memcpy(&x, &v, 8);
     return x;
   }
+  // a float2 read once and never again (a pass's input pencils): non-temporal when kStreamLd
+  __device__ __forceinline__ float2 ld2s(uint32_t off, uint32_t soff = 0) const {
+    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, (int)soff, kStreamLd ? 2 : 0);
+    float2 x;
+    __builtin_memcpy(&x, &v, 8);
+    return x;
+  }
   __device__ __forceinline__ void st2(uint32_t off, float2 x) const {
     u32x2 v;
     __builtin_memcpy(&v, &x, 8);
-    __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)off, 0, kStreamSt ? 2 : 0);
   }
   __device__ __forceinline__ unsigned ld1(uint32_t off, uint32_t soff = 0) const {
     return __builtin_amdgcn_raw_buffer_load_b8(r, (int)off, (int)soff, 0);
@@ -505,7 +521,7 @@ __global__ __launch_bounds__(kThreadsP<INV>) void k_pencil(
   constexpr int T = kThreadsP<INV>;
   auto load = [&](int i0, int i1, int p) -> float2 {
     const uint32_t b = kx0 + p < H ? off2(i0, rs8, p) : kNoOff;
-    return src.ld2(b + (uint32_t)i1 * rs8);
+    return src.ld2s(b + (uint32_t)i1 * rs8);
   };
   auto store = [&](int k0, int k1, int p, float2 v, int) {
     int c = k0 + k1 - out_off;
@@ -609,7 +625,7 @@ __global__ __launch_bounds__(kThreadsZ) void k_zpass(
   auto loader = [&](const RView& src) {
     return [&src, kx0, H, zs8](int i0, int i1, int p) -> float2 {
       const uint32_t b = kx0 + p < H ? off2(i0, zs8, p) : kNoOff;
-      return src.ld2(b + (uint32_t)i1 * zs8);
+      return src.ld2s(b + (uint32_t)i1 * zs8);
     };
   };
   if constexpr (!PACKED) {
@@ -1020,8 +1036,8 @@ __global__ __launch_bounds__(kThreadsC) void k_final_x(
     const bool lo = k < half;
     const int kk = k == half ? 0 : lo ? k : Px - k;
     const uint32_t o0 = off2(r0, hp8, kk);
-    const float2 a = rows.ld2((fmask >> (2 * p)) & 1u ? o0 : kNoOff);
-    const float2 c = rows.ld2((fmask >> (2 * p + 1)) & 1u ? o0 + hp8 : kNoOff);
+    const float2 a = rows.ld2s((fmask >> (2 * p)) & 1u ? o0 : kNoOff);
+    const float2 c = rows.ld2s((fmask >> (2 * p + 1)) & 1u ? o0 + hp8 : kNoOff);
     // k < half: S1 + i S2; k > half: conj(S1) + i conj(S2); k = 0 / half: DC / Nyquist
     const float sg = lo ? 1.0f : -1.0f;
     float2 z = make_float2(fmaf(-sg, c.y, a.x), fmaf(sg, a.y, c.x));

@@ -1036,8 +1036,9 @@ __global__ __launch_bounds__(kThreadsC) void k_final_x(
     const bool lo = k < half;
     const int kk = k == half ? 0 : lo ? k : Px - k;
     const uint32_t o0 = off2(r0, hp8, kk);
-    const float2 a = rows.ld2s((fmask >> (2 * p)) & 1u ? o0 : kNoOff);
-    const float2 c = rows.ld2s((fmask >> (2 * p + 1)) & 1u ? o0 + hp8 : kNoOff);
+    // (cached loads: each bin is read twice, for k and Px - k)
+    const float2 a = rows.ld2((fmask >> (2 * p)) & 1u ? o0 : kNoOff);
+    const float2 c = rows.ld2((fmask >> (2 * p + 1)) & 1u ? o0 + hp8 : kNoOff);
     // k < half: S1 + i S2; k > half: conj(S1) + i conj(S2); k = 0 / half: DC / Nyquist
     const float sg = lo ? 1.0f : -1.0f;
     float2 z = make_float2(fmaf(-sg, c.y, a.x), fmaf(sg, a.y, c.x));

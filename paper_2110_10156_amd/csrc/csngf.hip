@@ -216,6 +216,9 @@ struct csngf_ctx {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_yfwd = nullptr, ev_zpack = nullptr;
   uint8_t* d_flags = nullptr;
   long long flag_slot = 0;
+  // the final pass's work list (active row groups) and its length at d_work[0]
+  unsigned* d_work = nullptr;
+  long long work_slot = 0;
   unsigned long long* d_keys = nullptr;
   RotResultDev* d_res = nullptr;
   int res_cap = 0;
@@ -306,6 +309,7 @@ void release(csngf_ctx* c) {
   dfree(c->d_mask);
   dfree(c->d_sat);
   dfree(c->d_plane);
+  dfree(c->d_work);
   dfree(c->d_flags);
   dfree(c->d_keys);
   dfree(c->d_res);
@@ -446,7 +450,12 @@ int run_batch(csngf_ctx* c, const float* dB, const uint8_t* dmB, const int* rotq
     }
     hipLaunchKernelGGL(k_bounds, dim3((c->Wd[2] * c->Wd[1] + kThreads - 1) / kThreads, slots), dim3(kThreads), 0,
                        st, c->d_sat, g, c->Wd[1], c->Wd[2], c->sat_slot, c->count_a, c->gamma, c->d_flags,
-                       c->flag_slot, c->d_keys);
+                       c->flag_slot, c->d_keys, c->d_work);
+    {
+      const int items = slots * c->Wd[2] * ((c->Wd[1] + 2 * kRowsC - 1) / (2 * kRowsC));
+      hipLaunchKernelGGL(k_worklist, dim3((items + kThreads - 1) / kThreads), dim3(kThreads), 0, st, c->d_flags,
+                         c->flag_slot, c->Wd[1], c->Wd[2], 2 * kRowsC, slots, c->d_work + 64, c->d_work);
+    }
     prof_end(c, KT_SAT, ev, st);
     LAUNCHCHK("k_sat");
     HIPCHK(hipEventRecord(c->ev_join, st));
@@ -505,6 +514,10 @@ int run_batch(csngf_ctx* c, const float* dB, const uint8_t* dmB, const int* rotq
       g.nB[i] = c->nB[i];
     }
     const dim3 grid((c->Wd[1] + 2 * kRowsC - 1) / (2 * kRowsC), c->Wd[2], slots);
+    // without a map: a fixed grid over the work list of row groups that hold a valid
+    // displacement (most do not at gamma = 0.5)
+    const int items = (int)(grid.x * grid.y * grid.z);
+    const dim3 lgrid(std::min(items, 2048));
     const size_t lds = lds_final(c->plx.L, c->nB[0]);
     hipError_t ae = hipSuccess;
     ev = prof_begin(c);
@@ -515,13 +528,15 @@ int run_batch(csngf_ctx* c, const float* dB, const uint8_t* dmB, const int* rotq
         if (ae == hipSuccess)
           hipLaunchKernelGGL((k_final_x<true, LC>), grid, dim3(kThreadsC), lds, c->stream, c->d_buf2, c->d_sat,
                              c->d_keys, g, c->Wd[0], c->Wd[1], c->Wd[2], c->H, c->Hp, c->plx, c->d_tw, c->buf2_slot,
-                             c->sat_slot, c->count_a, c->gamma, cmap, nmap, c->d_flags, c->flag_slot);
+                             c->sat_slot, c->count_a, c->gamma, cmap, nmap, c->d_flags, c->flag_slot, nullptr,
+                             nullptr);
       } else {
         ae = allow_lds(k_final_x<false, LC>, lds);
         if (ae == hipSuccess)
-          hipLaunchKernelGGL((k_final_x<false, LC>), grid, dim3(kThreadsC), lds, c->stream, c->d_buf2, c->d_sat,
+          hipLaunchKernelGGL((k_final_x<false, LC>), lgrid, dim3(kThreadsC), lds, c->stream, c->d_buf2, c->d_sat,
                              c->d_keys, g, c->Wd[0], c->Wd[1], c->Wd[2], c->H, c->Hp, c->plx, c->d_tw, c->buf2_slot,
-                             c->sat_slot, c->count_a, c->gamma, cmap, nmap, c->d_flags, c->flag_slot);
+                             c->sat_slot, c->count_a, c->gamma, cmap, nmap, c->d_flags, c->flag_slot,
+                             c->d_work + 64, c->d_work);
       }
     });
     if (ae != hipSuccess) return hip_fail(ae, "hipFuncSetAttribute(k_final_x)");
@@ -802,8 +817,9 @@ int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims
     c->flag_slot = ((long long)c->Wd[2] * (1 + c->Wd[1]) + 255) / 256 * 256;
     const int plane_bytes = (long long)nB[0] * nB[1] < 65536 ? 2 : 4;   // per voxel, as the SAT kernels use
     c->plane_slot = ((nvB * plane_bytes + 3) / 4 + 63) / 64 * 64;
+    c->work_slot = (long long)c->Wd[2] * ((c->Wd[1] + 2 * kRowsC - 1) / (2 * kRowsC));
     const long long per = sizeof(float2) * (c->buf1_slot + c->buf2_slot) + c->mask_slot + 4 * c->sat_slot +
-                          4 * c->plane_slot + c->flag_slot;
+                          4 * c->plane_slot + c->flag_slot + 4 * c->work_slot;
     int batch = prm.batch;
     if (batch == 0) {
       size_t fr = 0, tot = 0;
@@ -815,6 +831,7 @@ int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims
     if ((rc = dalloc(&c->d_buf1, sizeof(float2) * c->buf1_slot * batch))) return bail(rc);
     if ((rc = dalloc(&c->d_buf2, sizeof(float2) * c->buf2_slot * batch))) return bail(rc);
     if ((rc = dalloc(&c->d_plane, 4 * (size_t)c->plane_slot * batch))) return bail(rc);
+    if ((rc = dalloc(&c->d_work, 4 * (64 + (size_t)c->work_slot * batch)))) return bail(rc);
     if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess ||
@@ -1104,7 +1121,8 @@ extern "C" int csngf_footprint(csngf_dims dA, csngf_dims dB, const csngf_params*
   const long long per = (long long)sizeof(float2) * (buf1 + buf2) + (nvB + 255) / 256 * 256 +
                         4 * (((long long)(nB[0] + 1) * (nB[1] + 1) * (nB[2] + 1) + 63) / 64 * 64) +
                         4 * (((nvB * plane_bytes + 3) / 4 + 63) / 64 * 64) +
-                        ((long long)Wd[2] * (1 + Wd[1]) + 255) / 256 * 256;
+                        ((long long)Wd[2] * (1 + Wd[1]) + 255) / 256 * 256 +
+                        4LL * Wd[2] * ((Wd[1] + 2 * kRowsC - 1) / (2 * kRowsC));
   if (spectra_bytes) *spectra_bytes = (long long)sizeof(float2) * nf * P[2] * P[1] * Hp;
   if (slot_bytes) *slot_bytes = per;
   if (pad_out)

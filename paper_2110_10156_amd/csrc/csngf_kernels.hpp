@@ -909,10 +909,12 @@ __device__ __forceinline__ long long threshold(long long count_a, long long coun
 __global__ __launch_bounds__(kThreads) void k_bounds(const int* __restrict__ sat, OverlapGeom g, int Wy, int Wz,
                                                      long long sat_sstride, long long count_a, float gamma,
                                                      uint8_t* __restrict__ flags, long long flag_sstride,
-                                                     unsigned long long* __restrict__ keys) {
+                                                     unsigned long long* __restrict__ keys,
+                                                     unsigned* __restrict__ nwork) {
   const int slot = blockIdx.y;
   const int t = blockIdx.x * kThreads + threadIdx.x;
   if (t == 0) keys[slot] = 0ull;   // the slot's argmax key, maximised by the final pass
+  if (t == 0 && slot == 0 && nwork) *nwork = 0u;   // the final pass's work list, built next
   if (t >= Wz * Wy) return;
   const int zc = t / Wy, yc = t % Wy;
   const int* s = sat + slot * sat_sstride;
@@ -947,7 +949,7 @@ __global__ __launch_bounds__(kThreadsC) void k_final_x(
     OverlapGeom g, int Wx, int Wy, int Wz, int H, int Hp, FftPlan pl, const float2* __restrict__ twtab,
     long long y4_sstride, long long sat_sstride, long long count_a, float gamma,
     float* __restrict__ cmap, long long* __restrict__ nmap, const uint8_t* __restrict__ flags,
-    long long flag_sstride) {
+    long long flag_sstride, const unsigned* __restrict__ work, const unsigned* __restrict__ nwork) {
   constexpr int T = kThreadsC;
   constexpr int WP = kRowsC;  // packed pencils
   constexpr int NR = 2 * WP;  // output rows
@@ -959,9 +961,8 @@ __global__ __launch_bounds__(kThreadsC) void k_final_x(
   float2* tw = reinterpret_cast<float2*>(smem);
   float2* buf = reinterpret_cast<float2*>(smem + align16(sizeof(float2) * Px));
   int* drow = reinterpret_cast<int*>(smem + align16(sizeof(float2) * Px) + align16(sizeof(float2) * Px * (WP + 1)));
-  const int yc0 = blockIdx.x * NR;
-  const int zc = blockIdx.y;
-  const int slot = blockIdx.z;
+  // one group of NR displacement rows (slot, zc, yc0 .. yc0 + NR - 1)
+  auto run = [&](const int slot, const int zc, const int yc0) {
   const int* s = sat + slot * sat_sstride;
   // rows whose overlap bound is below the threshold hold no valid displacement and were
   // not produced by the inverse passes; without a map to write, skip groups of such rows
@@ -978,7 +979,6 @@ __global__ __launch_bounds__(kThreadsC) void k_final_x(
     for (int rr = 0; rr < NR; ++rr) fmask |= fl[rr] ? 1u << rr : 0u;
   }
   if (!WRITE_MAP && !fmask) return;
-  load_twiddles(tw, twtab, pl);
   const int half = Px / 2;
   // D rows: for row rr (yc = yc0 + rr), D(x) = sum of the SAT over the row's z and y ranges
   // up to column x (x = 0 .. nB_x); empty ranges give D = 0.  Rows go to groups of DG
@@ -1086,6 +1086,46 @@ __global__ __launch_bounds__(kThreadsC) void k_final_x(
     for (int w = 1; w < T / 64; ++w) m = red[w] > m ? red[w] : m;
     if (m) atomicMax(keys + slot, m);
   }
+  };
+  load_twiddles(tw, twtab, pl);
+  if constexpr (WRITE_MAP) {
+    // every row group, one per workgroup (a map entry is written for every displacement)
+    run((int)blockIdx.z, (int)blockIdx.y, (int)blockIdx.x * NR);
+  } else {
+    // only the row groups that hold a valid displacement, listed by k_worklist; a fixed grid
+    // strides over the list (the reduction's barrier ends each group's use of LDS)
+    const unsigned n = *nwork;
+    for (unsigned it = blockIdx.x; it < n; it += gridDim.x) {
+      const unsigned w = work[it];
+      run((int)(w >> 24), (int)((w >> 12) & 0xFFFu), (int)(w & 0xFFFu) * NR);
+    }
+  }
+}
+
+// The final pass's work list: the (slot, zc, row group) items with any row flag set, packed
+// as slot << 24 | zc << 12 | group (slots < 256, Wz and the groups < 4096).  One global atomic
+// per workgroup; the order of the list is not deterministic, the results do not depend on it.
+__global__ __launch_bounds__(kThreads) void k_worklist(const uint8_t* __restrict__ flags, long long flag_sstride,
+                                                       int Wy, int Wz, int rows, int nslots,
+                                                       unsigned* __restrict__ work, unsigned* __restrict__ nwork) {
+  __shared__ unsigned cnt, base;
+  const int ngroups = (Wy + rows - 1) / rows;
+  const int t = blockIdx.x * kThreads + threadIdx.x;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  bool any = false;
+  unsigned item = 0, local = 0;
+  if (t < nslots * Wz * ngroups) {
+    const int grp = t % ngroups, zc = (t / ngroups) % Wz, slot = t / (ngroups * Wz);
+    const RView rf(flags + slot * flag_sstride + Wz + (long long)zc * Wy, Wy);   // rows >= Wy read 0
+    for (int r = 0; r < rows; ++r) any |= rf.ld1((uint32_t)(grp * rows + r)) != 0;
+    item = (unsigned)slot << 24 | (unsigned)zc << 12 | (unsigned)grp;
+  }
+  if (any) local = atomicAdd(&cnt, 1u);
+  __syncthreads();
+  if (threadIdx.x == 0) base = cnt ? atomicAdd(nwork, cnt) : 0u;
+  __syncthreads();
+  if (any) work[base + local] = item;
 }
 
 // Per-slot result from its key: score bits, canonical index -> displacement, exact N.

@@ -79,7 +79,7 @@ typedef struct {
   int32_t pad[3];       /* FFT size (Px, Py, Pz); 0 = automatic: the smallest supported length
                            >= n_A + n_B - 1, or the smallest one with a compile-time plan when
                            that is at most 1.5x as long (see csngf_footprint for the result) */
-  int32_t batch;        /* rotations in flight per launch sequence; 0 = automatic */
+  int32_t batch;        /* rotations in flight per launch sequence, 0 .. 255; 0 = automatic */
   uint32_t flags;       /* CSNGF_DEVICE_PTRS | CSNGF_UNSQUARED | CSNGF_GRAPHS */
 } csngf_params;
 

@@ -692,7 +692,8 @@ int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims
   if (rc) return rc;
   if (!(prm.eps > 0.f) || !std::isfinite(prm.eps)) return fail(CSNGF_E_INVALID_ARG, "eps must be finite and > 0");
   if (!(prm.gamma >= 0.f && prm.gamma <= 1.f)) return fail(CSNGF_E_INVALID_ARG, "gamma must lie in [0, 1]");
-  if (prm.batch < 0) return fail(CSNGF_E_INVALID_ARG, "batch must be >= 0");
+  if (prm.batch < 0 || prm.batch > 255)   // (the final pass's work list packs the slot in 8 bits)
+    return fail(CSNGF_E_INVALID_ARG, "batch must lie in [0, 255]");
   if (prm.flags & ~(CSNGF_DEVICE_PTRS | CSNGF_UNSQUARED | CSNGF_GRAPHS))
     return fail(CSNGF_E_INVALID_ARG, "unknown flag bits");
   if (maskA) return fail(CSNGF_E_UNSUPPORTED, "a user mask on the fixed volume is not supported (pass NULL)");

@@ -86,6 +86,10 @@ def test_create_rejects_bad_arguments_before_touching_a_device():
     p = bd.default_params()
     p.struct_size = 4
     assert _create(A, dB, params=p)[0] == bd.E_INVALID_ARG
+    for batch in (-1, 256):   # slots are packed in 8 bits in the final pass's work list
+        p = bd.default_params()
+        p.batch = batch
+        assert _create(A, dB, params=p)[0] == bd.E_INVALID_ARG
     p = bd.default_params()
     p.pad[0] = 10  # < 8 + 8 - 1
     assert _create(A, dB, params=p)[0] == bd.E_INVALID_ARG

@@ -73,9 +73,12 @@ typedef struct {
 } csngf_dims;
 
 typedef struct {
-  uint32_t struct_size; /* sizeof(csngf_params) */
+  uint32_t struct_size; /* sizeof(csngf_params) (40 bytes) */
   float eps;            /* NGF regulariser, Eq. (1); default 1e-5 */
-  float gamma;          /* minimum overlap fraction in [0, 1], Sec. 3.2; default 0.5 */
+  double gamma;         /* minimum overlap fraction in [0, 1], Sec. 3.2; default 0.5.  chi is
+                           valid iff N >= 1 and N >= gamma * m with m = min(|M_A|, |M_B^|), the
+                           product gamma * m taken in double precision (round to nearest), so
+                           a decimal gamma such as 0.3 keeps its meaning at N = 0.3 m */
   int32_t pad[3];       /* FFT size (Px, Py, Pz); 0 = automatic: the smallest supported length
                            >= n_A + n_B - 1, or the smallest one with a compile-time plan when
                            that is at most 1.5x as long (see csngf_footprint for the result) */

@@ -34,7 +34,7 @@ class Dims(C.Structure):
 
 
 class Params(C.Structure):
-    _fields_ = [("struct_size", C.c_uint32), ("eps", C.c_float), ("gamma", C.c_float),
+    _fields_ = [("struct_size", C.c_uint32), ("eps", C.c_float), ("gamma", C.c_double),
                 ("pad", C.c_int32 * 3), ("batch", C.c_int32), ("flags", C.c_uint32)]
 
 

@@ -190,7 +190,8 @@ struct csngf_ctx {
   int P[3] = {0, 0, 0};
   int Wd[3] = {0, 0, 0};
   int H = 0, Hp = 0, tiles = 0;
-  float eps = 1e-5f, gamma = 0.5f;
+  float eps = 1e-5f;
+  double gamma = 0.5;
   uint32_t flags = 0;
   int nf = 6;  // separable fields: 6 (squared measure) or 3 (unsquared)
   int batch = 1;
@@ -670,7 +671,7 @@ int csngf_default_params(csngf_params* out) {
   std::memset(out, 0, sizeof(*out));
   out->struct_size = sizeof(csngf_params);
   out->eps = 1e-5f;
-  out->gamma = 0.5f;
+  out->gamma = 0.5;
   return CSNGF_OK;
 }
 
@@ -691,7 +692,7 @@ int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims
   rc = check_dims(dB, "B");
   if (rc) return rc;
   if (!(prm.eps > 0.f) || !std::isfinite(prm.eps)) return fail(CSNGF_E_INVALID_ARG, "eps must be finite and > 0");
-  if (!(prm.gamma >= 0.f && prm.gamma <= 1.f)) return fail(CSNGF_E_INVALID_ARG, "gamma must lie in [0, 1]");
+  if (!(prm.gamma >= 0.0 && prm.gamma <= 1.0)) return fail(CSNGF_E_INVALID_ARG, "gamma must lie in [0, 1]");
   if (prm.batch < 0 || prm.batch > 255)   // (the final pass's work list packs the slot in 8 bits)
     return fail(CSNGF_E_INVALID_ARG, "batch must lie in [0, 255]");
   if (prm.flags & ~(CSNGF_DEVICE_PTRS | CSNGF_UNSQUARED | CSNGF_GRAPHS))

@@ -895,9 +895,11 @@ __device__ __forceinline__ unsigned int ordered_bits(float f) {
   return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
-__device__ __forceinline__ long long threshold(long long count_a, long long count_b, float gamma) {
+// Smallest N that meets the minimum overlap: N >= gamma * m (the product rounded to double,
+// N an integer, so N >= ceil(gamma * m)) and N >= 1.
+__device__ __forceinline__ long long threshold(long long count_a, long long count_b, double gamma) {
   const long long m = count_a < count_b ? count_a : count_b;
-  const double t = ceil((double)gamma * (double)m);
+  const double t = ceil(gamma * (double)m);
   const long long tt = (long long)t;
   return tt > 1 ? tt : 1;
 }
@@ -907,7 +909,7 @@ __device__ __forceinline__ long long threshold(long long count_a, long long coun
 // (all x of B).  flags[slot] = zflag[Wz] then rowflag[Wz][Wy]; a 0 flag means no displacement
 // of that z-row (resp. row) can reach the overlap threshold, so the inverse passes skip it.
 __global__ __launch_bounds__(kThreads) void k_bounds(const int* __restrict__ sat, OverlapGeom g, int Wy, int Wz,
-                                                     long long sat_sstride, long long count_a, float gamma,
+                                                     long long sat_sstride, long long count_a, double gamma,
                                                      uint8_t* __restrict__ flags, long long flag_sstride,
                                                      unsigned long long* __restrict__ keys,
                                                      unsigned* __restrict__ nwork) {
@@ -947,7 +949,7 @@ template <bool WRITE_MAP, int LC>
 __global__ __launch_bounds__(kThreadsC) void k_final_x(
     const float2* __restrict__ Y4, const int* __restrict__ sat, unsigned long long* __restrict__ keys,
     OverlapGeom g, int Wx, int Wy, int Wz, int H, int Hp, FftPlan pl, const float2* __restrict__ twtab,
-    long long y4_sstride, long long sat_sstride, long long count_a, float gamma,
+    long long y4_sstride, long long sat_sstride, long long count_a, double gamma,
     float* __restrict__ cmap, long long* __restrict__ nmap, const uint8_t* __restrict__ flags,
     long long flag_sstride, const unsigned* __restrict__ work, const unsigned* __restrict__ nwork) {
   constexpr int T = kThreadsC;

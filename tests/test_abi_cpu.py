@@ -39,7 +39,8 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_sizes_match_header_layout():
-    assert C.sizeof(bd.Params) == 32
+    assert C.sizeof(bd.Params) == 40
+    assert bd.Params.gamma.offset == 8 and bd.Params.pad.offset == 16 and bd.Params.flags.offset == 32
     assert C.sizeof(bd.RotResult) == 32
     assert C.sizeof(bd.Best) == 32 + 72
     assert C.sizeof(bd.Dims) == 12

@@ -1,4 +1,5 @@
-"""Many pairs in flight, graph replay and the autotuner: same results as the plain path."""
+"""Many pairs in flight, graph replay and the autotuner: same results as the plain path,
+and the same results as the FP64 oracle (Sec. 3.1 Eq. (5) and the Sec. 3.2 argmax)."""
 import sys
 
 import numpy as np
@@ -6,6 +7,7 @@ import pytest
 
 from paper_2110_10156_amd import binding as bd
 from paper_2110_10156_amd import synth
+from parity_util import check_against_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -30,6 +32,18 @@ def test_graph_replay_equals_eager_across_calls_and_pointer_changes():
     B2 = B1.clone()
     with bd.Context(A, pair.dims_b, batch=7) as eager, bd.Context(A, pair.dims_b, batch=7, graphs=True) as graph:
         ref, rb = eager.evaluate(B1, pair.rotations)
+        got0, gb0 = graph.evaluate(B1, pair.rotations)
+        _same(ref, got0)
+        # a sample of the replayed rotations (first and last full batch, the eager tail and the
+        # generating rotation) against the oracle
+        pick = [0, 6, 21, 34, 35, pair.true_index]
+        sub_best = bd.Best()
+        sub = [got0[i] for i in pick]
+        k = max(range(len(pick)), key=lambda j: (sub[j].valid, sub[j].score, -j))
+        sub_best.rot_index, sub_best.score = k, sub[k].score
+        sub_best.shift[:] = list(sub[k].shift)
+        _say("graph replay vs oracle", pick)
+        check_against_oracle(pair.A, pair.B, pair.rotations[pick], sub, sub_best, P=tuple(eager.info().pad))
         for i, B in enumerate((B1, B1, B2, B1)):
             _say("graph replay", i)
             got, gb = graph.evaluate(B, pair.rotations)     # 5 full batches replayed + 1 eager tail
@@ -51,6 +65,9 @@ def test_concurrent_contexts_equal_sequential():
     for (ps, bs), (pc, bc) in zip(seq, conc):
         _same(ps, pc)
         assert bs.rot_index == bc.rot_index
+    for c, p, r, (pc, bc) in zip(ctxs, pairs, rots, conc):
+        _say("concurrent vs oracle", p.A.shape)
+        check_against_oracle(p.A, p.B, r, pc, bc, P=tuple(c.info().pad))
     with pytest.raises(bd.CsngfError):
         ctxs[0].wait()          # nothing in flight
     for c in ctxs:

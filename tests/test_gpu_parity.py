@@ -222,6 +222,50 @@ def test_gamma_zero_small_overlaps(seed):
     _say("gamma 0", seed, "max|dC| =", float(d.max()), "max|dS| =", float((d * n).max()))
 
 
+@pytest.mark.parametrize("gamma", [0.3, 0.1, 0.6])
+def test_decimal_gamma_threshold_matches_oracle(gamma):
+    """Sec. 3.2's rule N >= gamma * m for a decimal gamma.  A's eroded mask is a 5 x 4 x 2 box
+    (m = 40 against a larger B), so gamma * m is an integer and displacements with exactly
+    N = gamma * m exist (box overlaps 1 x 4 x 1, 3 x 4 x 1, 3 x 4 x 2); they must be valid on both sides.
+    Then a rotated random pair at the same gamma."""
+    rng = np.random.default_rng(int(gamma * 100))
+    A = rng.random((4, 6, 7)).astype(np.float32)          # (nz, ny, nx): eroded box 2 x 4 x 5
+    B = rng.random((12, 12, 12)).astype(np.float32)
+    _say("decimal gamma", gamma)
+    with bd.Context(A, bd.dims_of(B), gamma=gamma) as ctx:
+        Cg, Ng = ctx.evaluate_map(B, np.eye(3))
+    Co, No, vo = _oracle_maps(A, B, np.eye(3), gamma=gamma)
+    _compare_maps(Cg, Ng, Co, No, f"gamma{gamma}-box")
+    edge = No == int(round(gamma * 40))
+    assert edge.any() and vo[edge].all() and np.isfinite(Cg[edge]).all()
+    assert not np.isfinite(Cg[No == int(round(gamma * 40)) - 1]).any()
+    from scipy.ndimage import gaussian_filter
+    sa = tuple(int(v) for v in rng.integers(6, 20, size=3))
+    sb = tuple(int(v) for v in rng.integers(6, 20, size=3))
+    A2 = gaussian_filter(rng.random(sa), 1.0).astype(np.float32)
+    B2 = gaussian_filter(rng.random(sb), 1.0).astype(np.float32)
+    R = _rand_rot(rng, 50)
+    with bd.Context(A2, bd.dims_of(B2), gamma=gamma) as ctx:
+        Cg, Ng = ctx.evaluate_map(B2, R)
+    Co, No, _ = _oracle_maps(A2, B2, R, gamma=gamma)
+    _compare_maps(Cg, Ng, Co, No, f"gamma{gamma}-rotated")
+
+
+def test_repeated_rotation_reports_the_first_index():
+    """Across rotations an exact tie goes to the smaller index: the same matrix given twice (in
+    different slots of one launch and in a later launch) scores bit-identically, and the first
+    copy is the reported best, as in the oracle."""
+    pair = synth.config0()
+    R = np.eye(3)
+    rots = np.stack([_rand_rot(np.random.default_rng(5), 40), R, R, _rand_rot(np.random.default_rng(6), 40), R])
+    with bd.Context(pair.A, pair.dims_b, batch=3) as ctx:
+        per, best = ctx.evaluate(pair.B, rots)
+    assert per[1].score == per[2].score == per[4].score
+    assert tuple(per[1].shift) == tuple(per[2].shift) == tuple(per[4].shift)
+    res, ob = O.evaluate(pair.A, pair.B, rots, P_xyz=pair.pad)
+    assert ob == 1 and best.rot_index == 1
+
+
 def test_padding_invariance_and_minimum_extent():
     rng = np.random.default_rng(9)
     A = rng.random((3, 4, 5)).astype(np.float32)

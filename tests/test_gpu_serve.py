@@ -6,6 +6,7 @@ import pytest
 
 from paper_2110_10156_amd import binding as bd
 from paper_2110_10156_amd import serve, synth
+from parity_util import check_against_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -26,7 +27,7 @@ def test_served_mix_equals_each_request_alone():
     import torch
     vols = _pool(torch)
     keys = ["c16", "c24", "c0", "m48", "c16", "c0", "m48", "c24"]
-    reqs = [serve.Request(i, k, vols[k][0], vols[k][1], synth.random_rotations(40 + 7 * i, 900 + i))
+    reqs = [serve.Request(i, k, vols[k][0], vols[k][1], synth.random_rotations(12 + 3 * i, 900 + i))
             for i, k in enumerate(keys)]
     srv = serve.Server(hbm_budget=6 << 30, slot_budget=1 << 28)
     res = serve.run_stream(srv, lambda i: reqs[i], np.zeros(len(reqs)))   # all arrive at once
@@ -40,6 +41,10 @@ def test_served_mix_equals_each_request_alone():
         assert best.rot_index == r.best.rot_index
         for a, b in zip(per, r.per):
             assert a.score == b.score and tuple(a.shift) == tuple(b.shift) and a.overlap == b.overlap
+        # and each served result against the oracle
+        _say("served request", req.rid, "vs oracle", tuple(req.A.shape))
+        check_against_oracle(req.A.cpu().numpy(), req.B.cpu().numpy(), req.rotations, r.per, r.best,
+                             P=bd.footprint(bd.dims_of(req.A), bd.dims_of(req.B))[2])
 
 
 def test_admission_by_footprint_and_eviction():

@@ -344,6 +344,38 @@ def test_range_and_numerator_bound():
     assert np.all(C[v] >= -1e-12) and np.all(C[v] <= 1 + 1e-12)
 
 
+@pytest.mark.parametrize("tenths", [1, 3, 7, 9])
+def test_gamma_rule_exact_for_decimal_fractions(tenths):
+    """Sec. 3.2's minimum overlap N >= gamma * m for gamma = tenths / 10, checked against exact
+    rational arithmetic (10 N >= tenths * m) at every N around the threshold, including the
+    m for which gamma * m is an integer (validity must hold there: N = gamma * m meets it)."""
+    from fractions import Fraction
+    gamma = tenths / 10.0
+    for m in (10, 20, 30, 70, 1000, 3_000_000, 3_232_110, 7, 13, 333_333):
+        lo = max(0, int(tenths * m // 10) - 3)
+        N = np.arange(lo, lo + 8, dtype=np.int64)
+        S = np.zeros(N.shape)
+        for ca, cb in ((m, m + 5), (m + 9, m)):         # m = min(|M_A|, |M_B^|) either way
+            _, valid = O.normalise(S, N, ca, cb, gamma)
+            exact = (N >= 1) & np.array([Fraction(int(n)) >= Fraction(tenths, 10) * m for n in N])
+            assert np.array_equal(valid, exact), (tenths, m, N[valid != exact])
+
+
+def test_cross_rotation_tie_goes_to_the_smaller_index():
+    """Equal best scores across rotations: the smaller rotation index wins.  The same matrix
+    twice gives bit-identical maps, so the first copy must be reported, wherever it sits."""
+    rng = np.random.default_rng(12)
+    A, B = rng.random((7, 8, 6)), rng.random((6, 7, 8))
+    R1, R2 = _rand_rot(rng, 30), _rand_rot(rng, 30)
+    res, best = O.evaluate(A, B, np.stack([R1, R1]))
+    assert res[0].score == res[1].score and best == 0
+    res, best = O.evaluate(A, B, np.stack([R2, R1, R1, R2]))
+    top = max(r.score for r in res)
+    assert best == min(i for i, r in enumerate(res) if r.score == top)
+    assert res[0].score == res[3].score and res[1].score == res[2].score
+    assert best in (0, 1)
+
+
 def test_argmax_tie_break_smallest_canonical_index():
     C = np.full((3, 3, 3), -np.inf)
     C[2, 0, 0] = 0.5

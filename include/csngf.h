@@ -176,6 +176,21 @@ int csngf_destroy(csngf_ctx* ctx);
 int csngf_smooth_downsample(const float* vol, csngf_dims d, float sigma, int32_t factor, float* out,
                             csngf_dims* out_dims, uint32_t flags, void* stream);
 
+/* Allocation-free form of csngf_smooth_downsample, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that forbid allocation.
+ * Same arguments and bit-identical results, but vol and out are always DEVICE pointers on the
+ * current device, and the call only enqueues the blur on stream (a hipStream_t; NULL = the
+ * default stream) and returns; no hipMalloc, hipFree or other allocating call is made.
+ * The two intermediate volumes of the separable blur (m0 n1 n2 and m0 m1 n2 floats, n = dims
+ * d, m = out dims) live in a fixed scratch array of CSNGF_NOALLOC_SCRATCH_BYTES that the
+ * library holds on each device it runs on until the process ends; inputs whose intermediates
+ * do not fit return CSNGF_E_UNSUPPORTED.  Every call on a device shares that device's array,
+ * so calls that overlap in time on one device race: order them (one stream, or events).
+ * The array is fully written before it is read, so nothing is left over from earlier calls. */
+#define CSNGF_NOALLOC_SCRATCH_BYTES (32u << 20)
+int csngf_smooth_downsample_noalloc(const float* vol, csngf_dims d, float sigma, int32_t factor, float* out,
+                                    csngf_dims* out_dims, void* stream);
+
 /* Device memory a context would hold, without allocating anything (admission control of a
  * server): *spectra_bytes for A's resident spectra, *slot_bytes per rotation slot of
  * workspace (a context holds batch slots), and the FFT size pad_out[3] that would be used.

@@ -82,6 +82,8 @@ SIGNATURES = {
                                      C.c_void_p, C.c_void_p, C.c_uint32]),
     "csngf_smooth_downsample": (C.c_int, [C.c_void_p, Dims, C.c_float, C.c_int32, C.c_void_p, C.POINTER(Dims),
                                           C.c_uint32, C.c_void_p]),
+    "csngf_smooth_downsample_noalloc": (C.c_int, [C.c_void_p, Dims, C.c_float, C.c_int32, C.c_void_p,
+                                                  C.POINTER(Dims), C.c_void_p]),
     "csngf_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
     "csngf_profile_read": (C.c_int, [C.c_void_p, C.POINTER(KernelStat), C.c_int32, C.POINTER(C.c_int32)]),
     "csngf_profile_reset": (C.c_int, [C.c_void_p]),
@@ -358,4 +360,26 @@ def smooth_downsample(vol, sigma, factor, stream=None):
     out = np.empty(shape, dtype=np.float32)
     _check(lib().csngf_smooth_downsample(_ptr(vol), dims_of(vol), float(sigma), int(factor), _ptr(out), C.byref(od),
                                          0, None))
+    return out
+
+
+NOALLOC_SCRATCH_BYTES = 32 << 20
+
+
+def smooth_downsample_noalloc(vol, sigma, factor, out=None, stream=None):
+    """csngf_smooth_downsample_noalloc on a CUDA tensor: the library allocates nothing (its
+    intermediates sit in a fixed per-device scratch array).  ``out`` (float32, the output
+    shape) is allocated here by torch when omitted; the blur is enqueued on ``stream`` (else
+    the current stream) and not synchronised."""
+    import torch
+    od = Dims()
+    _check(lib().csngf_smooth_downsample_noalloc(_ptr(vol), dims_of(vol), float(sigma), int(factor), None,
+                                                 C.byref(od), None))
+    shape = (od.nz, od.ny, od.nx)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float32, device=vol.device)
+    assert tuple(out.shape) == shape and out.dtype == torch.float32 and out.is_contiguous()
+    s = stream if stream is not None else torch.cuda.current_stream(vol.device)
+    _check(lib().csngf_smooth_downsample_noalloc(_ptr(vol), dims_of(vol), float(sigma), int(factor), _ptr(out),
+                                                 C.byref(od), C.c_void_p(s.cuda_stream)))
     return out

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <mutex>
 #include <random>
 #include <cstdint>
 #include <cstdio>
@@ -1023,35 +1024,97 @@ int csngf_destroy(csngf_ctx* c) {
   return CSNGF_OK;
 }
 
-int csngf_smooth_downsample(const float* vol, csngf_dims d, float sigma, int32_t factor, float* out,
-                            csngf_dims* out_dims, uint32_t flags, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Normalised Gaussian taps of csngf_smooth_downsample, computed in double and rounded once.
+void blur_taps(float sigma, BlurTaps* t, int* K) {
+  const int k = sigma > 0.f ? (int)(4.0 * sigma + 0.5) : 0;
+  std::vector<double> wd(2 * k + 1);
+  double sum = 0;
+  for (int j = -k; j <= k; ++j) {
+    wd[j + k] = k ? std::exp(-(double)j * j / (2.0 * (double)sigma * sigma)) : 1.0;
+    sum += wd[j + k];
+  }
+  std::memset(t, 0, sizeof(*t));
+  for (int j = 0; j <= 2 * k; ++j) t->w[j] = (float)(wd[j] / sum);
+  *K = k;
+}
+
+// The three separable passes: x keeps m0 of n0 columns (din -> t1), y m1 of n1 rows (t1 -> t2),
+// z m2 of n2 slices (t2 -> dout).  t1 holds m0 n1 n2 floats, t2 m0 m1 n2.
+hipError_t launch_pyramid(const float* din, float* t1, float* t2, float* dout, const int* n, const int* m, int factor,
+                          const BlurTaps& taps, int K, hipStream_t s) {
+  auto blur = [&](const float* a, float* b, int outer, int len, int inner, int mm) {
+    const long long total = (long long)outer * mm * inner;
+    hipLaunchKernelGGL(k_blur_axis, dim3((unsigned)((total + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, a, b,
+                       outer, len, inner, mm, factor, taps, K);
+  };
+  blur(din, t1, n[2] * n[1], n[0], 1, m[0]);          // along x
+  blur(t1, t2, n[2], n[1], m[0], m[1]);               // along y
+  blur(t2, dout, 1, n[2], m[1] * m[0], m[2]);         // along z
+  return hipGetLastError();
+}
+
+int pyramid_args(const float* vol, csngf_dims d, float sigma, int32_t factor, csngf_dims* out_dims, int* n, int* m) {
   if (!vol || !out_dims) return fail(CSNGF_E_INVALID_ARG, "NULL argument");
   if (d.nx < 1 || d.ny < 1 || d.nz < 1) return fail(CSNGF_E_INVALID_ARG, "extents must be >= 1");
   if (factor < 1) return fail(CSNGF_E_INVALID_ARG, "factor must be >= 1");
   if (!(sigma >= 0.f && sigma <= 64.f)) return fail(CSNGF_E_INVALID_ARG, "sigma must lie in [0, 64]");
-  if (flags & ~CSNGF_DEVICE_PTRS) return fail(CSNGF_E_INVALID_ARG, "unknown flag bits");
-  const int n[3] = {d.nx, d.ny, d.nz};
-  int m[3];
+  n[0] = d.nx;
+  n[1] = d.ny;
+  n[2] = d.nz;
   for (int i = 0; i < 3; ++i) m[i] = (n[i] + factor - 1) / factor;
   *out_dims = csngf_dims{m[0], m[1], m[2]};
-  if (!out) return CSNGF_OK;
-  int rc = check_device();
+  return CSNGF_OK;
+}
+
+// Scratch of csngf_smooth_downsample_noalloc: the two intermediate volumes of the separable
+// blur.  Each device the library runs on holds its own copy until the process ends.  In host
+// code the name stands for the host-side shadow, not a device address: kernels get the
+// address from scratch_on_current_device().
+constexpr size_t kScratchFloats = CSNGF_NOALLOC_SCRATCH_BYTES / sizeof(float);
+static __device__ __align__(256) float scratch[kScratchFloats];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of scratch on the current device, looked up once per device.
+int scratch_on_current_device(float** out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(CSNGF_E_UNSUPPORTED, "device index above 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = static_cast<float*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return CSNGF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int csngf_smooth_downsample(const float* vol, csngf_dims d, float sigma, int32_t factor, float* out,
+                            csngf_dims* out_dims, uint32_t flags, void* stream) {
+  int n[3], m[3];
+  int rc = pyramid_args(vol, d, sigma, factor, out_dims, n, m);
   if (rc) return rc;
+  if (flags & ~CSNGF_DEVICE_PTRS) return fail(CSNGF_E_INVALID_ARG, "unknown flag bits");
+  if (!out) return CSNGF_OK;
+  if ((rc = check_device())) return rc;
   const bool dev = flags & CSNGF_DEVICE_PTRS;
   const size_t nv = (size_t)n[0] * n[1] * n[2], mv = (size_t)m[0] * m[1] * m[2];
   if (!dev && !all_finite(vol, nv)) return fail(CSNGF_E_INVALID_ARG, "non-finite volume");
-  // taps, in double then rounded
-  const int K = sigma > 0.f ? (int)(4.0 * sigma + 0.5) : 0;
-  std::vector<float> w(2 * K + 1);
-  {
-    std::vector<double> wd(2 * K + 1);
-    double sum = 0;
-    for (int k = -K; k <= K; ++k) {
-      wd[k + K] = K ? std::exp(-(double)k * k / (2.0 * (double)sigma * sigma)) : 1.0;
-      sum += wd[k + K];
-    }
-    for (int k = 0; k <= 2 * K; ++k) w[k] = (float)(wd[k] / sum);
-  }
+  BlurTaps taps;
+  int K = 0;
+  blur_taps(sigma, &taps, &K);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   std::vector<void*> owned;
   auto done = [&](int code) {
@@ -1059,10 +1122,7 @@ int csngf_smooth_downsample(const float* vol, csngf_dims d, float sigma, int32_t
     for (void* p : owned) (void)hipFree(p);
     return code;
   };
-  float *dw = nullptr, *t1 = nullptr, *t2 = nullptr, *din = const_cast<float*>(vol), *dout = out;
-  if ((rc = dalloc(&dw, sizeof(float) * w.size()))) return done(rc);
-  owned.push_back(dw);
-  // pass x keeps m0 of n0 columns, pass y m1 of n1 rows, pass z m2 of n2 slices
+  float *t1 = nullptr, *t2 = nullptr, *din = const_cast<float*>(vol), *dout = out;
   if ((rc = dalloc(&t1, sizeof(float) * (size_t)m[0] * n[1] * n[2]))) return done(rc);
   owned.push_back(t1);
   if ((rc = dalloc(&t2, sizeof(float) * (size_t)m[0] * m[1] * n[2]))) return done(rc);
@@ -1075,23 +1135,39 @@ int csngf_smooth_downsample(const float* vol, csngf_dims d, float sigma, int32_t
     if (hipMemcpyAsync(din, vol, sizeof(float) * nv, hipMemcpyHostToDevice, s) != hipSuccess)
       return done(hip_fail(hipGetLastError(), "upload"));
   }
-  if (hipMemcpyAsync(dw, w.data(), sizeof(float) * w.size(), hipMemcpyHostToDevice, s) != hipSuccess)
-    return done(hip_fail(hipGetLastError(), "upload"));
-  auto blur = [&](const float* a, float* b, int outer, int len, int inner, int mm) {
-    const long long total = (long long)outer * mm * inner;
-    hipLaunchKernelGGL(k_blur_axis, dim3((unsigned)((total + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, a, b,
-                       outer, len, inner, mm, factor, dw, K);
-  };
-  blur(din, t1, n[2] * n[1], n[0], 1, m[0]);          // along x
-  blur(t1, t2, n[2], n[1], m[0], m[1]);               // along y
-  blur(t2, dout, 1, n[2], m[1] * m[0], m[2]);         // along z
-  hipError_t e = hipGetLastError();
+  const hipError_t e = launch_pyramid(din, t1, t2, dout, n, m, factor, taps, K, s);
   if (e != hipSuccess) return done(hip_fail(e, "k_blur_axis"));
   if (!dev) {
     if (hipMemcpyAsync(out, dout, sizeof(float) * mv, hipMemcpyDeviceToHost, s) != hipSuccess)
       return done(hip_fail(hipGetLastError(), "download"));
   }
   return done(CSNGF_OK);
+}
+
+int csngf_smooth_downsample_noalloc(const float* vol, csngf_dims d, float sigma, int32_t factor, float* out,
+                                    csngf_dims* out_dims, void* stream) {
+  int n[3], m[3];
+  int rc = pyramid_args(vol, d, sigma, factor, out_dims, n, m);
+  if (rc) return rc;
+  if (!out) return CSNGF_OK;
+  const unsigned long long need1 = (unsigned long long)m[0] * n[1] * n[2];
+  const unsigned long long need2 = (unsigned long long)m[0] * m[1] * n[2];
+  // each intermediate starts on a 256-byte boundary of the scratch array
+  const unsigned long long off2 = (need1 + 63) / 64 * 64;
+  if (off2 + need2 > kScratchFloats)
+    return fail(CSNGF_E_UNSUPPORTED, "volume too large for the allocation-free pyramid: its intermediates need " +
+                                          std::to_string(4 * (off2 + need2)) + " bytes of the " +
+                                          std::to_string(CSNGF_NOALLOC_SCRATCH_BYTES) + "-byte scratch");
+  if ((rc = check_device())) return rc;
+  float* base = nullptr;
+  if ((rc = scratch_on_current_device(&base))) return rc;
+  BlurTaps taps;
+  int K = 0;
+  blur_taps(sigma, &taps, &K);
+  const hipError_t e = launch_pyramid(vol, base, base + off2, out, n, m, factor, taps, K,
+                                      reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "k_blur_axis");
+  return CSNGF_OK;
 }
 
 // ---------------------------------------------------------------------------- footprint

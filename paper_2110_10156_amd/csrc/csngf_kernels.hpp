@@ -1173,12 +1173,20 @@ __global__ void k_check_finite(const float* __restrict__ v, long long n, int* __
 }
 
 // ------------------------------------------------------------------------------ pyramid
+// Blur taps travel by value in the kernel arguments (no device buffer): 2 K + 1 <= 513 taps,
+// K = int(4 sigma + 0.5) with sigma <= 64.
+constexpr int kMaxBlurTaps = 513;
+struct BlurTaps {
+  float w[kMaxBlurTaps];
+};
+
 // One separable pass of a Gaussian blur along one axis, keeping every step-th output sample:
 // out[.., i, ..] = sum_k w[k] in[.., clamp(i * step + k - K), ..] along the axis, edges
 // replicated.  in is [outer][n][inner] (the blurred axis in the middle), out is [outer][m][inner].
 __global__ __launch_bounds__(kThreads) void k_blur_axis(const float* __restrict__ in, float* __restrict__ out,
                                                         int outer, int n, int inner, int m, int step,
-                                                        const float* __restrict__ w, int K) {
+                                                        BlurTaps taps, int K) {
+  const float* w = taps.w;
   const long long t = (long long)blockIdx.x * kThreads + threadIdx.x;
   const long long total = (long long)outer * m * inner;
   if (t >= total) return;

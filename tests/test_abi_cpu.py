@@ -141,3 +141,26 @@ def test_automatic_fft_size_prefers_fixed_length_plans():
     assert bd.footprint((176, 176, 110), (176, 176, 110))[2] == (352, 352, 220)
     # an explicit pad is kept as given
     assert bd.footprint((100, 100, 100), (100, 100, 100), pad=(200, 200, 200))[2] == (200, 200, 200)
+
+
+def test_noalloc_pyramid_rejects_bad_and_oversized_arguments():
+    """The allocation-free pyramid entry point validates before touching a device: NULL
+    pointers, bad sigma or factor, and inputs whose intermediates exceed the fixed scratch."""
+    L = bd.lib()
+    od = bd.Dims()
+    x = C.c_void_p(256)
+    assert L.csngf_smooth_downsample_noalloc(None, bd.Dims(8, 8, 8), 1.0, 1, x, C.byref(od), None) == bd.E_INVALID_ARG
+    assert L.csngf_smooth_downsample_noalloc(x, bd.Dims(8, 8, 8), -1.0, 1, x, C.byref(od), None) == bd.E_INVALID_ARG
+    assert L.csngf_smooth_downsample_noalloc(x, bd.Dims(8, 8, 8), 1.0, 0, x, C.byref(od), None) == bd.E_INVALID_ARG
+    # output dims can be queried without an output
+    assert L.csngf_smooth_downsample_noalloc(x, bd.Dims(9, 8, 7), 1.0, 2, None, C.byref(od), None) == bd.OK
+    assert (od.nx, od.ny, od.nz) == (5, 4, 4)
+    # 256^3 at factor 1: 2 x 64 MiB of intermediates, above the 32 MiB scratch
+    rc = L.csngf_smooth_downsample_noalloc(x, bd.Dims(256, 256, 256), 1.0, 1, x, C.byref(od), None)
+    assert rc == bd.E_UNSUPPORTED and b"scratch" in L.csngf_last_error()
+    # the largest cube that fits at factor 1: 2 n^3 floats <= 8 Mi (n = 161); 162 does not
+    rc = L.csngf_smooth_downsample_noalloc(x, bd.Dims(162, 162, 162), 1.0, 1, x, C.byref(od), None)
+    assert rc == bd.E_UNSUPPORTED
+    if not _gpu_present():   # past the size check, the call needs a device
+        for dims in (bd.Dims(161, 161, 161), bd.Dims(176, 176, 110)):
+            assert L.csngf_smooth_downsample_noalloc(x, dims, 1.0, 1, x, C.byref(od), None) == bd.E_NO_DEVICE

@@ -239,6 +239,9 @@ class Context:
                 import torch
                 Cm = torch.empty(W, dtype=torch.float32, device=B.device)
                 Nm = torch.empty(W, dtype=torch.int64, device=B.device) if with_overlap else None
+                # the blocks belong to torch's current stream, where earlier work may still read
+                # them; the library writes them on the context's stream, so let that work finish
+                torch.cuda.current_stream(B.device).synchronize()
             else:
                 Cm, Nm = out
             _check(lib().csngf_evaluate_map(self.h, _ptr(B), _ptr(mask_b), R.ctypes.data, _ptr(Cm), _ptr(Nm)))

@@ -30,25 +30,29 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "rotations/s at 3.4 Mvoxel (full displacement map); p50/p99 alignment latency"
 
 
-def kernel_bytes(nA, nB, P, rotations_per_launch=1.0):
+def kernel_bytes(nA, nB, P, rotations_per_launch=1.0, kept=None):
     """Algorithmic HBM bytes per rotation of each kernel family (complex64 = 8 B).
 
     Pruned pencils: only nonzero input rows are read, H = Px/2 bins per row (the real DC and
-    Nyquist bins share one complex value), only the kept displacement rows are written. A's
-    six conjugate spectra are read once per launch sequence, shared by all of its rotations,
-    so each rotation is charged 1/rotations_per_launch of them.
+    Nyquist bins share one complex value).  A's six conjugate spectra are read once per
+    launch sequence, shared by all of its rotations, so each rotation is charged
+    1/rotations_per_launch of them.  kept = (z-rows, rows) per rotation that the
+    minimum-overlap pruning keeps (csngf_profile_rows): the z pass writes, the y inverse reads
+    and writes, and the final pass reads only those rows (plus the overlap table once).
+    Without it every displacement row is charged.
     """
     nxA, nyA, nzA = nA
     nxB, nyB, nzB = nB
     Px, Py, Pz = P
     H = Px // 2
     Wx, Wy, Wz = (nA[i] + nB[i] - 1 for i in range(3))
+    kz, kr = (Wz, Wz * Wy) if kept is None else kept
     vox = nxB * nyB * nzB
     x1 = 6 * (nzB - 2) * (nyB - 2) * H * 8   # after the x pass (interior rows and slices)
     x2 = 6 * (nzB - 2) * Py * H * 8          # after the y forward pass
     spec = 6 * Pz * Py * H * 8          # A's conjugate spectra
-    y3 = Wz * Py * H * 8                # after the z inverse (kept rows)
-    y4 = Wz * Wy * H * 8                # after the y inverse (kept rows)
+    y3 = kz * Py * H * 8                # after the z inverse (kept z-rows)
+    y4 = kr * H * 8                     # after the y inverse (kept rows)
     sat = 4 * (nxB + 1) * (nyB + 1) * (nzB + 1)
     plane = 2 if nxB * nyB < 65536 else 4   # bytes per slice prefix sum (uint16 / uint32)
     return {
@@ -57,8 +61,31 @@ def kernel_bytes(nA, nB, P, rotations_per_launch=1.0):
         "y_forward": x1 + x2,
         "z_mac_inverse": x2 + spec / rotations_per_launch + y3,
         "y_inverse": y3 + y4,
-        "x_c2r_argmax": y4,
+        "x_c2r_argmax": y4 + (sat if kept is not None else 0),
     }
+
+
+def survey_yardstick(nA, nB, P):
+    """The fixed per-rotation byte model of the method as the paper states it (Sec. 3.1: 7
+    forward and 2 inverse zero-padded real 3-D FFTs per rotation with A's 7 spectra cached and
+    read once per rotation), as three pruned complex64 pencil passes each: x writes and y
+    reads nz ny (Px/2+1) bins per field, y writes and z reads nz Py (Px/2+1), each inverse
+    moves Pz Py (Px/2+1) four times; plus B once.  A design that moves fewer bytes (here: no
+    mask transforms, spectra shared per launch, pruned inverse rows) shows up as a fraction
+    of this yardstick above its HBM-bound rate."""
+    nxB, nyB, nzB = nB
+    Px, Py, Pz = P
+    H1 = Px // 2 + 1
+    f = 7
+    x_out = f * nzB * nyB * H1 * 8
+    y_out = f * nzB * Py * H1 * 8
+    spec = f * Pz * Py * H1 * 8
+    inv = 2 * 4 * Pz * Py * H1 * 8
+    return 2 * x_out + 2 * y_out + spec + inv + 4 * nxB * nyB * nzB
+
+
+# Sec. 5.2, Table 3: FFT-based CSNGF, one evaluation, seconds, by cube side (RTX 3090; context)
+PAPER_TABLE3_S = {8: 0.002, 16: 0.002, 32: 0.002, 64: 0.008, 128: 0.088}
 
 
 KERNEL_SOURCE = {"z_mac_inverse": "k_zpass", "y_forward": "k_pencil", "y_inverse": "k_pencil",
@@ -92,14 +119,89 @@ def read_traffic(kernel, workload):
 
 
 def cpu_baseline(pair, n_rot):
+    """The FP64 oracle timed per rotation on the host: A's fixed fields once (untimed, as the
+    GPU context holds them), then for each rotation the oracle's own steps in its order
+    (resample + NGF, Eq. (6)-(8) FFT correlation, normalise, argmax).  Median over n_rot
+    rotations with the FFTs on all permitted threads, and again on one thread."""
     from oracle import csngf_oracle as O
     rots = pair.rotations[:n_rot]
-    t0 = time.perf_counter()
-    O.evaluate(pair.A, pair.B, rots, P_xyz=pair.pad)
-    dt = time.perf_counter() - t0
-    return {"value": n_rot / dt, "unit": "rotations/s", "cores": int(O.WORKERS), "kind": "oracle",
-            "sample": f"{n_rot} rotations of the 176x176x110 pair at FFT size 352x352x220 "
-                      f"(FP64 numpy/scipy, {dt:.1f} s; FFTs on {O.WORKERS} threads, the rest single-threaded)"}
+    fa = O.fixed_fields(pair.A)
+    count_a = int(np.count_nonzero(fa.mask))
+
+    def one(R):
+        fb = O.moving_fields(pair.B, O.quantize_rotation(R))
+        S, N = O.correlation_maps_fft(fa, fb, pair.pad)
+        C, _ = O.normalise(S, N, count_a, int(np.count_nonzero(fb.mask)))
+        O.argmax_map(C)
+
+    def median_time(workers):
+        saved = O.WORKERS
+        O.WORKERS = workers
+        try:
+            ts = []
+            for R in rots:
+                t0 = time.perf_counter()
+                one(R)
+                ts.append(time.perf_counter() - t0)
+        finally:
+            O.WORKERS = saved
+        return float(np.median(ts))
+
+    t_all = median_time(O.WORKERS)
+    t_one = median_time(1)
+    return {"value": round(1.0 / t_all, 4), "unit": "rotations/s", "cores": int(O.WORKERS), "kind": "oracle",
+            "sample": f"median of {n_rot} rotations of the 176x176x110 pair at FFT size 352x352x220 "
+                      f"(FP64 numpy/scipy; {t_all:.2f} s per rotation with FFTs on {O.WORKERS} threads, "
+                      f"the rest single-threaded)",
+            "one_thread": {"value": round(1.0 / t_one, 4), "unit": "rotations/s", "cores": 1,
+                           "seconds_per_rotation": round(t_one, 3)}}
+
+
+def secondary_lines(torch, bd, synth, n_small=2048, n_mid=512, sweep_reps=20):
+    """Throughput of the 32^3 pair (FFT 64^3) and the 96x96x64 pair (FFT 192x192x128), plain
+    (one rotation per launch sequence) and batched (automatic slots), and the per-evaluation
+    time by cube side (Sec. 5.2, Table 3 sweep: sides 8..128, FFT 2n per axis)."""
+    dev = torch.device("cuda:0")
+    out = {}
+
+    def rate(ctx, B, rots):
+        ctx.evaluate(B, rots[:8])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.evaluate(B, rots)
+        return len(rots) / (time.perf_counter() - t0)
+
+    for name, pair, n in (("32x32x32", synth.config0(), n_small), ("96x96x64", synth.config1(n_random=0), n_mid)):
+        A = torch.from_numpy(pair.A).to(dev)
+        B = torch.from_numpy(pair.B).to(dev)
+        rots = synth.random_rotations(n, 4242)
+        with bd.Context(A, pair.dims_b, pad=pair.pad, batch=1) as c1, bd.Context(A, pair.dims_b, pad=pair.pad) as cb:
+            plain = rate(c1, B, rots[: max(64, n // 8)])
+            batched = rate(cb, B, rots)
+            out[name] = {"fft_size": list(cb.info().pad), "slots": cb.info().batch,
+                         "plain_rotations_per_s": round(plain, 1), "batched_rotations_per_s": round(batched, 1)}
+        print(f"[bench] {name}: plain {plain:.1f} rot/s, batched {batched:.1f} rot/s", file=sys.stderr, flush=True)
+    sweep = {}
+    for side in sorted(PAPER_TABLE3_S):
+        pair = synth.cube_pair(side)
+        A = torch.from_numpy(pair.A).to(dev)
+        B = torch.from_numpy(pair.B).to(dev)
+        R1 = np.eye(3)[None]
+        with bd.Context(A, pair.dims_b, pad=pair.pad, batch=1) as c1, bd.Context(A, pair.dims_b, pad=pair.pad) as cb:
+            c1.evaluate(B, R1)
+            ts = []
+            for _ in range(sweep_reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                c1.evaluate(B, R1)        # one evaluation, host to host
+                ts.append(time.perf_counter() - t0)
+            batched = rate(cb, B, synth.random_rotations(256, 4243))
+        sweep[str(side)] = {"fft_size": list(pair.pad), "ms_per_evaluation": round(float(np.median(ts)) * 1e3, 3),
+                            "batched_ms_per_rotation": round(1e3 / batched, 4),
+                            "paper_table3_ms_rtx3090": PAPER_TABLE3_S[side] * 1e3}
+        print(f"[bench] cube {side}: {sweep[str(side)]}", file=sys.stderr, flush=True)
+    out["cube_side_sweep"] = sweep
+    return out
 
 
 def many_pairs(torch, bd, synth, big_pair, n_pairs, n_rot, budget_gib=160.0):
@@ -161,32 +263,57 @@ def many_pairs(torch, bd, synth, big_pair, n_pairs, n_rot, budget_gib=160.0):
     return out
 
 
-def serving(torch, bd, synth, big_pair, rates, n_req, n_rot, budget_gib=96.0):
-    """Poisson request streams: each request pairs a fixed volume of a size drawn uniformly
-    from synth.MIXED_SHAPES with its moving volume and n_rot random rotations.  One phantom
-    pair per size stands in for every request of that size, so the spectra cache is keyed by
-    size.  Latency is finish - arrival on the server clock."""
+def requests_for_rate(rate, cap):
+    """Requests per rate: about 8 s of arrivals, at least 12 and at most cap."""
+    return int(max(12, min(cap, round(8 * rate))))
+
+
+def serving(torch, bd, synth, big_pair, rates, n_cap, n_rot, miss_rate=0.5, budget_gib=96.0):
+    """Poisson request streams.  Each request pairs a fixed volume of a size drawn uniformly
+    from synth.MIXED_SHAPES with its moving volume and n_rot random rotations.  With
+    probability miss_rate the request brings a fixed volume the server has never seen (the
+    size's phantom plus fresh noise, so its spectra must be computed and a context admitted),
+    otherwise it reuses the size's phantom, whose context is cached.  Latency is finish -
+    arrival on the server clock, reported for all requests and separately for cache hits and
+    misses.  Volumes are built on the device before each stream starts."""
     from paper_2110_10156_amd import serve
     dev = torch.device("cuda:0")
     vols = {}
     for sz in synth.MIXED_SHAPES:
         p = big_pair if sz == big_pair.dims_a else synth.mixed_pair_of_size(sz)
         vols[sz] = (torch.from_numpy(p.A).to(dev), torch.from_numpy(p.B).to(dev))
-    out = {"requests_per_rate": n_req, "rotations_per_request": n_rot, "hbm_budget_gib": budget_gib}
+    out = {"rotations_per_request": n_rot, "hbm_budget_gib": budget_gib, "miss_rate": miss_rate,
+           "what": "latency = finish - arrival; a miss computes a new fixed volume's spectra"}
     srv = serve.Server(hbm_budget=int(budget_gib * 2**30))
     warm = [serve.Request(-1 - i, str(sz), *vols[sz], synth.random_rotations(8, 77)) for i, sz in
             enumerate(synth.MIXED_SHAPES)]
     serve.run_stream(srv, lambda i: warm[i], np.zeros(len(warm)))
     for rate in rates:
+        n_req = requests_for_rate(rate, n_cap)
         rng = np.random.default_rng(int(rate * 100))
         sizes = [synth.MIXED_SHAPES[int(rng.integers(0, len(synth.MIXED_SHAPES)))] for _ in range(n_req)]
+        miss = rng.random(n_req) < miss_rate
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(int(rate * 1000))
+        fixed = []
+        for i, sz in enumerate(sizes):
+            A0 = vols[sz][0]
+            if miss[i]:
+                A1 = A0 + 1e-3 * torch.randn(A0.shape, device=dev, generator=gen)
+                fixed.append((f"{sz}-{rate:g}-{i}", A1))
+            else:
+                fixed.append((str(sz), A0))
+        torch.cuda.synchronize()
         rots = [synth.random_rotations(n_rot, 7000 + i) for i in range(n_req)]
         arr = serve.poisson_arrivals(rate, n_req, seed=int(rate * 10))
-        res = serve.run_stream(srv, lambda i: serve.Request(i, str(sizes[i]), *vols[sizes[i]], rots[i]), arr)
+        res = serve.run_stream(srv, lambda i: serve.Request(i, fixed[i][0], fixed[i][1], vols[sizes[i]][1],
+                                                            rots[i]), arr)
         summ = serve.summarize(res, n_rot)
         out[f"{rate:g}_req_per_s"] = summ
         print(f"[bench] serving {rate:g} req/s: {summ}", file=sys.stderr, flush=True)
+        del fixed
     out["contexts_created"] = srv.stats.created
+    out["contexts_evicted"] = srv.stats.evicted
     out["peak_in_flight"] = srv.stats.peak_inflight
     srv.close()
     return out
@@ -199,7 +326,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--rotations", type=int, default=1000, help="rotations per step")
     ap.add_argument("--batch", type=int, default=0, help="rotation slots in flight (0 = library default)")
-    ap.add_argument("--cpu-rotations", type=int, default=2, help="oracle sample size (0 = skip)")
+    ap.add_argument("--cpu-rotations", type=int, default=3,
+                    help="oracle sample: rotations timed (median), on all threads and on one (0 = skip)")
     ap.add_argument("--plain-rotations", type=int, default=64,
                     help="rotations timed on the one-rotation-per-launch path (0 = skip)")
     ap.add_argument("--usngf-rotations", type=int, default=200,
@@ -209,9 +337,14 @@ def main():
     ap.add_argument("--batched-pairs", type=int, default=32,
                     help="uneven volume pairs (48^3 .. 176x176x110) for the many-pairs measurement (0 = skip)")
     ap.add_argument("--batched-rotations", type=int, default=256, help="rotations per pair in that measurement")
-    ap.add_argument("--serve-rates", default="5,10,20",
+    ap.add_argument("--serve-rates", default="1,2,5,10,20",
                     help="Poisson arrival rates (requests/s) for the serving measurement ('' = skip)")
-    ap.add_argument("--serve-requests", type=int, default=40, help="requests per rate")
+    ap.add_argument("--serve-requests", type=int, default=100,
+                    help="most requests per rate (each rate gets about 8 s of arrivals, at least 12)")
+    ap.add_argument("--serve-miss-rate", type=float, default=0.5,
+                    help="fraction of requests that bring a fixed volume the server has not seen")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the 32^3 / 96x96x64 throughput lines and the cube-side sweep")
     ap.add_argument("--serve-rotations", type=int, default=200, help="rotations per request")
     ap.add_argument("--no-profile", action="store_true", help="do not record per-kernel events")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -273,26 +406,40 @@ def main():
     elapsed = t1 - t0
     value = args.steps * len(rots) / elapsed
 
-    roofline = None
+    roofline = roofline_fields = None
+    kept = None
     seq_rot = len(rots) / math.ceil(len(rots) / slots)   # mean rotations per launch sequence
-    kb = kernel_bytes(pair.dims_a, pair.dims_b, tuple(info.pad), seq_rot)
     if stats:
-        dom = max((k for k in kb if stats.get(k, (0, 0))[0] > 0), key=lambda k: stats[k][1])
-        launches, ms = stats[dom]
+        kz, kr, nr = ctx.profile_rows()
+        if nr > 0:
+            kept = (kz / nr, kr / nr)
+    kb = kernel_bytes(pair.dims_a, pair.dims_b, tuple(info.pad), seq_rot, kept)
+
+    def roof(kernel):
+        launches, ms = stats[kernel]
         per_launch_rot = len(rots) * args.steps / launches
-        alg = kb[dom] * per_launch_rot
+        alg = kb[kernel] * per_launch_rot
         avg_s = ms / launches / 1e3
         achieved = alg / avg_s / 1e9
-        tr = read_traffic(dom, "176x176x110")
-        traffic = None
-        if tr is not None:
-            traffic = tr[0] / tr[1] * per_launch_rot
-        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
-                    "avg_launch_ms": round(avg_s * 1e3, 4), "rotations_per_launch": per_launch_rot,
-                    "alg_bytes_per_launch": alg,
-                    "kernels_ms_per_rotation": {k: round(v[1] / (len(rots) * args.steps), 5)
-                                                for k, v in stats.items() if v[0]}}
+        tr = read_traffic(kernel, "176x176x110")
+        traffic = None if tr is None else tr[0] / tr[1] * per_launch_rot
+        return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kernel,
+                "avg_launch_ms": round(avg_s * 1e3, 4), "rotations_per_launch": per_launch_rot,
+                "alg_bytes_per_launch": alg}
+
+    if stats:
+        dom = max((k for k in kb if stats.get(k, (0, 0))[0] > 0), key=lambda k: stats[k][1])
+        roofline = roof(dom)
+        roofline["kernels_ms_per_rotation"] = {k: round(v[1] / (len(rots) * args.steps), 5)
+                                               for k, v in stats.items() if v[0]}
+        if kept is not None:
+            roofline["kept_rows_per_rotation"] = {"z_rows": round(kept[0], 2), "rows": round(kept[1], 1),
+                                                  "of_z_rows": pair.dims_a[2] + pair.dims_b[2] - 1,
+                                                  "of_rows": (pair.dims_a[2] + pair.dims_b[2] - 1)
+                                                  * (pair.dims_a[1] + pair.dims_b[1] - 1)}
+        if stats.get("fields_x", (0, 0))[0] > 0:
+            roofline_fields = roof("fields_x")
         print(f"[bench] kernel ms/rotation: {roofline['kernels_ms_per_rotation']}", file=sys.stderr, flush=True)
 
     plain = None
@@ -346,7 +493,11 @@ def main():
     served = None
     if args.serve_rates:
         served = serving(torch, bd, synth, pair, [float(r) for r in args.serve_rates.split(",")],
-                         args.serve_requests, args.serve_rotations)
+                         args.serve_requests, args.serve_rotations, miss_rate=args.serve_miss_rate)
+
+    secondary = None
+    if not args.no_secondary:
+        secondary = secondary_lines(torch, bd, synth)
 
     cpu = None
     if args.cpu_rotations > 0:
@@ -355,6 +506,7 @@ def main():
 
     lat_ms = np.array(lat) * 1e3
     yard = sum(kb.values())
+    survey_yard = survey_yardstick(pair.dims_a, pair.dims_b, tuple(info.pad))
     out = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -380,9 +532,17 @@ def main():
         "plain_rotations_per_s": None if plain is None else round(plain, 2),
         "usngf_rotations_per_s": None if usngf is None else round(usngf, 2),
         "path_bytes_per_rotation": yard,
+        "path_bytes_kept_rows": kept is not None,
         "path_hbm_frac": round(yard * value / (HBM_PEAK_GBS * 1e9), 4),
+        "yardstick_bytes_per_rotation": survey_yard,
+        "yardstick_frac": round(survey_yard * value / (HBM_PEAK_GBS * 1e9), 4),
+        "yardstick_what": "fixed byte model of the paper's 7 forward + 2 inverse FFTs with A's 7 spectra read per "
+                          "rotation; this design skips the mask transforms, shares A's spectra per launch and "
+                          "prunes inverse rows, so this fraction can exceed what its own kernels move",
+        "secondary": secondary,
         "best": {"rot_index": best.rot_index, "shift": list(best.shift), "score": best.score},
         "roofline": roofline,
+        "roofline_field_stage": roofline_fields,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

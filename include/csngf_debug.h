@@ -49,7 +49,16 @@ int csngf_profile_enable(csngf_ctx* ctx, int32_t enable);
  * copy up to max entries into out; *count receives the number of families. */
 int csngf_profile_read(csngf_ctx* ctx, csngf_kernel_stat* out, int32_t max, int32_t* count);
 
+/* Clear the per-family totals and the kept-row counts. */
 int csngf_profile_reset(csngf_ctx* ctx);
+
+/* Displacement rows kept by the minimum-overlap pruning (Sec. 3.2), summed over the rotations
+ * evaluated while profiling was enabled since the last reset: *z_rows = z-rows with a flag
+ * set (of W_z per rotation), *rows = (z, y) rows with a flag set (of W_z W_y), *rotations =
+ * the rotations counted.  They are the rows that the pruned inverse passes write and read,
+ * so a benchmark can charge those passes the bytes they move.  Any output may be NULL;
+ * synchronises the context's streams. */
+int csngf_profile_rows(csngf_ctx* ctx, int64_t* z_rows, int64_t* rows, int64_t* rotations);
 
 #ifdef __cplusplus
 }

@@ -87,6 +87,8 @@ SIGNATURES = {
     "csngf_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
     "csngf_profile_read": (C.c_int, [C.c_void_p, C.POINTER(KernelStat), C.c_int32, C.POINTER(C.c_int32)]),
     "csngf_profile_reset": (C.c_int, [C.c_void_p]),
+    "csngf_profile_rows": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                     C.POINTER(C.c_int64)]),
 }
 
 _lib = None
@@ -264,6 +266,12 @@ class Context:
         cnt = C.c_int32()
         _check(lib().csngf_profile_read(self.h, stats, 16, C.byref(cnt)))
         return {stats[i].name.decode(): (stats[i].launches, stats[i].total_ms) for i in range(min(cnt.value, 16))}
+
+    def profile_rows(self):
+        """(kept z-rows, kept rows, rotations) counted while profiling (minimum-overlap pruning)."""
+        z, r, n = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib().csngf_profile_rows(self.h, C.byref(z), C.byref(r), C.byref(n)))
+        return z.value, r.value, n.value
 
     def close(self):
         if getattr(self, "h", None):

@@ -250,6 +250,9 @@ struct csngf_ctx {
   std::vector<hipEvent_t> ev_pool;
   long long stat_launches[KT_COUNT] = {0};
   double stat_ms[KT_COUNT] = {0};
+  // kept displacement rows while profiling: [0] z-rows, [1] (z, y) rows; rotations counted
+  unsigned long long* d_rowstat = nullptr;
+  long long stat_rotations = 0;
 };
 
 namespace {
@@ -321,6 +324,7 @@ void release(csngf_ctx* c) {
   dfree(c->d_flag);
   dfree(c->d_rot_stage);
   dfree(c->d_res_stage);
+  dfree(c->d_rowstat);
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->done_ev) (void)hipEventDestroy(c->done_ev);
   if (c->h_res) hipHostFree(c->h_res);
@@ -452,7 +456,8 @@ int run_batch(csngf_ctx* c, const float* dB, const uint8_t* dmB, const int* rotq
     }
     hipLaunchKernelGGL(k_bounds, dim3((c->Wd[2] * c->Wd[1] + kThreads - 1) / kThreads, slots), dim3(kThreads), 0,
                        st, c->d_sat, g, c->Wd[1], c->Wd[2], c->sat_slot, c->count_a, c->gamma, c->d_flags,
-                       c->flag_slot, c->d_keys, c->d_work);
+                       c->flag_slot, c->d_keys, c->d_work, c->prof ? c->d_rowstat : nullptr);
+    if (c->prof) c->stat_rotations += slots;
     {
       const int items = slots * c->Wd[2] * ((c->Wd[1] + 2 * kRowsC - 1) / (2 * kRowsC));
       hipLaunchKernelGGL(k_worklist, dim3((items + kThreads - 1) / kThreads), dim3(kThreads), 0, st, c->d_flags,
@@ -845,6 +850,9 @@ int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims
     if ((rc = dalloc(&c->d_sat, 4 * (size_t)c->sat_slot * batch))) return bail(rc);
     if ((rc = dalloc(&c->d_flags, (size_t)c->flag_slot * batch))) return bail(rc);
     if ((rc = dalloc(&c->d_keys, sizeof(unsigned long long) * batch))) return bail(rc);
+    if ((rc = dalloc(&c->d_rowstat, 2 * sizeof(unsigned long long)))) return bail(rc);
+    if (hipMemset(c->d_rowstat, 0, 2 * sizeof(unsigned long long)) != hipSuccess)
+      return bail(hip_fail(hipGetLastError(), "hipMemset"));
     if (prm.flags & CSNGF_GRAPHS) {
       if ((rc = dalloc(&c->d_rot_stage, sizeof(int) * 9 * (size_t)batch))) return bail(rc);
       if ((rc = dalloc(&c->d_res_stage, sizeof(RotResultDev) * (size_t)batch))) return bail(rc);
@@ -1430,11 +1438,26 @@ int csngf_profile_read(csngf_ctx* c, csngf_kernel_stat* out, int32_t max, int32_
 int csngf_profile_reset(csngf_ctx* c) {
   if (!c) return fail(CSNGF_E_INVALID_ARG, "ctx is NULL");
   HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(hipStreamSynchronize(c->side));
   prof_fold(c);
   for (int i = 0; i < KT_COUNT; ++i) {
     c->stat_launches[i] = 0;
     c->stat_ms[i] = 0;
   }
+  HIPCHK(hipMemset(c->d_rowstat, 0, 2 * sizeof(unsigned long long)));
+  c->stat_rotations = 0;
+  return CSNGF_OK;
+}
+
+int csngf_profile_rows(csngf_ctx* c, int64_t* z_rows, int64_t* rows, int64_t* rotations) {
+  if (!c) return fail(CSNGF_E_INVALID_ARG, "ctx is NULL");
+  HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(hipStreamSynchronize(c->side));
+  unsigned long long h[2] = {0, 0};
+  HIPCHK(hipMemcpy(h, c->d_rowstat, sizeof(h), hipMemcpyDeviceToHost));
+  if (z_rows) *z_rows = (int64_t)h[0];
+  if (rows) *rows = (int64_t)h[1];
+  if (rotations) *rotations = c->stat_rotations;
   return CSNGF_OK;
 }
 

@@ -905,19 +905,11 @@ __device__ __forceinline__ long long threshold(long long count_a, long long coun
 }
 
 // ------------------------------------------------------------------------------ gamma pruning
-// Upper bounds of N(chi) from the SAT: over a z-row (all y and x of B) and over a (z, y) row
-// (all x of B).  flags[slot] = zflag[Wz] then rowflag[Wz][Wy]; a 0 flag means no displacement
-// of that z-row (resp. row) can reach the overlap threshold, so the inverse passes skip it.
-__global__ __launch_bounds__(kThreads) void k_bounds(const int* __restrict__ sat, OverlapGeom g, int Wy, int Wz,
-                                                     long long sat_sstride, long long count_a, double gamma,
-                                                     uint8_t* __restrict__ flags, long long flag_sstride,
-                                                     unsigned long long* __restrict__ keys,
-                                                     unsigned* __restrict__ nwork) {
-  const int slot = blockIdx.y;
-  const int t = blockIdx.x * kThreads + threadIdx.x;
-  if (t == 0) keys[slot] = 0ull;   // the slot's argmax key, maximised by the final pass
-  if (t == 0 && slot == 0 && nwork) *nwork = 0u;   // the final pass's work list, built next
-  if (t >= Wz * Wy) return;
+// One (zc, yc) row of k_bounds: its row flag, and for yc = 0 its z-row flag.
+__device__ __forceinline__ void bounds_row(const int* __restrict__ sat, const OverlapGeom& g, int Wy, int Wz,
+                                           long long sat_sstride, long long count_a, double gamma,
+                                           uint8_t* __restrict__ flags, long long flag_sstride, int slot, int t,
+                                           bool* rowflag, bool* zflag) {
   const int zc = t / Wy, yc = t % Wy;
   const int* s = sat + slot * sat_sstride;
   const int X = g.nB[0] + 1, Y = g.nB[1] + 1;
@@ -930,13 +922,43 @@ __global__ __launch_bounds__(kThreads) void k_bounds(const int* __restrict__ sat
   auto at = [&](int z, int y) { return (long long)s[((long long)z * Y + y) * X + (X - 1)]; };
   long long rb = 0;
   if (lz <= hz && ly <= hy) rb = at(hz + 1, hy + 1) - at(lz, hy + 1) - at(hz + 1, ly) + at(lz, ly);
-  f[Wz + t] = rb >= thr ? 1 : 0;
+  *rowflag = rb >= thr;
+  f[Wz + t] = *rowflag ? 1 : 0;
   if (yc == 0) {
     long long pb = 0;
     if (lz <= hz) pb = at(hz + 1, Y - 1) - at(lz, Y - 1);
-    f[zc] = pb >= thr ? 1 : 0;
+    *zflag = pb >= thr;
+    f[zc] = *zflag ? 1 : 0;
   }
 }
+
+// Upper bounds of N(chi) from the SAT: over a z-row (all y and x of B) and over a (z, y) row
+// (all x of B).  flags[slot] = zflag[Wz] then rowflag[Wz][Wy]; a 0 flag means no displacement
+// of that z-row (resp. row) can reach the overlap threshold, so the inverse passes skip it.
+// rowstat (optional, measurement): rowstat[0] += flagged z-rows, rowstat[1] += flagged rows.
+__global__ __launch_bounds__(kThreads) void k_bounds(const int* __restrict__ sat, OverlapGeom g, int Wy, int Wz,
+                                                     long long sat_sstride, long long count_a, double gamma,
+                                                     uint8_t* __restrict__ flags, long long flag_sstride,
+                                                     unsigned long long* __restrict__ keys,
+                                                     unsigned* __restrict__ nwork,
+                                                     unsigned long long* __restrict__ rowstat) {
+  const int slot = blockIdx.y;
+  const int t = blockIdx.x * kThreads + threadIdx.x;
+  if (t == 0) keys[slot] = 0ull;   // the slot's argmax key, maximised by the final pass
+  if (t == 0 && slot == 0 && nwork) *nwork = 0u;   // the final pass's work list, built next
+  bool rowflag = false, zflag = false;
+  if (t < Wz * Wy) bounds_row(sat, g, Wy, Wz, sat_sstride, count_a, gamma, flags, flag_sstride, slot, t,
+                              &rowflag, &zflag);
+  if (rowstat) {
+    // one atomic per wave and counter; every lane of the wave reaches the ballots
+    const unsigned long long br = __ballot(rowflag), bz = __ballot(zflag);
+    if ((threadIdx.x & 63) == 0) {
+      if (br) atomicAdd(rowstat + 1, (unsigned long long)__popcll(br));
+      if (bz) atomicAdd(rowstat, (unsigned long long)__popcll(bz));
+    }
+  }
+}
+
 
 // ------------------------------------------------------------------------------ final x pass
 // Workgroup (row group, zc, slot): 8 packed complex pencils = 16 output rows (yc).

@@ -197,13 +197,25 @@ def run_stream(server: Server, make_request, arrivals, idle_sleep=2e-4):
 
 
 def summarize(results, rotations_per_request):
+    """Latency percentiles (ms) over all requests and separately over cache hits and misses
+    (a miss created a context: A's spectra were computed for it), and the sustained rate."""
     lat = np.array([r.latency for r in results]) * 1e3
+    hit = np.array([r.cache_hit for r in results], dtype=bool)
     span = max(r.finish for r in results) - min(r.arrival for r in results)
+
+    def pct(x):
+        if x.size == 0:
+            return None
+        return {"n": int(x.size), "p50_ms": round(float(np.percentile(x, 50)), 2),
+                "p99_ms": round(float(np.percentile(x, 99)), 2)}
+
     return {
         "requests": len(results),
         "p50_ms": round(float(np.percentile(lat, 50)), 2),
         "p99_ms": round(float(np.percentile(lat, 99)), 2),
         "mean_ms": round(float(lat.mean()), 2),
         "rotations_per_s": round(len(results) * rotations_per_request / span, 1),
-        "cache_hits": int(sum(r.cache_hit for r in results)),
+        "cache_hits": int(hit.sum()),
+        "hits": pct(lat[hit]),
+        "misses": pct(lat[~hit]),
     }

@@ -266,6 +266,52 @@ def test_repeated_rotation_reports_the_first_index():
     assert ob == 1 and best.rot_index == 1
 
 
+def test_kept_row_counts_match_overlap_bounds():
+    """The minimum-overlap pruning (Sec. 3.2) keeps a displacement row (z, y) when the count of
+    the moving mask over A's box rows shifted by (chi_z, chi_y) and all x reaches the threshold
+    (an upper bound of N on that row), and a z-row likewise over all y and x.  The counters the
+    benchmark reads must equal those rules recomputed from the oracle's mask, and every row
+    that holds a valid displacement must be kept."""
+    import math as _m
+    pair = synth.config0()
+    rng = np.random.default_rng(21)
+    rots = np.stack([np.eye(3), _rand_rot(rng, 40), _rand_rot(rng, 70)])
+    nza, nya, nxa = pair.A.shape
+    nzb, nyb, nxb = pair.B.shape
+    Wz, Wy = nza + nzb - 1, nya + nyb - 1
+    want_z = want_r = 0
+    maps = []
+    with bd.Context(pair.A, pair.dims_b, pad=pair.pad, batch=2) as ctx:
+        ctx.profile_reset()
+        ctx.profile_enable(True)
+        ctx.evaluate(pair.B, rots)
+        kz, kr, nrot = ctx.profile_rows()
+        ctx.profile_enable(False)
+        for R in rots:
+            maps.append(ctx.evaluate_map(pair.B, R)[0])
+    assert nrot == len(rots)
+    count_a = (nxa - 2) * (nya - 2) * (nza - 2)
+    for R, Cg in zip(rots, maps):
+        mb = O.moving_fields(pair.B, O.quantize_rotation(R)).mask
+        thr = max(1, _m.ceil(0.5 * min(count_a, int(mb.sum()))))
+        plane = mb.sum(axis=2)                       # [z][y] counts over x
+        for zc in range(Wz):
+            cz = zc - (nza - 1)
+            lz, hz = max(1 + cz, 0), min(nza - 2 + cz, nzb - 1)
+            zsum = int(plane[lz:hz + 1].sum()) if lz <= hz else 0
+            want_z += zsum >= thr
+            for yc in range(Wy):
+                cy = yc - (nya - 1)
+                ly, hy = max(1 + cy, 0), min(nya - 2 + cy, nyb - 1)
+                rsum = int(plane[lz:hz + 1, ly:hy + 1].sum()) if (lz <= hz and ly <= hy) else 0
+                kept = rsum >= thr
+                want_r += kept
+                if not kept:
+                    assert not np.isfinite(Cg[zc, yc]).any(), (zc, yc)
+    _say("kept rows", kz, kr, "expected", want_z, want_r)
+    assert (kz, kr) == (want_z, want_r)
+
+
 def test_padding_invariance_and_minimum_extent():
     rng = np.random.default_rng(9)
     A = rng.random((3, 4, 5)).astype(np.float32)

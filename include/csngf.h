@@ -45,7 +45,7 @@ extern "C" {
 
 #define CSNGF_OK 0
 #define CSNGF_E_INVALID_ARG (-1)    /* NULL pointer, extent < 3, non-finite input, bad gamma/eps/R */
-#define CSNGF_E_UNSUPPORTED (-2)    /* FFT size not built (see csngf_supported_length), user mask on A */
+#define CSNGF_E_UNSUPPORTED (-2)    /* FFT size not built (see csngf_supported_length), volume too large */
 #define CSNGF_E_NO_DEVICE (-3)      /* no HIP device visible */
 #define CSNGF_E_OUT_OF_MEMORY (-4)  /* device allocation failed */
 #define CSNGF_E_DEVICE (-5)         /* HIP runtime error; message holds the HIP error text */
@@ -123,9 +123,16 @@ int csngf_supported_length(int32_t L);
 /* Precompute the fixed side for volume A (dims dA) against moving volumes of dims dB:
  * NGF of A, its six weighted product fields (cross terms x2, Eq. (6)), their zero-padded
  * 3-D FFTs, conjugated and kept resident on the device (Sec. 3.1, Eq. (7)-(8)).
- * maskA must be NULL (full domain; eroded to the box [1, n_A - 2]) - a user mask on A
- * returns CSNGF_E_UNSUPPORTED.  A is copied; the caller may free it on return.
- * p may be NULL for the defaults.  On success *out owns all device memory. */
+ * maskA: NULL = full domain (eroded to the box [1, n_A - 2]), or a uint8 mask M_A in A's
+ * layout (nonzero = inside; Sec. 3.1, Eq. (4)-(5)), eroded like B's so every counted voxel
+ * has its six neighbours.  With NULL, N(chi) is an integer box sum over B^'s mask.  With a
+ * mask, N(chi) is the mask cross-correlation of Sec. 3.1 (after Eq. (5)), computed by FP64
+ * zero-padded FFTs against A's resident FP64 mask spectrum and rounded to the exact integer
+ * (the FP64 error is far below 1/2); this adds one FP64 pencil chain per rotation and about
+ * 16 B x (2 W_z P_y + W_z W_y) x Px/2 + 4 B x W_x W_y W_z of workspace per rotation slot (the
+ * figure csngf_footprint reports is for NULL; csngf_get_info gives the context's own).
+ * A and maskA are copied; the caller may free them on return.  p may be NULL for the
+ * defaults.  On success *out owns all device memory. */
 int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims dB,
                  const csngf_params* p, csngf_ctx** out);
 

@@ -161,6 +161,8 @@ class Context:
         self.device = _is_device(A)
         if not self.device:
             A = np.ascontiguousarray(A, dtype=np.float32)
+            if mask_a is not None:
+                mask_a = np.ascontiguousarray(mask_a, dtype=np.uint8)
         p = default_params()
         p.eps = eps
         p.gamma = gamma

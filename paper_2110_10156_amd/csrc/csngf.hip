@@ -107,6 +107,13 @@ void twiddles(int L, std::vector<float2>& out) {
   }
 }
 
+void twiddles(int L, std::vector<double2>& out) {
+  for (int j = 0; j < L; ++j) {
+    const double a = -2.0 * M_PI * (double)j / (double)L;
+    out.push_back(make_double2(std::cos(a), std::sin(a)));
+  }
+}
+
 size_t a16(size_t b) { return (b + 15) & ~size_t(15); }
 
 // twiddles, transform rows, ring of 3 halo planes, NGF of one slice (+ Px floats of padding
@@ -121,7 +128,7 @@ size_t lds_fields(int Px, int nx) {
 #define CSNGF_SLICES 8
 #endif
 constexpr int kSlicesX = CSNGF_SLICES;
-size_t lds_pencil(int L, int W = kTileW) { return a16(sizeof(float2) * L) + a16(sizeof(float2) * L * W); }
+size_t lds_pencil(int L, int W = kTileW, size_t el = sizeof(float2)) { return a16(el * L) + a16(el * L * W); }
 size_t lds_final(int Px, int nxB) {
   return a16(sizeof(float2) * Px) + a16(sizeof(float2) * Px * (kRowsC + 1)) + a16(sizeof(int) * 2 * kRowsC * (nxB + 1));
 }
@@ -172,9 +179,9 @@ bool all_finite(const float* v, size_t n) {
   return true;
 }
 
-enum KType { KT_FIELDS, KT_SAT, KT_YFWD, KT_ZPASS, KT_YINV, KT_FINAL, KT_MISC, KT_COUNT };
+enum KType { KT_FIELDS, KT_SAT, KT_YFWD, KT_ZPASS, KT_YINV, KT_FINAL, KT_MISC, KT_MASK, KT_COUNT };
 const char* kTypeName[KT_COUNT] = {"fields_x", "overlap_sat", "y_forward", "z_mac_inverse",
-                                   "y_inverse", "x_c2r_argmax", "misc"};
+                                   "y_inverse", "x_c2r_argmax", "misc", "overlap_fp64"};
 
 struct PendingEv {
   int type;
@@ -253,6 +260,18 @@ struct csngf_ctx {
   // kept displacement rows while profiling: [0] z-rows, [1] (z, y) rows; rotations counted
   unsigned long long* d_rowstat = nullptr;
   long long stat_rotations = 0;
+  // a user mask on A: its eroded mask's bounding box (without one: [1, n_A - 2]), and the
+  // FP64 chain that counts overlaps exactly
+  bool masked = false;
+  int lo[3] = {1, 1, 1}, hi[3] = {0, 0, 0};
+  double2* d_twd = nullptr;     // FP64 twiddles, same offsets as d_tw
+  double2* d_mspec = nullptr;   // conj of A's mask spectrum / (Px Py Pz), [Pz][Py][Hp]
+  double2* d_mbuf1 = nullptr;   // per slot: X1m, then Y3m
+  double2* d_mbuf2 = nullptr;   // per slot: X2m, then Y4m
+  long long mbuf1_slot = 0, mbuf2_slot = 0;
+  int* d_ncount = nullptr;      // per slot: exact N(chi), [Wz][Wy][Wx]
+  long long ncount_slot = 0;
+  uint8_t* d_ones = nullptr;    // every row flag set (full maps)
 };
 
 namespace {
@@ -302,6 +321,20 @@ void dfree(T*& p) {
   p = nullptr;
 }
 
+template <typename T>
+int dalloc(T** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(p), bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return fail(CSNGF_E_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " +
+                                           hipGetErrorString(e));
+  }
+  return CSNGF_OK;
+}
+
 void release(csngf_ctx* c) {
   if (!c) return;
   hipSetDevice(c->dev);
@@ -325,6 +358,12 @@ void release(csngf_ctx* c) {
   dfree(c->d_rot_stage);
   dfree(c->d_res_stage);
   dfree(c->d_rowstat);
+  dfree(c->d_twd);
+  dfree(c->d_mspec);
+  dfree(c->d_mbuf1);
+  dfree(c->d_mbuf2);
+  dfree(c->d_ncount);
+  dfree(c->d_ones);
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->done_ev) (void)hipEventDestroy(c->done_ev);
   if (c->h_res) hipHostFree(c->h_res);
@@ -363,28 +402,81 @@ int check_dims(const csngf_dims& d, const char* what) {
 
 // Launch helpers -------------------------------------------------------------------------
 
-int launch_pencil(csngf_ctx* c, bool inv, const float2* in, float2* out, int n_in, int n_out, int out_off,
+template <typename V>
+const V* twiddle_table(const csngf_ctx* c);
+template <>
+const float2* twiddle_table<float2>(const csngf_ctx* c) { return c->d_tw; }
+template <>
+const double2* twiddle_table<double2>(const csngf_ctx* c) { return c->d_twd; }
+
+// The FP32 pencil passes of the product fields, or (double2) those of the exact overlap chain.
+template <typename V>
+int launch_pencil(csngf_ctx* c, bool inv, const V* in, V* out, int n_in, int n_out, int out_off,
                   const FftPlan& pl, long long in_g, long long out_g, int groups, long long in_s,
                   long long out_s, int slots, const uint8_t* flags = nullptr, long long flag_s = 0) {
   // tiles cover the H = Px/2 stored bins (bin 0 = DC + i Nyquist); the padding columns up to
   // Hp are never touched
   const int W = inv ? kTileP<true> : kTileP<false>;
   const dim3 grid((c->H + W - 1) / W, groups, slots);
-  const size_t lds = lds_pencil(pl.L, W) + (inv ? a16(pl.L) : 0);   // + the inverse's row flags
+  const size_t lds = lds_pencil(pl.L, W, sizeof(V)) + (inv ? a16(pl.L) : 0);   // + the inverse's row flags
+  if (lds > kLdsMax) return fail(CSNGF_E_UNSUPPORTED, "FFT length too large for the pencil pass");
+  hipError_t ae = hipSuccess;
   hipEvent_t ev = prof_begin(c);
   const bool half = 2 * n_in <= pl.L;  // inputs i >= L/2 are zero: first stage pruned
   with_len(pl.L, [&](auto lc) {
     constexpr int LC = decltype(lc)::value;
     auto go = [&](auto kern, int threads) {
-      hipLaunchKernelGGL(kern, grid, dim3(threads), lds, c->stream, in, out, n_in, n_out, out_off, pl, c->d_tw, c->H,
-                         c->Hp, in_g, out_g, in_s, out_s, flags, flag_s, groups);
+      ae = allow_lds(kern, lds);
+      if (ae == hipSuccess)
+        hipLaunchKernelGGL(kern, grid, dim3(threads), lds, c->stream, in, out, n_in, n_out, out_off, pl,
+                           twiddle_table<V>(c), c->H, c->Hp, in_g, out_g, in_s, out_s, flags, flag_s, groups);
     };
-    if (inv) go(k_pencil<true, LC, false>, kThreadsP<true>);
-    else if (half) go(k_pencil<false, LC, true>, kThreadsP<false>);
-    else go(k_pencil<false, LC, false>, kThreadsP<false>);
+    if (inv) go(k_pencil<true, LC, false, V>, kThreadsP<true>);
+    else if (half) go(k_pencil<false, LC, true, V>, kThreadsP<false>);
+    else go(k_pencil<false, LC, false, V>, kThreadsP<false>);
   });
-  prof_end(c, inv ? KT_YINV : KT_YFWD, ev);
+  prof_end(c, std::is_same<V, double2>::value ? KT_MASK : inv ? KT_YINV : KT_YFWD, ev);
+  if (ae != hipSuccess) return hip_fail(ae, "hipFuncSetAttribute(k_pencil)");
   LAUNCHCHK(inv ? "k_pencil<inverse>" : "k_pencil<forward>");
+  return CSNGF_OK;
+}
+
+// z pass over the slots' X2 tiles: per field the z forward, the MAC against A's conjugate
+// spectra, then the z inverse of the sum, storing the kept z-rows.  The two tiles that hold the
+// packed DC/Nyquist column go to pack_stream (the side stream for the product fields), the
+// rest to the context's stream.
+template <typename V>
+int launch_zpass(csngf_ctx* c, const V* X2, const V* spec, V* Y3, int nf, long long x2_slot, long long y3_slot,
+                 const uint8_t* flags, long long flag_slot, int slots, hipStream_t pack_stream) {
+  const int nreal = c->P[1] * c->tiles * slots;
+  const int nb8 = (nreal + 7) / 8 * 8;
+  const size_t lds = lds_pencil(c->plz.L, kTileW, sizeof(V)) + a16(c->plz.L);   // + the kept-row flags
+  if (lds > kLdsMax) return fail(CSNGF_E_UNSUPPORTED, "FFT length too large for the z pass");
+  const int out_off = c->P[2] - (c->nA[2] - 1);
+  hipError_t ae = hipSuccess;
+  hipEvent_t ev = prof_begin(c);
+  // inputs z >= Pz/2 are zero when nz - 2 <= Pz/2: the forward transforms' first stage is pruned
+  const bool half = 2 * (c->nB[2] - 2) <= c->plz.L;
+  with_len(c->plz.L, [&](auto lc) {
+    constexpr int LC = decltype(lc)::value;
+    auto go = [&](auto kern, int nblocks, hipStream_t st) {
+      if (ae == hipSuccess) ae = allow_lds(kern, lds);
+      if (ae == hipSuccess)
+        hipLaunchKernelGGL(kern, dim3(nblocks), dim3(kThreadsZ), lds, st, X2, spec, Y3, c->nB[2] - 2, c->P[1], c->H,
+                           c->Hp, c->Wd[2], out_off, c->plz, twiddle_table<V>(c), x2_slot, y3_slot, c->tiles, slots,
+                           nreal, flags, flag_slot, nf);
+    };
+    if (half) {
+      go(k_zpass<LC, true, true, V>, 2 * slots, pack_stream);
+      go(k_zpass<LC, true, false, V>, nb8, c->stream);
+    } else {
+      go(k_zpass<LC, false, true, V>, 2 * slots, pack_stream);
+      go(k_zpass<LC, false, false, V>, nb8, c->stream);
+    }
+  });
+  prof_end(c, std::is_same<V, double2>::value ? KT_MASK : KT_ZPASS, ev);
+  if (ae != hipSuccess) return hip_fail(ae, "hipFuncSetAttribute(k_zpass)");
+  LAUNCHCHK("k_zpass");
   return CSNGF_OK;
 }
 
@@ -421,6 +513,155 @@ int launch_fields(csngf_ctx* c, bool moving, const float* vol, const uint8_t* um
   return CSNGF_OK;
 }
 
+OverlapGeom geometry(const csngf_ctx* c) {
+  OverlapGeom g;
+  for (int i = 0; i < 3; ++i) {
+    g.nA[i] = c->nA[i];
+    g.nB[i] = c->nB[i];
+    g.lo[i] = c->lo[i];
+    g.hi[i] = c->hi[i];
+  }
+  return g;
+}
+
+// The exact overlap chain of a fixed side with a general mask (FP64): the eroded moving masks
+// of the slots -> x R2C -> y forward -> z forward x conj(A's mask spectrum) -> z inverse ->
+// y inverse -> x C2R, rounded into d_ncount.  flags: the kept rows (all ones for a full map).
+int run_overlap_chain(csngf_ctx* c, int slots, const uint8_t* flags, long long flag_slot) {
+  const int nx = c->nB[0], ny = c->nB[1], nz = c->nB[2];
+  {
+    const size_t lds = a16(sizeof(double2) * c->plx.L) + a16(sizeof(double2) * c->plx.L * kMaskPairs);
+    if (lds > kLdsMax) return fail(CSNGF_E_UNSUPPORTED, "x extent too large for the overlap chain");
+    const dim3 grid(((ny - 2 + 1) / 2 + kMaskPairs - 1) / kMaskPairs, nz - 2, slots);
+    const bool half = 2 * nx <= c->plx.L;
+    hipError_t ae = hipSuccess;
+    hipEvent_t ev = prof_begin(c);
+    with_len(c->plx.L, [&](auto lc) {
+      constexpr int LC = decltype(lc)::value;
+      auto go = [&](auto kern) {
+        ae = allow_lds(kern, lds);
+        if (ae == hipSuccess)
+          hipLaunchKernelGGL(kern, grid, dim3(kThreadsM), lds, c->stream, c->d_mask, nx, ny, nz, c->mask_slot, c->plx,
+                             c->d_twd, c->d_mbuf1, c->H, c->Hp, c->mbuf1_slot);
+      };
+      if (half) go(k_mask_x<LC, true>);
+      else go(k_mask_x<LC, false>);
+    });
+    prof_end(c, KT_MASK, ev);
+    if (ae != hipSuccess) return hip_fail(ae, "hipFuncSetAttribute(k_mask_x)");
+    LAUNCHCHK("k_mask_x");
+  }
+  int rc = launch_pencil(c, false, c->d_mbuf1, c->d_mbuf2, ny - 2, c->P[1], 0, c->ply, (long long)(ny - 2) * c->Hp,
+                         (long long)c->P[1] * c->Hp, nz - 2, c->mbuf1_slot, c->mbuf2_slot, slots);
+  if (rc) return rc;
+  rc = launch_zpass(c, c->d_mbuf2, c->d_mspec, c->d_mbuf1, 1, c->mbuf2_slot, c->mbuf1_slot, flags, flag_slot, slots,
+                    c->stream);
+  if (rc) return rc;
+  rc = launch_pencil(c, true, c->d_mbuf1, c->d_mbuf2, c->P[1], c->Wd[1], c->P[1] - (c->nA[1] - 1), c->ply,
+                     (long long)c->P[1] * c->Hp, (long long)c->Wd[1] * c->Hp, c->Wd[2], c->mbuf1_slot, c->mbuf2_slot,
+                     slots, flags, flag_slot);
+  if (rc) return rc;
+  {
+    const size_t lds = a16(sizeof(double2) * c->plx.L) + a16(sizeof(double2) * c->plx.L * (kRowsC + 1));
+    if (lds > kLdsMax) return fail(CSNGF_E_UNSUPPORTED, "x extent too large for the overlap chain");
+    const dim3 grid((c->Wd[1] + 2 * kRowsC - 1) / (2 * kRowsC), c->Wd[2], slots);
+    hipError_t ae = hipSuccess;
+    hipEvent_t ev = prof_begin(c);
+    with_len(c->plx.L, [&](auto lc) {
+      constexpr int LC = decltype(lc)::value;
+      ae = allow_lds(k_overlap_x<LC>, lds);
+      if (ae == hipSuccess)
+        hipLaunchKernelGGL((k_overlap_x<LC>), grid, dim3(kThreadsC), lds, c->stream, c->d_mbuf2, c->d_ncount, c->Wd[0],
+                           c->Wd[1], c->Wd[2], c->H, c->Hp, c->nA[0] - 1, c->plx, c->d_twd, c->mbuf2_slot,
+                           c->ncount_slot, flags, flag_slot);
+    });
+    prof_end(c, KT_MASK, ev);
+    if (ae != hipSuccess) return hip_fail(ae, "hipFuncSetAttribute(k_overlap_x)");
+    LAUNCHCHK("k_overlap_x");
+  }
+  return CSNGF_OK;
+}
+
+// A's side of the overlap chain: its eroded mask meff (device, dims nA) -> count and bounding
+// box (host) -> FP64 x R2C, y forward, z forward -> d_mspec = conj(.) / (Px Py Pz).
+int fixed_mask_spectrum(csngf_ctx* c, const uint8_t* meff, const int* nA) {
+  const size_t nvA = (size_t)nA[0] * nA[1] * nA[2];
+  {
+    // the field stage wrote meff on the context's stream, which is non-blocking: a plain
+    // hipMemcpy would not wait for it
+    std::vector<uint8_t> h(nvA);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipMemcpy(h.data(), meff, nvA, hipMemcpyDeviceToHost));
+    long long cnt = 0;
+    int lo[3] = {nA[0], nA[1], nA[2]}, hi[3] = {-1, -1, -1};
+    for (int z = 0; z < nA[2]; ++z)
+      for (int y = 0; y < nA[1]; ++y)
+        for (int x = 0; x < nA[0]; ++x)
+          if (h[((size_t)z * nA[1] + y) * nA[0] + x]) {
+            ++cnt;
+            const int v[3] = {x, y, z};
+            for (int i = 0; i < 3; ++i) {
+              lo[i] = std::min(lo[i], v[i]);
+              hi[i] = std::max(hi[i], v[i]);
+            }
+          }
+    c->count_a = cnt;
+    for (int i = 0; i < 3; ++i) {
+      c->lo[i] = cnt ? lo[i] : 1;   // an empty mask: lo > hi, every bound is 0
+      c->hi[i] = cnt ? hi[i] : 0;
+    }
+  }
+  const int* P = c->P;
+  const long long Hp = c->Hp;
+  double2 *x1m = nullptr, *x2m = nullptr;
+  int rc = dalloc(&x1m, sizeof(double2) * (size_t)(nA[2] - 2) * (nA[1] - 2) * Hp);
+  if (!rc) rc = dalloc(&x2m, sizeof(double2) * (size_t)(nA[2] - 2) * P[1] * Hp);
+  if (!rc) {
+    const size_t lds = a16(sizeof(double2) * c->plx.L) + a16(sizeof(double2) * c->plx.L * kMaskPairs);
+    const dim3 grid(((nA[1] - 2 + 1) / 2 + kMaskPairs - 1) / kMaskPairs, nA[2] - 2, 1);
+    const bool half = 2 * nA[0] <= c->plx.L;
+    hipError_t ae = hipSuccess;
+    with_len(c->plx.L, [&](auto lc) {
+      constexpr int LC = decltype(lc)::value;
+      auto go = [&](auto kern) {
+        ae = allow_lds(kern, lds);
+        if (ae == hipSuccess)
+          hipLaunchKernelGGL(kern, grid, dim3(kThreadsM), lds, c->stream, meff, nA[0], nA[1], nA[2], 0LL, c->plx,
+                             c->d_twd, x1m, c->H, c->Hp, 0LL);
+      };
+      if (lds > kLdsMax) ae = hipErrorInvalidValue;
+      else if (half) go(k_mask_x<LC, true>);
+      else go(k_mask_x<LC, false>);
+    });
+    if (ae != hipSuccess) rc = hip_fail(ae, "k_mask_x (fixed side)");
+    else if (hipGetLastError() != hipSuccess) rc = fail(CSNGF_E_DEVICE, "k_mask_x (fixed side) launch");
+  }
+  if (!rc)
+    rc = launch_pencil(c, false, x1m, x2m, nA[1] - 2, P[1], 0, c->ply, (long long)(nA[1] - 2) * Hp,
+                       (long long)P[1] * Hp, nA[2] - 2, 0, 0, 1);
+  if (!rc) rc = dalloc(&c->d_mspec, sizeof(double2) * (size_t)P[2] * P[1] * Hp);
+  if (!rc) {
+    const double scale = 1.0 / ((double)P[0] * (double)P[1] * (double)P[2]);
+    const dim3 grid(c->tiles, P[1], 1);
+    const size_t lds = lds_pencil(P[2], kTileW, sizeof(double2));
+    hipError_t ae = hipSuccess;
+    with_len(P[2], [&](auto lc) {
+      constexpr int LC = decltype(lc)::value;
+      ae = allow_lds(k_zstore<LC, double2>, lds);
+      if (ae == hipSuccess)
+        hipLaunchKernelGGL((k_zstore<LC, double2>), grid, dim3(kThreads), lds, c->stream, x2m, c->d_mspec, nA[2] - 2,
+                           P[1], c->H, c->Hp, c->plz, c->d_twd, scale, 1);
+    });
+    if (ae != hipSuccess) rc = hip_fail(ae, "k_zstore (mask)");
+    else if (hipGetLastError() != hipSuccess) rc = fail(CSNGF_E_DEVICE, "k_zstore (mask) launch");
+  }
+  const hipError_t se = hipStreamSynchronize(c->stream);
+  if (!rc && se != hipSuccess) rc = hip_fail(se, "fixed-side mask spectrum");
+  if (x1m) hipFree(x1m);
+  if (x2m) hipFree(x2m);
+  return rc;
+}
+
 // One launch sequence over `slots` rotations whose Q16 tables start at rotq (device).
 int run_batch(csngf_ctx* c, const float* dB, const uint8_t* dmB, const int* rotq, int slots, RotResultDev* res,
               float* cmap, long long* nmap) {
@@ -449,11 +690,7 @@ int run_batch(csngf_ctx* c, const float* dB, const uint8_t* dmB, const int* rotq
       hipLaunchKernelGGL(k_sat_z<uint32_t>, gz, dim3(kThreads), 0, st, c->d_plane, c->d_sat, nx, ny, nz,
                          c->plane_slot, c->sat_slot);
     }
-    OverlapGeom g;
-    for (int i = 0; i < 3; ++i) {
-      g.nA[i] = c->nA[i];
-      g.nB[i] = c->nB[i];
-    }
+    const OverlapGeom g = geometry(c);
     hipLaunchKernelGGL(k_bounds, dim3((c->Wd[2] * c->Wd[1] + kThreads - 1) / kThreads, slots), dim3(kThreads), 0,
                        st, c->d_sat, g, c->Wd[1], c->Wd[2], c->sat_slot, c->count_a, c->gamma, c->d_flags,
                        c->flag_slot, c->d_keys, c->d_work, c->prof ? c->d_rowstat : nullptr);
@@ -479,47 +716,25 @@ int run_batch(csngf_ctx* c, const float* dB, const uint8_t* dmB, const int* rotq
   HIPCHK(hipEventRecord(c->ev_yfwd, c->stream));
   HIPCHK(hipStreamWaitEvent(c->side, c->ev_yfwd, 0));
   HIPCHK(hipStreamWaitEvent(c->stream, c->ev_join, 0));
-  {
-    const int nreal = c->P[1] * c->tiles * slots;
-    const int nb8 = (nreal + 7) / 8 * 8;
-    const size_t lds = lds_pencil(c->plz.L) + a16(c->plz.L);   // + the kept-row flags
-    const int out_off = c->P[2] - (c->nA[2] - 1);
-    ev = prof_begin(c);
-    // inputs z >= Pz/2 are zero when nz - 2 <= Pz/2: the forward transforms' first stage is pruned
-    const bool half = 2 * (c->nB[2] - 2) <= c->plz.L;
-    with_len(c->plz.L, [&](auto lc) {
-      constexpr int LC = decltype(lc)::value;
-      auto go = [&](auto kern, int nblocks, hipStream_t st) {
-        hipLaunchKernelGGL(kern, dim3(nblocks), dim3(kThreadsZ), lds, st, c->d_buf2, c->d_spec, c->d_buf1,
-                           c->nB[2] - 2, c->P[1], c->H, c->Hp, c->Wd[2], out_off, c->plz, c->d_tw, c->buf2_slot,
-                           c->buf1_slot, c->tiles, slots, nreal, c->d_flags, c->flag_slot, c->nf);
-      };
-      // the packed DC/Nyquist tiles (tile 0 at ky = 0 and Py/2) on the side stream, all other
-      // tiles here
-      if (half) {
-        go(k_zpass<LC, true, true>, 2 * slots, c->side);
-        go(k_zpass<LC, true, false>, nb8, c->stream);
-      } else {
-        go(k_zpass<LC, false, true>, 2 * slots, c->side);
-        go(k_zpass<LC, false, false>, nb8, c->stream);
-      }
-    });
-    prof_end(c, KT_ZPASS, ev);
-    LAUNCHCHK("k_zpass");
-    HIPCHK(hipEventRecord(c->ev_zpack, c->side));
-    HIPCHK(hipStreamWaitEvent(c->stream, c->ev_zpack, 0));
-  }
+  // the packed DC/Nyquist tiles (tile 0 at ky = 0 and Py/2) on the side stream, all other
+  // tiles here
+  rc = launch_zpass(c, c->d_buf2, c->d_spec, c->d_buf1, c->nf, c->buf2_slot, c->buf1_slot, c->d_flags, c->flag_slot,
+                    slots, c->side);
+  if (rc) return rc;
+  HIPCHK(hipEventRecord(c->ev_zpack, c->side));
+  HIPCHK(hipStreamWaitEvent(c->stream, c->ev_zpack, 0));
   // y inverse: Y3 [slot][zc][ky] -> Y4 [slot][zc][yc]
   rc = launch_pencil(c, true, c->d_buf1, c->d_buf2, c->P[1], c->Wd[1], c->P[1] - (c->nA[1] - 1), c->ply,
                      (long long)c->P[1] * c->Hp, (long long)c->Wd[1] * c->Hp, c->Wd[2], c->buf1_slot, c->buf2_slot,
                      slots, c->d_flags, c->flag_slot);
   if (rc) return rc;
+  // a fixed side with a general mask: exact counts from the FP64 overlap chain (every row for
+  // a full map, the kept rows otherwise)
+  if (c->masked && (rc = run_overlap_chain(c, slots, cmap ? c->d_ones : c->d_flags, cmap ? 0 : c->flag_slot)))
+    return rc;
   {
-    OverlapGeom g;
-    for (int i = 0; i < 3; ++i) {
-      g.nA[i] = c->nA[i];
-      g.nB[i] = c->nB[i];
-    }
+    const OverlapGeom g = geometry(c);
+    const int* ncount = c->masked ? c->d_ncount : nullptr;
     const dim3 grid((c->Wd[1] + 2 * kRowsC - 1) / (2 * kRowsC), c->Wd[2], slots);
     // without a map: a fixed grid over the work list of row groups that hold a valid
     // displacement (most do not at gamma = 0.5)
@@ -530,28 +745,25 @@ int run_batch(csngf_ctx* c, const float* dB, const uint8_t* dmB, const int* rotq
     ev = prof_begin(c);
     with_len(c->plx.L, [&](auto lc) {
       constexpr int LC = decltype(lc)::value;
-      if (cmap) {
-        ae = allow_lds(k_final_x<true, LC>, lds);
+      auto go = [&](auto kern, dim3 gr, const unsigned* work, const unsigned* nwork) {
+        ae = allow_lds(kern, lds);
         if (ae == hipSuccess)
-          hipLaunchKernelGGL((k_final_x<true, LC>), grid, dim3(kThreadsC), lds, c->stream, c->d_buf2, c->d_sat,
-                             c->d_keys, g, c->Wd[0], c->Wd[1], c->Wd[2], c->H, c->Hp, c->plx, c->d_tw, c->buf2_slot,
-                             c->sat_slot, c->count_a, c->gamma, cmap, nmap, c->d_flags, c->flag_slot, nullptr,
-                             nullptr);
-      } else {
-        ae = allow_lds(k_final_x<false, LC>, lds);
-        if (ae == hipSuccess)
-          hipLaunchKernelGGL((k_final_x<false, LC>), lgrid, dim3(kThreadsC), lds, c->stream, c->d_buf2, c->d_sat,
-                             c->d_keys, g, c->Wd[0], c->Wd[1], c->Wd[2], c->H, c->Hp, c->plx, c->d_tw, c->buf2_slot,
-                             c->sat_slot, c->count_a, c->gamma, cmap, nmap, c->d_flags, c->flag_slot,
-                             c->d_work + 64, c->d_work);
-      }
+          hipLaunchKernelGGL(kern, gr, dim3(kThreadsC), lds, c->stream, c->d_buf2, c->d_sat, c->d_keys, g, c->Wd[0],
+                             c->Wd[1], c->Wd[2], c->H, c->Hp, c->plx, c->d_tw, c->buf2_slot, c->sat_slot, c->count_a,
+                             c->gamma, cmap, nmap, c->d_flags, c->flag_slot, work, nwork, ncount, c->ncount_slot);
+      };
+      // with a map every row group gets a workgroup; without, a fixed grid walks the work list
+      if (cmap && ncount) go(k_final_x<true, LC, true>, grid, nullptr, nullptr);
+      else if (cmap) go(k_final_x<true, LC, false>, grid, nullptr, nullptr);
+      else if (ncount) go(k_final_x<false, LC, true>, lgrid, c->d_work + 64, c->d_work);
+      else go(k_final_x<false, LC, false>, lgrid, c->d_work + 64, c->d_work);
     });
     if (ae != hipSuccess) return hip_fail(ae, "hipFuncSetAttribute(k_final_x)");
     prof_end(c, KT_FINAL, ev);
     LAUNCHCHK("k_final_x");
     ev = prof_begin(c);
     hipLaunchKernelGGL(k_finalize, dim3((slots + 63) / 64), dim3(64), 0, c->stream, c->d_keys, c->d_sat, g, c->Wd[0],
-                       c->Wd[1], c->sat_slot, slots, res);
+                       c->Wd[1], c->sat_slot, slots, res, ncount, c->ncount_slot);
     prof_end(c, KT_MISC, ev);
     LAUNCHCHK("k_finalize");
   }
@@ -593,19 +805,6 @@ int run_graph_batch(csngf_ctx* c, const float* dB, const uint8_t* dmB, int base)
   return CSNGF_OK;
 }
 
-template <typename T>
-int dalloc(T** p, size_t bytes) {
-  *p = nullptr;
-  if (bytes == 0) bytes = 16;
-  hipError_t e = hipMalloc(reinterpret_cast<void**>(p), bytes);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    *p = nullptr;
-    return fail(CSNGF_E_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " +
-                                           hipGetErrorString(e));
-  }
-  return CSNGF_OK;
-}
 
 int ensure_rot_capacity(csngf_ctx* c, int n) {
   if (n <= c->rot_cap && n <= c->h_rot_cap && n <= c->res_cap && n <= c->h_res_cap) return CSNGF_OK;
@@ -703,7 +902,6 @@ int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims
     return fail(CSNGF_E_INVALID_ARG, "batch must lie in [0, 255]");
   if (prm.flags & ~(CSNGF_DEVICE_PTRS | CSNGF_UNSQUARED | CSNGF_GRAPHS))
     return fail(CSNGF_E_INVALID_ARG, "unknown flag bits");
-  if (maskA) return fail(CSNGF_E_UNSUPPORTED, "a user mask on the fixed volume is not supported (pass NULL)");
   const int nA[3] = {dA.nx, dA.ny, dA.nz}, nB[3] = {dB.nx, dB.ny, dB.nz};
   int P[3];
   for (int i = 0; i < 3; ++i) {
@@ -750,20 +948,36 @@ int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims
   factor_plan(P[0], c->plx);
   factor_plan(P[1], c->ply);
   factor_plan(P[2], c->plz);
+  c->masked = maskA != nullptr;
   {
     std::vector<float2> tw;
+    std::vector<double2> twd;
     c->plx.tw_off = (int)tw.size();
     twiddles(P[0], tw);
+    twiddles(P[0], twd);
     c->ply.tw_off = (int)tw.size();
     twiddles(P[1], tw);
+    twiddles(P[1], twd);
     c->plz.tw_off = (int)tw.size();
     twiddles(P[2], tw);
+    twiddles(P[2], twd);
     if ((rc = dalloc(&c->d_tw, sizeof(float2) * tw.size()))) return bail(rc);
     if (hipMemcpy(c->d_tw, tw.data(), sizeof(float2) * tw.size(), hipMemcpyHostToDevice) != hipSuccess)
       return bail(hip_fail(hipGetLastError(), "twiddle upload"));
+    if (c->masked) {   // same offsets as the FP32 table
+      if ((rc = dalloc(&c->d_twd, sizeof(double2) * twd.size()))) return bail(rc);
+      if (hipMemcpy(c->d_twd, twd.data(), sizeof(double2) * twd.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return bail(hip_fail(hipGetLastError(), "twiddle upload"));
+    }
   }
   const long long Hp = c->Hp;
+  // A's eroded mask without a user mask is the box [1, n_A - 2]; with one, its count and
+  // bounding box come from the eroded mask below
   c->count_a = (long long)(nA[0] - 2) * (nA[1] - 2) * (nA[2] - 2);
+  for (int i = 0; i < 3; ++i) {
+    c->lo[i] = 1;
+    c->hi[i] = nA[i] - 2;
+  }
   c->spec_bytes = (long long)sizeof(float2) * c->nf * P[2] * P[1] * Hp;
   if ((rc = dalloc(&c->d_spec, (size_t)c->spec_bytes))) return bail(rc);
   if ((rc = dalloc(&c->d_flag, sizeof(int)))) return bail(rc);
@@ -781,14 +995,25 @@ int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims
       dA_ptr = tmpA;
     }
     float2 *x1 = nullptr, *x2 = nullptr;
+    uint8_t *um = nullptr, *meff = nullptr;   // user mask on the device, A's eroded mask
+    const uint8_t* dmA = maskA;
     const long long x1e = (long long)c->nf * nA[2] * nA[1] * Hp, x2e = (long long)c->nf * nA[2] * P[1] * Hp;
     rc = dalloc(&x1, sizeof(float2) * x1e);
     if (!rc) rc = dalloc(&x2, sizeof(float2) * x2e);
+    if (!rc && c->masked) {
+      rc = dalloc(&meff, nvA);
+      if (!rc && !(prm.flags & CSNGF_DEVICE_PTRS)) {
+        rc = dalloc(&um, nvA);
+        if (!rc && hipMemcpy(um, maskA, nvA, hipMemcpyHostToDevice) != hipSuccess)
+          rc = hip_fail(hipGetLastError(), "upload of mask A");
+        dmA = um;
+      }
+    }
     if (!rc && (prm.flags & CSNGF_DEVICE_PTRS)) {
       HIPCHK(hipMemsetAsync(c->d_flag, 0, sizeof(int), c->stream));
       hipLaunchKernelGGL(k_check_finite, dim3(1024), dim3(256), 0, c->stream, A, (long long)nvA, c->d_flag);
     }
-    if (!rc) rc = launch_fields(c, false, dA_ptr, nullptr, nA, nullptr, x1, 0, nullptr, 0, nullptr, 1);
+    if (!rc) rc = launch_fields(c, false, dA_ptr, dmA, nA, nullptr, x1, 0, meff, 0, nullptr, 1);
     if (!rc)
       rc = launch_pencil(c, false, x1, x2, nA[1] - 2, P[1], 0, c->ply, (long long)(nA[1] - 2) * Hp,
                          (long long)P[1] * Hp, c->nf * (nA[2] - 2), 0, 0, 1);
@@ -796,19 +1021,25 @@ int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims
       const float scale = (float)(1.0 / ((double)P[0] * (double)P[1] * (double)P[2]));
       const dim3 grid(c->tiles, P[1], c->nf);
       const size_t lds = lds_pencil(P[2]);
+      hipError_t ae = hipSuccess;
       with_len(P[2], [&](auto lc) {
         constexpr int LC = decltype(lc)::value;
-        hipLaunchKernelGGL((k_zstore<LC>), grid, dim3(kThreads), lds, c->stream, x2, c->d_spec, nA[2] - 2, P[1], c->H,
-                           c->Hp, c->plz, c->d_tw, scale, c->nf);
+        ae = allow_lds(k_zstore<LC>, lds);
+        if (ae == hipSuccess)
+          hipLaunchKernelGGL((k_zstore<LC>), grid, dim3(kThreads), lds, c->stream, x2, c->d_spec, nA[2] - 2, P[1],
+                             c->H, c->Hp, c->plz, c->d_tw, scale, c->nf);
       });
-      hipError_t e = hipGetLastError();
+      hipError_t e = ae != hipSuccess ? ae : hipGetLastError();
       if (e != hipSuccess) rc = hip_fail(e, "k_zstore");
     }
+    if (!rc && c->masked) rc = fixed_mask_spectrum(c, meff, nA);
     hipError_t se = hipStreamSynchronize(c->stream);
     if (!rc && se != hipSuccess) rc = hip_fail(se, "fixed-side precompute");
     if (x1) hipFree(x1);
     if (x2) hipFree(x2);
     if (tmpA) hipFree(tmpA);
+    if (um) hipFree(um);
+    if (meff) hipFree(meff);
     if (rc) return bail(rc);
     int bad = 0;
     if ((rc = read_flag(c, &bad))) return bail(rc);
@@ -826,8 +1057,14 @@ int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims
     const int plane_bytes = (long long)nB[0] * nB[1] < 65536 ? 2 : 4;   // per voxel, as the SAT kernels use
     c->plane_slot = ((nvB * plane_bytes + 3) / 4 + 63) / 64 * 64;
     c->work_slot = (long long)c->Wd[2] * ((c->Wd[1] + 2 * kRowsC - 1) / (2 * kRowsC));
+    if (c->masked) {
+      c->mbuf1_slot = std::max((long long)(nB[2] - 2) * (nB[1] - 2), (long long)c->Wd[2] * P[1]) * Hp;
+      c->mbuf2_slot = std::max((long long)(nB[2] - 2) * P[1], (long long)c->Wd[2] * c->Wd[1]) * Hp;
+      c->ncount_slot = ((long long)c->Wd[0] * c->Wd[1] * c->Wd[2] + 63) / 64 * 64;
+    }
     const long long per = sizeof(float2) * (c->buf1_slot + c->buf2_slot) + c->mask_slot + 4 * c->sat_slot +
-                          4 * c->plane_slot + c->flag_slot + 4 * c->work_slot;
+                          4 * c->plane_slot + c->flag_slot + 4 * c->work_slot +
+                          (long long)sizeof(double2) * (c->mbuf1_slot + c->mbuf2_slot) + 4 * c->ncount_slot;
     int batch = prm.batch;
     if (batch == 0) {
       size_t fr = 0, tot = 0;
@@ -850,15 +1087,25 @@ int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims
     if ((rc = dalloc(&c->d_sat, 4 * (size_t)c->sat_slot * batch))) return bail(rc);
     if ((rc = dalloc(&c->d_flags, (size_t)c->flag_slot * batch))) return bail(rc);
     if ((rc = dalloc(&c->d_keys, sizeof(unsigned long long) * batch))) return bail(rc);
+    if (c->masked) {
+      if ((rc = dalloc(&c->d_mbuf1, sizeof(double2) * c->mbuf1_slot * batch))) return bail(rc);
+      if ((rc = dalloc(&c->d_mbuf2, sizeof(double2) * c->mbuf2_slot * batch))) return bail(rc);
+      if ((rc = dalloc(&c->d_ncount, 4 * (size_t)c->ncount_slot * batch))) return bail(rc);
+      if ((rc = dalloc(&c->d_ones, (size_t)c->flag_slot))) return bail(rc);
+      if (hipMemsetAsync(c->d_ones, 1, (size_t)c->flag_slot, c->stream) != hipSuccess)
+        return bail(hip_fail(hipGetLastError(), "hipMemsetAsync"));
+    }
     if ((rc = dalloc(&c->d_rowstat, 2 * sizeof(unsigned long long)))) return bail(rc);
-    if (hipMemset(c->d_rowstat, 0, 2 * sizeof(unsigned long long)) != hipSuccess)
-      return bail(hip_fail(hipGetLastError(), "hipMemset"));
+    // (on the context's non-blocking stream, which a null-stream memset would not order)
+    if (hipMemsetAsync(c->d_rowstat, 0, 2 * sizeof(unsigned long long), c->stream) != hipSuccess)
+      return bail(hip_fail(hipGetLastError(), "hipMemsetAsync"));
     if (prm.flags & CSNGF_GRAPHS) {
       if ((rc = dalloc(&c->d_rot_stage, sizeof(int) * 9 * (size_t)batch))) return bail(rc);
       if ((rc = dalloc(&c->d_res_stage, sizeof(RotResultDev) * (size_t)batch))) return bail(rc);
     }
     if (hipEventCreateWithFlags(&c->done_ev, hipEventDisableTiming) != hipSuccess)
       return bail(hip_fail(hipGetLastError(), "hipEventCreate"));
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return bail(hip_fail(hipGetLastError(), "hipStreamSynchronize"));
     c->workspace_bytes = per * batch;
   }
   *out = c;
@@ -1444,7 +1691,8 @@ int csngf_profile_reset(csngf_ctx* c) {
     c->stat_launches[i] = 0;
     c->stat_ms[i] = 0;
   }
-  HIPCHK(hipMemset(c->d_rowstat, 0, 2 * sizeof(unsigned long long)));
+  HIPCHK(hipMemsetAsync(c->d_rowstat, 0, 2 * sizeof(unsigned long long), c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
   c->stat_rotations = 0;
   return CSNGF_OK;
 }

@@ -9,9 +9,15 @@
 //
 // Forward transforms use exp(-2 pi i j k / L); inverse ones use the conjugate and are
 // unnormalised (the caller folds 1/L into its data).
+//
+// Every routine is generic in the complex type V: float2 (the correlation of the product
+// fields) or double2 (the exact overlap counts of a general fixed-side mask, whose FP64
+// transform error stays far below the 1/2 that rounding to an integer tolerates).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 namespace csngf {
 
@@ -26,46 +32,65 @@ struct FftPlan {
   int tw_off;               // offset of this length's table W_L^j, j < L, in the table buffer
 };
 
-__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+// scalar type of a complex vector type, and construction
+template <typename V>
+using scalar_t = std::remove_reference_t<decltype(V{}.x)>;
+template <typename V>
+__device__ __forceinline__ V cplx(scalar_t<V> x, scalar_t<V> y) {
+  V r;
+  r.x = x;
+  r.y = y;
+  return r;
 }
-__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+template <typename V>
+__device__ __forceinline__ V czero() {
+  return cplx<V>(scalar_t<V>(0), scalar_t<V>(0));
+}
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return fma(a, b, c); }
+
+template <typename V>
+__device__ __forceinline__ V cadd(V a, V b) { return cplx<V>(a.x + b.x, a.y + b.y); }
+template <typename V>
+__device__ __forceinline__ V csub(V a, V b) { return cplx<V>(a.x - b.x, a.y - b.y); }
+template <typename V>
+__device__ __forceinline__ V cmul(V a, V b) {
+  return cplx<V>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
 // multiply by -i (forward) or +i (inverse)
-template <bool INV>
-__device__ __forceinline__ float2 rot_i(float2 a) {
-  return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+template <bool INV, typename V>
+__device__ __forceinline__ V rot_i(V a) {
+  return INV ? cplx<V>(-a.y, a.x) : cplx<V>(a.y, -a.x);
 }
 
 // ---------------------------------------------------------------- small DFTs
 // NZ: inputs x[m] with m >= NZ are known to be zero (the first stage of a zero-padded
 // transform), so the sums and differences that involve them are skipped.
-template <int NZ, int M>
-__device__ __forceinline__ float2 add_nz(const float2* x, int a) {  // x[a] + x[M] with x[M] maybe zero
+template <int NZ, int M, typename V>
+__device__ __forceinline__ V add_nz(const V* x, int a) {  // x[a] + x[M] with x[M] maybe zero
   return M >= NZ ? x[a] : cadd(x[a], x[M]);
 }
-template <int NZ, int M>
-__device__ __forceinline__ float2 sub_nz(const float2* x, int a) {  // x[a] - x[M] with x[M] maybe zero
+template <int NZ, int M, typename V>
+__device__ __forceinline__ V sub_nz(const V* x, int a) {  // x[a] - x[M] with x[M] maybe zero
   return M >= NZ ? x[a] : csub(x[a], x[M]);
 }
 
-template <bool INV, int NZ = 2>
-__device__ __forceinline__ void dft2(float2* x) {
-  float2 a = x[0];
+template <bool INV, int NZ = 2, typename V>
+__device__ __forceinline__ void dft2(V* x) {
+  V a = x[0];
   x[0] = add_nz<NZ, 1>(x, 0);
   x[1] = NZ > 1 ? csub(a, x[1]) : a;
 }
 
-template <bool INV, int NZ = 4>
-__device__ __forceinline__ void dft4(float2* x) {
-  float2 t0 = add_nz<NZ, 2>(x, 0), t1 = sub_nz<NZ, 2>(x, 0);
-  float2 t2, t3;
+template <bool INV, int NZ = 4, typename V>
+__device__ __forceinline__ void dft4(V* x) {
+  V t0 = add_nz<NZ, 2>(x, 0), t1 = sub_nz<NZ, 2>(x, 0);
+  V t2, t3;
   if constexpr (NZ > 1) {
     t2 = add_nz<NZ, 3>(x, 1);
     t3 = rot_i<INV>(sub_nz<NZ, 3>(x, 1));
   } else {
-    t2 = t3 = make_float2(0.f, 0.f);
+    t2 = t3 = czero<V>();
   }
   x[0] = cadd(t0, t2);
   x[2] = csub(t0, t2);
@@ -73,21 +98,22 @@ __device__ __forceinline__ void dft4(float2* x) {
   x[3] = csub(t1, t3);
 }
 
-template <bool INV, int NZ = 8>
-__device__ __forceinline__ void dft8(float2* x) {
+template <bool INV, int NZ = 8, typename V>
+__device__ __forceinline__ void dft8(V* x) {
   static_assert(NZ >= 4, "dft8 prunes at most its upper half");
-  constexpr float h = 0.70710678118654752f;
-  float2 a[4], b[4];
+  using S = scalar_t<V>;
+  constexpr S h = std::is_same<S, float>::value ? S(0.70710678118654752f) : S(0.70710678118654752440);
+  V a[4], b[4];
   a[0] = add_nz<NZ, 4>(x, 0); b[0] = sub_nz<NZ, 4>(x, 0);
   a[1] = add_nz<NZ, 5>(x, 1); b[1] = sub_nz<NZ, 5>(x, 1);
   a[2] = add_nz<NZ, 6>(x, 2); b[2] = sub_nz<NZ, 6>(x, 2);
   a[3] = add_nz<NZ, 7>(x, 3); b[3] = sub_nz<NZ, 7>(x, 3);
   // b[k] *= W8^k  (W8 = exp(-i pi/4) forward, conjugate inverse)
-  b[1] = INV ? make_float2(h * (b[1].x - b[1].y), h * (b[1].x + b[1].y))
-             : make_float2(h * (b[1].x + b[1].y), h * (b[1].y - b[1].x));
+  b[1] = INV ? cplx<V>(h * (b[1].x - b[1].y), h * (b[1].x + b[1].y))
+             : cplx<V>(h * (b[1].x + b[1].y), h * (b[1].y - b[1].x));
   b[2] = rot_i<INV>(b[2]);
-  b[3] = INV ? make_float2(-h * (b[3].x + b[3].y), h * (b[3].x - b[3].y))
-             : make_float2(h * (b[3].y - b[3].x), -h * (b[3].x + b[3].y));
+  b[3] = INV ? cplx<V>(-h * (b[3].x + b[3].y), h * (b[3].x - b[3].y))
+             : cplx<V>(h * (b[3].y - b[3].x), -h * (b[3].x + b[3].y));
   dft4<INV>(a);
   dft4<INV>(b);
 #pragma unroll
@@ -117,15 +143,46 @@ template <> struct OddRoots<11> {
   static constexpr float s[5] = {0.54064081745559756f, 0.90963199535451833f, 0.9898214418809328f,
                                  0.75574957435425827f, 0.28173255684142967f};
 };
+// the same in double precision
+template <int R> struct OddRootsD;
+template <> struct OddRootsD<3> {
+  static constexpr double c[1] = {-0.5};
+  static constexpr double s[1] = {0.86602540378443864676};
+};
+template <> struct OddRootsD<5> {
+  static constexpr double c[2] = {0.30901699437494742410, -0.80901699437494742410};
+  static constexpr double s[2] = {0.95105651629515357212, 0.58778525229247312917};
+};
+template <> struct OddRootsD<7> {
+  static constexpr double c[3] = {0.62348980185873353053, -0.22252093395631440429, -0.90096886790241912624};
+  static constexpr double s[3] = {0.78183148246802980871, 0.97492791218182360702, 0.43388373911755812048};
+};
+template <> struct OddRootsD<11> {
+  static constexpr double c[5] = {0.84125353283118116886, 0.41541501300188642553, -0.14231483827328514044,
+                                  -0.65486073394528506406, -0.95949297361449738989};
+  static constexpr double s[5] = {0.54064081745559758211, 0.90963199535451837141, 0.98982144188093273238,
+                                  0.75574957435425828377, 0.28173255684142969771};
+};
+template <typename S, int R>
+__device__ __forceinline__ S root_c(int i) {
+  if constexpr (std::is_same<S, float>::value) return OddRoots<R>::c[i];
+  else return OddRootsD<R>::c[i];
+}
+template <typename S, int R>
+__device__ __forceinline__ S root_s(int i) {
+  if constexpr (std::is_same<S, float>::value) return OddRoots<R>::s[i];
+  else return OddRootsD<R>::s[i];
+}
 
 // Odd prime R: pair x_m with x_{R-m}; y_k = A_k -+ i B_k, y_{R-k} = A_k +- i B_k with
 // A_k = x_0 + sum_m (x_m + x_{R-m}) cos(2 pi k m / R), B_k = sum_m (x_m - x_{R-m}) sin(..).
-template <int R, bool INV, int NZ = R>
-__device__ __forceinline__ void dft_odd(float2* x) {
+template <int R, bool INV, int NZ = R, typename V>
+__device__ __forceinline__ void dft_odd(V* x) {
+  using S = scalar_t<V>;
   constexpr int h = (R - 1) / 2;
   static_assert(NZ > h, "dft_odd prunes at most its upper half");
-  float2 a[h + 1], b[h + 1];
-  float2 y0 = x[0];
+  V a[h + 1], b[h + 1];
+  V y0 = x[0];
 #pragma unroll
   for (int m = 1; m <= h; ++m) {
     const bool upper_zero = R - m >= NZ;   // compile time after unrolling
@@ -133,36 +190,36 @@ __device__ __forceinline__ void dft_odd(float2* x) {
     b[m] = upper_zero ? x[m] : csub(x[m], x[R - m]);
     y0 = cadd(y0, a[m]);
   }
-  float2 out[R];
+  V out[R];
   out[0] = y0;
 #pragma unroll
   for (int k = 1; k <= h; ++k) {
-    float2 A = x[0];
-    float2 B = make_float2(0.f, 0.f);
+    V A = x[0];
+    V B = czero<V>();
 #pragma unroll
     for (int m = 1; m <= h; ++m) {
       const int j = (k * m) % R;
-      const float c = (j <= h) ? OddRoots<R>::c[j - 1] : OddRoots<R>::c[R - j - 1];
-      const float s = (j <= h) ? OddRoots<R>::s[j - 1] : -OddRoots<R>::s[R - j - 1];
-      A.x = fmaf(a[m].x, c, A.x);
-      A.y = fmaf(a[m].y, c, A.y);
-      B.x = fmaf(b[m].x, s, B.x);
-      B.y = fmaf(b[m].y, s, B.y);
+      const S c = (j <= h) ? root_c<S, R>(j - 1) : root_c<S, R>(R - j - 1);
+      const S s = (j <= h) ? root_s<S, R>(j - 1) : -root_s<S, R>(R - j - 1);
+      A.x = fmadd(a[m].x, c, A.x);
+      A.y = fmadd(a[m].y, c, A.y);
+      B.x = fmadd(b[m].x, s, B.x);
+      B.y = fmadd(b[m].y, s, B.y);
     }
     if (!INV) {
-      out[k] = make_float2(A.x + B.y, A.y - B.x);
-      out[R - k] = make_float2(A.x - B.y, A.y + B.x);
+      out[k] = cplx<V>(A.x + B.y, A.y - B.x);
+      out[R - k] = cplx<V>(A.x - B.y, A.y + B.x);
     } else {
-      out[k] = make_float2(A.x - B.y, A.y + B.x);
-      out[R - k] = make_float2(A.x + B.y, A.y - B.x);
+      out[k] = cplx<V>(A.x - B.y, A.y + B.x);
+      out[R - k] = cplx<V>(A.x + B.y, A.y - B.x);
     }
   }
 #pragma unroll
   for (int k = 0; k < R; ++k) x[k] = out[k];
 }
 
-template <int R, bool INV, int NZ = R>
-__device__ __forceinline__ void dft(float2* x) {
+template <int R, bool INV, int NZ = R, typename V>
+__device__ __forceinline__ void dft(V* x) {
   if constexpr (R == 2) dft2<INV, NZ>(x);
   else if constexpr (R == 4) dft4<INV, NZ>(x);
   else if constexpr (R == 8) dft8<INV, NZ>(x);
@@ -171,14 +228,14 @@ __device__ __forceinline__ void dft(float2* x) {
 
 // ---------------------------------------------------------------- one Stockham stage
 // LW is the largest L * W this instance must handle; it bounds the butterflies per thread.
-template <int R, int W, int T, int LW, bool INV>
-__device__ __forceinline__ void fft_stage(float2* __restrict__ buf, const float2* __restrict__ tw,
+template <int R, int W, int T, int LW, bool INV, typename V>
+__device__ __forceinline__ void fft_stage(V* __restrict__ buf, const V* __restrict__ tw,
                                           int L, int ns) {
   constexpr int NB = (LW / R + T - 1) / T;
   const int lr = L / R;
   const int nbf = lr * W;
   const int twstep = L / (ns * R);
-  float2 v[NB][R];
+  V v[NB][R];
 #pragma unroll
   for (int u = 0; u < NB; ++u) {
     const int bf = (int)threadIdx.x + u * T;
@@ -198,7 +255,7 @@ __device__ __forceinline__ void fft_stage(float2* __restrict__ buf, const float2
       if (ns > 1) {
 #pragma unroll
         for (int t = 1; t < R; ++t) {
-          float2 w = tw[t * k * twstep];
+          V w = tw[t * k * twstep];
           if (INV) w.y = -w.y;
           v[u][t] = cmul(v[u][t], w);
         }
@@ -252,13 +309,13 @@ constexpr CPlan make_cplan(int L) {
 
 // One stage with everything known at compile time (exact butterflies per thread, no
 // run-time division).
-template <int L, int R, int NS, int W, int T, bool INV>
-__device__ __forceinline__ void fft_stage_fixed(float2* __restrict__ buf, const float2* __restrict__ tw) {
+template <int L, int R, int NS, int W, int T, bool INV, typename V>
+__device__ __forceinline__ void fft_stage_fixed(V* __restrict__ buf, const V* __restrict__ tw) {
   constexpr int LR = L / R;
   constexpr int NBF = LR * W;
   constexpr int NB = (NBF + T - 1) / T;
   constexpr int TWSTEP = L / (NS * R);
-  float2 v[NB][R];
+  V v[NB][R];
 #pragma unroll
   for (int u = 0; u < NB; ++u) {
     const unsigned bf = threadIdx.x + u * T;
@@ -278,7 +335,7 @@ __device__ __forceinline__ void fft_stage_fixed(float2* __restrict__ buf, const 
       if constexpr (NS > 1) {
 #pragma unroll
         for (int t = 1; t < R; ++t) {
-          float2 w = tw[t * k * TWSTEP];
+          V w = tw[t * k * TWSTEP];
           if (INV) w.y = -w.y;
           v[u][t] = cmul(v[u][t], w);
         }
@@ -292,8 +349,8 @@ __device__ __forceinline__ void fft_stage_fixed(float2* __restrict__ buf, const 
   __syncthreads();
 }
 
-template <int L, int S, int W, int T, bool INV>
-__device__ __forceinline__ void fft_fixed(float2* __restrict__ buf, const float2* __restrict__ tw) {
+template <int L, int S, int W, int T, bool INV, typename V>
+__device__ __forceinline__ void fft_fixed(V* __restrict__ buf, const V* __restrict__ tw) {
   constexpr CPlan P = make_cplan(L);
   if constexpr (S < P.nst) {
     fft_stage_fixed<L, P.r[S], P.ns[S], W, T, INV>(buf, tw);
@@ -304,8 +361,8 @@ __device__ __forceinline__ void fft_fixed(float2* __restrict__ buf, const float2
 // Whole transform.  LC > 0: the length is LC, planned at compile time.  LC == 0: run-time
 // plan pl (any supported length up to kMaxLen).  Caller has synchronised after filling buf;
 // on return buf holds the result in natural order and the group is synchronised.
-template <int W, int T, int LC, bool INV>
-__device__ void fft_lds(float2* __restrict__ buf, const float2* __restrict__ tw, const FftPlan& pl) {
+template <int W, int T, int LC, bool INV, typename V>
+__device__ void fft_lds(V* __restrict__ buf, const V* __restrict__ tw, const FftPlan& pl) {
   if constexpr (LC > 0) {
     fft_fixed<LC, 0, W, T, INV>(buf, tw);
   } else {
@@ -329,7 +386,7 @@ __device__ void fft_lds(float2* __restrict__ buf, const float2* __restrict__ tw,
 // ---------------------------------------------------------------- transform with fused I/O
 // Fixed-length transform of W pencils whose first stage takes its inputs from a producer
 // and whose last stage hands its outputs to a consumer, so that neither passes through LDS:
-//   ld(i0, i1, p)       -> float2   input element i0 + i1 of pencil p     (IN_LDS = false)
+//   ld(i0, i1, p)       -> V        input element i0 + i1 of pencil p     (IN_LDS = false)
 //   st(k0, k1, p, v, slot)         output element k0 + k1 of pencil p; slot is a compile-time
 //                                  index (butterfly * R + t) unique per thread (OUT_LDS = false)
 // The element index comes in two parts: i0 / k0 is the same for all R elements of a
@@ -365,19 +422,19 @@ __device__ __forceinline__ unsigned opaque_base(unsigned x) {
 }
 
 template <int L, int R, int NS, int W, int WS, int WSO, int T, bool INV, bool FROM_LD, bool TO_ST, int NZ, typename LD,
-          typename ST>
-__device__ __forceinline__ void fft_stage_io(float2* __restrict__ buf, const float2* __restrict__ tw, LD& ld, ST& st) {
+          typename ST, typename V>
+__device__ __forceinline__ void fft_stage_io(V* __restrict__ buf, const V* __restrict__ tw, LD& ld, ST& st) {
   const unsigned tx = opaque_tid();
   constexpr int LR = L / R;
   constexpr int NBF = LR * W;
   constexpr int NB = (NBF + T - 1) / T;
   constexpr int TWSTEP = L / (NS * R);
-  auto finish = [&](float2* v, unsigned p, unsigned j, int u) {
+  auto finish = [&](V* v, unsigned p, unsigned j, int u) {
     const unsigned q = div_small<NS, LR>(j), k = j - q * NS;
     if constexpr (NS > 1) {
 #pragma unroll
       for (int t = 1; t < R; ++t) {
-        float2 w = tw[t * k * TWSTEP];
+        V w = tw[t * k * TWSTEP];
         if (INV) w.y = -w.y;
         v[t] = cmul(v[t], w);
       }
@@ -401,10 +458,10 @@ __device__ __forceinline__ void fft_stage_io(float2* __restrict__ buf, const flo
       const unsigned bf = tx + u * T;
       if (NBF % T == 0 || bf < NBF) {
         const unsigned p = bf % W, j = bf / W;
-        float2 v[R];
+        V v[R];
         if constexpr (FROM_LD) {
 #pragma unroll
-          for (int t = 0; t < R; ++t) v[t] = t < NZ ? ld(j, t * LR, p) : make_float2(0.f, 0.f);
+          for (int t = 0; t < R; ++t) v[t] = t < NZ ? ld(j, t * LR, p) : czero<V>();
         } else {
           const unsigned rb = opaque_base(j * WS + p);
 #pragma unroll
@@ -415,7 +472,7 @@ __device__ __forceinline__ void fft_stage_io(float2* __restrict__ buf, const flo
     }
   } else {
     // in place: every butterfly of the group is read before any is written
-    float2 v[NB][R];
+    V v[NB][R];
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
       const unsigned bf = tx + u * T;
@@ -437,8 +494,8 @@ __device__ __forceinline__ void fft_stage_io(float2* __restrict__ buf, const flo
 }
 
 template <int L, int S, int W, int WS, int WSO, int T, bool INV, bool IN_LDS, bool OUT_LDS, bool HALF, typename LD,
-          typename ST>
-__device__ __forceinline__ void fft_io_stages(float2* __restrict__ buf, const float2* __restrict__ tw, LD& ld, ST& st) {
+          typename ST, typename V>
+__device__ __forceinline__ void fft_io_stages(V* __restrict__ buf, const V* __restrict__ tw, LD& ld, ST& st) {
   constexpr CPlan P = make_cplan(L);
   if constexpr (S < P.nst) {
     constexpr bool first = (S == 0), last = (S + 1 == P.nst);
@@ -493,8 +550,8 @@ constexpr int consumer_slots() {
 // HALF (compile-time plans, producer input): the producer's inputs i >= L/2 are zero and
 // are neither requested nor added.
 template <int LC, int W, int T, bool INV, bool IN_LDS, bool OUT_LDS, int WSO = W, bool HALF = false, typename LD,
-          typename ST>
-__device__ __forceinline__ void fft_io(float2* __restrict__ buf, const float2* __restrict__ tw, const FftPlan& pl,
+          typename ST, typename V>
+__device__ __forceinline__ void fft_io(V* __restrict__ buf, const V* __restrict__ tw, const FftPlan& pl,
                                        LD&& ld, ST&& st) {
   static_assert(LC > 0 || WSO == W, "a padded result needs a compile-time plan");
   if constexpr (LC > 0) {
@@ -517,14 +574,14 @@ __device__ __forceinline__ void fft_io(float2* __restrict__ buf, const float2* _
 constexpr int kFastLengths[] = {16, 32, 48, 56, 64, 88, 96, 110, 128, 176, 192, 220, 256, 352, 440, 512};
 
 // Copy this length's twiddle table into LDS (caller synchronises before use).
-__device__ __forceinline__ void load_twiddles(float2* __restrict__ dst, const float2* __restrict__ table,
-                                              const FftPlan& pl) {
+template <typename V>
+__device__ __forceinline__ void load_twiddles(V* __restrict__ dst, const V* __restrict__ table, const FftPlan& pl) {
   // two loads in flight per thread before either is stored (L <= 2 * blockDim.x in one pass)
   const int L = pl.L, T = blockDim.x;
-  const float2* src = table + pl.tw_off;
+  const V* src = table + pl.tw_off;
   for (int i = threadIdx.x; i < L; i += 2 * T) {
     const int j = i + T < L ? i + T : i;
-    const float2 a = src[i], b = src[j];
+    const V a = src[i], b = src[j];
     dst[i] = a;
     dst[j] = b;
   }

@@ -102,6 +102,7 @@ __device__ __forceinline__ size_t align16(size_t b) { return (b + 15) & ~size_t(
 // Every view here spans less than 2 GiB, so kNoOff is always out of range.
 constexpr uint32_t kNoOff = 0x80000000u;
 typedef unsigned int u32x2 __attribute__((__vector_size__(8)));
+typedef unsigned int u32x4 __attribute__((__vector_size__(16)));
 
 // Cache policy of the intermediates: every pass writes its output once, for the next pass
 // to read once, so stores (bit 0) and those loads (bit 1) are non-temporal.  That keeps them
@@ -136,6 +137,29 @@ struct RView {
     __builtin_memcpy(&v, &x, 8);
     __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)off, 0, kStreamSt ? 2 : 0);
   }
+  // complex element of type V (float2 or double2); STREAM: read once (non-temporal when
+  // kStreamLd), as ld2s
+  template <typename V, bool STREAM>
+  __device__ __forceinline__ V ldv(uint32_t off, uint32_t soff = 0) const {
+    if constexpr (sizeof(V) == 8) {
+      return STREAM ? ld2s(off, soff) : ld2(off, soff);
+    } else {
+      const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, (int)soff, (STREAM && kStreamLd) ? 2 : 0);
+      V x;
+      __builtin_memcpy(&x, &v, 16);
+      return x;
+    }
+  }
+  template <typename V>
+  __device__ __forceinline__ void stv(uint32_t off, V x) const {
+    if constexpr (sizeof(V) == 8) {
+      st2(off, x);
+    } else {
+      u32x4 v;
+      __builtin_memcpy(&v, &x, 16);
+      __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)off, 0, kStreamSt ? 2 : 0);
+    }
+  }
   __device__ __forceinline__ unsigned ld1(uint32_t off, uint32_t soff = 0) const {
     return __builtin_amdgcn_raw_buffer_load_b8(r, (int)off, (int)soff, 0);
   }
@@ -158,6 +182,11 @@ struct RView {
 // (row < 2^24 and rs8 < 2^24, product < 2^31)
 __device__ __forceinline__ uint32_t off2(int row, uint32_t rs8, int col) {
   return __umul24((unsigned)row, rs8) + 8u * (unsigned)col;
+}
+// the same for an array of complex V with a row stride of rsb bytes
+template <typename V>
+__device__ __forceinline__ uint32_t offv(int row, uint32_t rsb, int col) {
+  return __umul24((unsigned)row, rsb) + (uint32_t)sizeof(V) * (unsigned)col;
 }
 
 // ------------------------------------------------------------------------------ x pass
@@ -483,12 +512,13 @@ __global__ __launch_bounds__(kThreadsF) void k_fields_x(
 // Pencils along the middle axis.  Workgroup (x-tile, group g, slot): input rows i < n_in of
 // in[g], zero beyond; output row c takes transform row (c + out_off) mod L.  HALF: n_in <= L/2
 // (first stage pruned).
-template <bool INV, int LC, bool HALF>
+template <bool INV, int LC, bool HALF, typename V = float2>
 __global__ __launch_bounds__(kThreadsP<INV>) void k_pencil(
-    const float2* __restrict__ in, float2* __restrict__ out, int n_in, int n_out, int out_off,
-    FftPlan pl, const float2* __restrict__ twtab, int H, int Hp, long long in_gstride,
+    const V* __restrict__ in, V* __restrict__ out, int n_in, int n_out, int out_off,
+    FftPlan pl, const V* __restrict__ twtab, int H, int Hp, long long in_gstride,
     long long out_gstride, long long in_sstride, long long out_sstride, const uint8_t* __restrict__ flags,
     long long flag_sstride, int ngroups) {
+  using S = scalar_t<V>;
   constexpr int W = kTileP<INV>;
   extern __shared__ __align__(16) unsigned char smem[];
   const int L = pl.L;
@@ -497,18 +527,18 @@ __global__ __launch_bounds__(kThreadsP<INV>) void k_pencil(
   const uint8_t* fl = flags ? flags + blockIdx.z * flag_sstride : nullptr;
   if (fl && !fl[blockIdx.y]) return;
   const uint8_t* rowfl = fl ? fl + ngroups + (long long)blockIdx.y * n_out : nullptr;
-  float2* tw = reinterpret_cast<float2*>(smem);
-  float2* buf = reinterpret_cast<float2*>(smem + align16(sizeof(float2) * L));
+  V* tw = reinterpret_cast<V*>(smem);
+  V* buf = reinterpret_cast<V*>(smem + align16(sizeof(V) * L));
   const int kx0 = blockIdx.x * W;
   // views from this tile's first element to the end of its group (rows n_in resp. n_out)
-  const RView src(in + blockIdx.z * in_sstride + blockIdx.y * in_gstride + kx0, 8LL * ((long long)n_in * Hp - kx0));
+  const RView src(in + blockIdx.z * in_sstride + blockIdx.y * in_gstride + kx0, (long long)sizeof(V) * ((long long)n_in * Hp - kx0));
   const RView dst(out + blockIdx.z * out_sstride + blockIdx.y * out_gstride + kx0,
-                  8LL * ((long long)n_out * Hp - kx0));
-  const uint32_t rs8 = 8u * (uint32_t)Hp;
+                  (long long)sizeof(V) * ((long long)n_out * Hp - kx0));
+  const uint32_t rsb = (uint32_t)sizeof(V) * (uint32_t)Hp;
   load_twiddles(tw, twtab, pl);
   // inverse with flags: the group's row flags go to LDS once (rows c >= n_out read 0), so the
   // last stage's stores need no global load each
-  uint8_t* rfl = reinterpret_cast<uint8_t*>(smem + align16(sizeof(float2) * L) + align16(sizeof(float2) * L * W));
+  uint8_t* rfl = reinterpret_cast<uint8_t*>(smem + align16(sizeof(V) * L) + align16(sizeof(V) * L * W));
   if (INV && rowfl) {
     const RView rflag(rowfl, n_out);
     for (int c = threadIdx.x; c < L; c += kThreadsP<INV>) rfl[c] = (uint8_t)rflag.ld1((uint32_t)c);
@@ -519,16 +549,16 @@ __global__ __launch_bounds__(kThreadsP<INV>) void k_pencil(
   // rows i >= n_in lie past the input view and load zero; rows c >= n_out past the output
   // view (and its flag view) and are dropped; columns >= H are masked by kNoOff
   constexpr int T = kThreadsP<INV>;
-  auto load = [&](int i0, int i1, int p) -> float2 {
-    const uint32_t b = kx0 + p < H ? off2(i0, rs8, p) : kNoOff;
-    return src.ld2s(b + (uint32_t)i1 * rs8);
+  auto load = [&](int i0, int i1, int p) -> V {
+    const uint32_t b = kx0 + p < H ? offv<V>(i0, rsb, p) : kNoOff;
+    return src.template ldv<V, true>(b + (uint32_t)i1 * rsb);
   };
-  auto store = [&](int k0, int k1, int p, float2 v, int) {
+  auto store = [&](int k0, int k1, int p, V v, int) {
     int c = k0 + k1 - out_off;
     if (c < 0) c += L;
     bool keep = kx0 + p < H;
     if constexpr (INV) keep = keep & (!rowfl | (rfl[c] != 0));   // the flag region exists for the inverse
-    dst.st2(keep ? off2(c, rs8, p) : kNoOff, v);
+    dst.template stv<V>(keep ? offv<V>(c, rsb, p) : kNoOff, v);
   };
   if (kx0 != 0) {
     fft_io<LC, W, T, INV, false, false, W, HALF>(buf, tw, pl, load, store);
@@ -540,17 +570,17 @@ __global__ __launch_bounds__(kThreadsP<INV>) void k_pencil(
     // forward (out_off = 0, all rows kept): transform into LDS, then split the packed pencil,
     // Y = D + i N: row c < L/2 takes D(c) = (Y(c) + conj Y(-c)) / 2, row L - c takes
     // N(c) = -i (Y(c) - conj Y(-c)) / 2; rows 0 and L/2 keep Y
-    fft_io<LC, W, T, false, false, true, W, HALF>(buf, tw, pl, load, [](int, int, int, float2, int) {});
+    fft_io<LC, W, T, false, false, true, W, HALF>(buf, tw, pl, load, [](int, int, int, V, int) {});
     __syncthreads();
     for (int e = threadIdx.x; e < L * W; e += T) {
       const int c = e / W, p = e - c * W;
-      float2 v = buf[e];
+      V v = buf[e];
       if (p == 0 && c != 0 && c != half) {
-        const float2 m = buf[(L - c) * W];
-        v = c < half ? make_float2(0.5f * (v.x + m.x), 0.5f * (v.y - m.y))
-                     : make_float2(0.5f * (v.y + m.y), 0.5f * (v.x - m.x));
+        const V m = buf[(L - c) * W];
+        v = c < half ? cplx<V>(S(0.5) * (v.x + m.x), S(0.5) * (v.y - m.y))
+                     : cplx<V>(S(0.5) * (v.y + m.y), S(0.5) * (v.x - m.x));
       }
-      dst.st2(kx0 + p < H ? off2(c, rs8, p) : kNoOff, v);
+      dst.template stv<V>(kx0 + p < H ? offv<V>(c, rsb, p) : kNoOff, v);
     }
   } else {
     // inverse: the input rows are S_D(ky) for ky < L/2 and S_N(L - ky) above (rows 0 and
@@ -558,13 +588,13 @@ __global__ __launch_bounds__(kThreadsP<INV>) void k_pencil(
     // of both planes for the rows that are not stored
     fft_io<LC, W, T, true, false, false, W, false>(
         buf, tw, pl,
-        [&](int i0, int i1, int p) -> float2 {
+        [&](int i0, int i1, int p) -> V {
           // branch-free, so a butterfly's loads are all in flight together
-          const float2 s = load(i0, i1, p);
+          const V s = load(i0, i1, p);
           const int i = i0 + i1;
           const bool mix = p == 0 && i != 0 && i != half;
-          const float2 m = src.ld2(mix ? off2(L - i, rs8, 0) : kNoOff);
-          const float2 g = i < half ? make_float2(s.x - m.y, s.y + m.x) : make_float2(m.x + s.y, s.x - m.y);
+          const V m = src.template ldv<V, false>(mix ? offv<V>(L - i, rsb, 0) : kNoOff);
+          const V g = i < half ? cplx<V>(s.x - m.y, s.y + m.x) : cplx<V>(m.x + s.y, s.x - m.y);
           return mix ? g : s;
         },
         store);
@@ -580,18 +610,19 @@ __global__ __launch_bounds__(kThreadsP<INV>) void k_pencil(
 // PACKED: a separate launch of 2 workgroups per slot for tile 0 at ky = 0 and Py/2, whose
 // first pencil is the packed DC/Nyquist column (see the top of this file); the main launch
 // skips those two tiles.  Kept apart so the main kernel's register budget is unchanged.
-template <int LC, bool HALF, bool PACKED>
+template <int LC, bool HALF, bool PACKED, typename V = float2>
 __global__ __launch_bounds__(kThreadsZ) void k_zpass(
-    const float2* __restrict__ X2, const float2* __restrict__ spec, float2* __restrict__ Y3,
-    int nz, int Py, int H, int Hp, int Wz, int out_off, FftPlan pl, const float2* __restrict__ twtab,
+    const V* __restrict__ X2, const V* __restrict__ spec, V* __restrict__ Y3,
+    int nz, int Py, int H, int Hp, int Wz, int out_off, FftPlan pl, const V* __restrict__ twtab,
     long long x2_sstride, long long y3_sstride, int ntiles, int nslots, int nreal,
     const uint8_t* __restrict__ flags, long long flag_sstride, int nf) {
+  using S = scalar_t<V>;
   constexpr int W = kTileW;
   constexpr int NSLOT = consumer_slots<LC, W, kThreadsZ>();
   extern __shared__ __align__(16) unsigned char smem[];
   const int Pz = pl.L;
-  float2* tw = reinterpret_cast<float2*>(smem);
-  float2* buf = reinterpret_cast<float2*>(smem + align16(sizeof(float2) * Pz));
+  V* tw = reinterpret_cast<V*>(smem);
+  V* buf = reinterpret_cast<V*>(smem + align16(sizeof(V) * Pz));
   int slot, ky, kx0;
   if constexpr (PACKED) {
     if ((int)blockIdx.x >= 2 * nslots) return;
@@ -617,32 +648,32 @@ __global__ __launch_bounds__(kThreadsZ) void k_zpass(
   const long long fstride_sp = (long long)Pz * Py * Hp;
   const long long zs = (long long)Py * Hp;
   const long long col0 = (long long)ky * Hp + kx0;
-  const uint32_t zs8 = 8u * (uint32_t)zs;
+  const uint32_t zsb = (uint32_t)sizeof(V) * (uint32_t)zs;
   // views from this pencil tile to the end of field f: moving input (rows i >= nz lie past
   // it and load zero) and A's spectrum; masked columns load zero and are never stored
-  auto src_view = [&](int f) { return RView(X2 + slot * x2_sstride + f * fstride_x2 + col0, 8 * (fstride_x2 - col0)); };
-  auto spec_view = [&](int f) { return RView(spec + f * fstride_sp + col0, 8 * (fstride_sp - col0)); };
+  auto src_view = [&](int f) { return RView(X2 + slot * x2_sstride + f * fstride_x2 + col0, (long long)sizeof(V) * (fstride_x2 - col0)); };
+  auto spec_view = [&](int f) { return RView(spec + f * fstride_sp + col0, (long long)sizeof(V) * (fstride_sp - col0)); };
   auto loader = [&](const RView& src) {
-    return [&src, kx0, H, zs8](int i0, int i1, int p) -> float2 {
-      const uint32_t b = kx0 + p < H ? off2(i0, zs8, p) : kNoOff;
-      return src.ld2s(b + (uint32_t)i1 * zs8);
+    return [&src, kx0, H, zsb](int i0, int i1, int p) -> V {
+      const uint32_t b = kx0 + p < H ? offv<V>(i0, zsb, p) : kNoOff;
+      return src.template ldv<V, true>(b + (uint32_t)i1 * zsb);
     };
   };
   if constexpr (!PACKED) {
-    float2 acc[NSLOT];
+    V acc[NSLOT];
 #pragma unroll
-    for (int u = 0; u < NSLOT; ++u) acc[u] = make_float2(0.f, 0.f);
+    for (int u = 0; u < NSLOT; ++u) acc[u] = czero<V>();
 #pragma unroll 1
     for (int f = 0; f < nf; ++f) {
       const RView src = src_view(f);
       const RView a = spec_view(f);
       fft_io<LC, W, kThreadsZ, false, false, false, W, HALF>(
           buf, tw, pl, loader(src),
-          [&](int k0, int k1, int p, float2 v, int sl) {
-            const uint32_t b = kx0 + p < H ? off2(k0, zs8, p) : kNoOff;
-            const float2 sv = a.ld2(b + (uint32_t)k1 * zs8);
-            acc[sl].x = fmaf(v.x, sv.x, fmaf(-v.y, sv.y, acc[sl].x));
-            acc[sl].y = fmaf(v.x, sv.y, fmaf(v.y, sv.x, acc[sl].y));
+          [&](int k0, int k1, int p, V v, int sl) {
+            const uint32_t b = kx0 + p < H ? offv<V>(k0, zsb, p) : kNoOff;
+            const V sv = a.template ldv<V, false>(b + (uint32_t)k1 * zsb);
+            acc[sl].x = fmadd(v.x, sv.x, fmadd(-v.y, sv.y, acc[sl].x));
+            acc[sl].y = fmadd(v.x, sv.y, fmadd(v.y, sv.x, acc[sl].y));
           });
       __syncthreads();
     }
@@ -658,46 +689,46 @@ __global__ __launch_bounds__(kThreadsZ) void k_zpass(
     // A's D and N spectra from the same split stored by k_zstore, and accumulate
     // conj(A_D) B_D + i conj(A_N) B_N, whose z inverse is (D-plane sum) + i (Nyquist-plane sum).
     constexpr int NE = ((LC > 0 ? LC : kMaxLen) * W + kThreadsZ - 1) / kThreadsZ;
-    float2 acc[NE];
+    V acc[NE];
 #pragma unroll
-    for (int u = 0; u < NE; ++u) acc[u] = make_float2(0.f, 0.f);
+    for (int u = 0; u < NE; ++u) acc[u] = czero<V>();
     const int hz = Pz / 2;
 #pragma unroll 1
     for (int f = 0; f < nf; ++f) {
       const RView src = src_view(f);
       const RView a = spec_view(f);
       fft_io<LC, W, kThreadsZ, false, false, true, W, HALF>(buf, tw, pl, loader(src),
-                                                          [](int, int, int, float2, int) {});
+                                                          [](int, int, int, V, int) {});
       __syncthreads();
 #pragma unroll
       for (int u = 0; u < NE; ++u) {
         const int e = (int)threadIdx.x + u * kThreadsZ;
         if (e < Pz * W) {
           const int kz = e / W, p = e - kz * W;
-          const float2 v = buf[e];
-          const float2 sk = a.ld2(kx0 + p < H ? off2(kz, zs8, p) : kNoOff);
+          const V v = buf[e];
+          const V sk = a.template ldv<V, false>(kx0 + p < H ? offv<V>(kz, zsb, p) : kNoOff);
           if (p != 0) {
-            acc[u].x = fmaf(v.x, sk.x, fmaf(-v.y, sk.y, acc[u].x));
-            acc[u].y = fmaf(v.x, sk.y, fmaf(v.y, sk.x, acc[u].y));
+            acc[u].x = fmadd(v.x, sk.x, fmadd(-v.y, sk.y, acc[u].x));
+            acc[u].y = fmadd(v.x, sk.y, fmadd(v.y, sk.x, acc[u].y));
           } else {
             const int m = kz ? Pz - kz : 0;
-            const float2 vm = buf[m * W];
-            const float2 sm = a.ld2(off2(m, zs8, 0));
-            const float2 bd = make_float2(0.5f * (v.x + vm.x), 0.5f * (v.y - vm.y));   // B_D(kz)
-            const float2 bn = make_float2(0.5f * (v.y + vm.y), 0.5f * (vm.x - v.x));   // B_N(kz)
-            float2 ad, an;   // w conj(A_D(kz)), w conj(A_N(kz))
+            const V vm = buf[m * W];
+            const V sm = a.template ldv<V, false>(offv<V>(m, zsb, 0));
+            const V bd = cplx<V>(S(0.5) * (v.x + vm.x), S(0.5) * (v.y - vm.y));   // B_D(kz)
+            const V bn = cplx<V>(S(0.5) * (v.y + vm.y), S(0.5) * (vm.x - v.x));   // B_N(kz)
+            V ad, an;   // w conj(A_D(kz)), w conj(A_N(kz))
             if (kz == 0 || kz == hz) {
-              ad = make_float2(sk.x, 0.f);
-              an = make_float2(-sk.y, 0.f);
+              ad = cplx<V>(sk.x, S(0));
+              an = cplx<V>(-sk.y, S(0));
             } else if (kz < hz) {
               ad = sk;
               an = sm;
             } else {
-              ad = make_float2(sm.x, -sm.y);
-              an = make_float2(sk.x, -sk.y);
+              ad = cplx<V>(sm.x, -sm.y);
+              an = cplx<V>(sk.x, -sk.y);
             }
-            const float2 t1 = make_float2(ad.x * bd.x - ad.y * bd.y, ad.x * bd.y + ad.y * bd.x);
-            const float2 t2 = make_float2(an.x * bn.x - an.y * bn.y, an.x * bn.y + an.y * bn.x);
+            const V t1 = cplx<V>(ad.x * bd.x - ad.y * bd.y, ad.x * bd.y + ad.y * bd.x);
+            const V t2 = cplx<V>(an.x * bn.x - an.y * bn.y, an.x * bn.y + an.y * bn.x);
             acc[u].x += t1.x - t2.y;
             acc[u].y += t1.y + t2.x;
           }
@@ -712,69 +743,70 @@ __global__ __launch_bounds__(kThreadsZ) void k_zpass(
     }
   }
   __syncthreads();
-  const RView dst(Y3 + slot * y3_sstride + col0, 8 * ((long long)Wz * zs - col0));
+  const RView dst(Y3 + slot * y3_sstride + col0, (long long)sizeof(V) * ((long long)Wz * zs - col0));
   // kept-row flags to LDS (rows c >= Wz read 0); the inverse's stage barriers order these
   // writes before the last stage reads them
-  uint8_t* zfl = reinterpret_cast<uint8_t*>(smem + align16(sizeof(float2) * Pz) + align16(sizeof(float2) * Pz * W));
+  uint8_t* zfl = reinterpret_cast<uint8_t*>(smem + align16(sizeof(V) * Pz) + align16(sizeof(V) * Pz * W));
   {
     const RView zflag(flags + slot * flag_sstride, Wz);
     for (int c = threadIdx.x; c < Pz; c += kThreadsZ) zfl[c] = (uint8_t)zflag.ld1((uint32_t)c);
     __syncthreads();
   }
   fft_io<LC, W, kThreadsZ, true, true, false>(
-      buf, tw, pl, [](int, int, int) { return make_float2(0.f, 0.f); },
-      [&](int k0, int k1, int p, float2 v, int) {
+      buf, tw, pl, [](int, int, int) { return czero<V>(); },
+      [&](int k0, int k1, int p, V v, int) {
         int c = k0 + k1 - out_off;
         if (c < 0) c += Pz;
         const bool keep = (kx0 + p < H) & (zfl[c] != 0);   // no short-circuit: no branch per element
-        dst.st2(keep ? off2(c, zs8, p) : kNoOff, v);
+        dst.template stv<V>(keep ? offv<V>(c, zsb, p) : kNoOff, v);
       });
 }
 
 // Fixed side: z forward of A's fields, stored as w_f * scale * conj(.) in spec[f][kz][ky][kx]
 // (w_f = 2 for the cross products of the squared measure, else 1).
-template <int LC>
+template <int LC, typename V = float2>
 __global__ __launch_bounds__(kThreads) void k_zstore(
-    const float2* __restrict__ X2, float2* __restrict__ spec, int nz, int Py, int H, int Hp,
-    FftPlan pl, const float2* __restrict__ twtab, float scale, int nf) {
+    const V* __restrict__ X2, V* __restrict__ spec, int nz, int Py, int H, int Hp,
+    FftPlan pl, const V* __restrict__ twtab, scalar_t<V> scale, int nf) {
+  using S = scalar_t<V>;
   constexpr int W = kTileW;
   extern __shared__ __align__(16) unsigned char smem[];
   const int Pz = pl.L;
-  float2* tw = reinterpret_cast<float2*>(smem);
-  float2* buf = reinterpret_cast<float2*>(smem + align16(sizeof(float2) * Pz));
+  V* tw = reinterpret_cast<V*>(smem);
+  V* buf = reinterpret_cast<V*>(smem + align16(sizeof(V) * Pz));
   const int kx0 = blockIdx.x * W;
   const int ky = blockIdx.y;
   const int f = blockIdx.z;
   load_twiddles(tw, twtab, pl);
   if (LC == 0) __syncthreads();
   const long long zs = (long long)Py * Hp;
-  const float2* src = X2 + (long long)f * nz * zs + (long long)ky * Hp + kx0;
-  const float w = (nf == 6 && f >= 3 ? 2.0f : 1.0f) * scale;  // Eq. (6) cross terms x2
-  float2* dst = spec + (long long)f * Pz * zs + (long long)ky * Hp + kx0;
-  auto load = [&](int i0, int i1, int p) -> float2 {
+  const V* src = X2 + (long long)f * nz * zs + (long long)ky * Hp + kx0;
+  const S w = (nf == 6 && f >= 3 ? S(2) : S(1)) * scale;  // Eq. (6) cross terms x2
+  V* dst = spec + (long long)f * Pz * zs + (long long)ky * Hp + kx0;
+  auto load = [&](int i0, int i1, int p) -> V {
     const int i = i0 + i1;
-    return (i < nz && kx0 + p < H) ? src[(long long)i * zs + p] : make_float2(0.f, 0.f);
+    return (i < nz && kx0 + p < H) ? src[(long long)i * zs + p] : czero<V>();
   };
   if (kx0 != 0 || (ky != 0 && 2 * ky != Py)) {
-    fft_io<LC, W, kThreads, false, false, false>(buf, tw, pl, load, [&](int k0, int k1, int p, float2 v, int) {
-      if (kx0 + p < H) dst[(long long)(k0 + k1) * zs + p] = make_float2(w * v.x, -w * v.y);
+    fft_io<LC, W, kThreads, false, false, false>(buf, tw, pl, load, [&](int k0, int k1, int p, V v, int) {
+      if (kx0 + p < H) dst[(long long)(k0 + k1) * zs + p] = cplx<V>(w * v.x, -w * v.y);
     });
     return;
   }
   // tile 0 at ky = 0 or Py/2: the first pencil transforms to Z = D^ + i N^ (both Hermitian in
   // kz); store D^(kz) at kz in (0, Pz/2), N^(Pz - kz) at kz in (Pz/2, Pz), and Z at 0 and Pz/2
-  fft_io<LC, W, kThreads, false, false, true>(buf, tw, pl, load, [](int, int, int, float2, int) {});
+  fft_io<LC, W, kThreads, false, false, true>(buf, tw, pl, load, [](int, int, int, V, int) {});
   __syncthreads();
   const int hz = Pz / 2;
   for (int e = threadIdx.x; e < Pz * W; e += kThreads) {
     const int kz = e / W, p = e - kz * W;
-    float2 v = buf[e];
+    V v = buf[e];
     if (p == 0 && kz != 0 && kz != hz) {
-      const float2 m = buf[(Pz - kz) * W];
-      v = kz < hz ? make_float2(0.5f * (v.x + m.x), 0.5f * (v.y - m.y))
-                  : make_float2(0.5f * (v.y + m.y), 0.5f * (v.x - m.x));
+      const V m = buf[(Pz - kz) * W];
+      v = kz < hz ? cplx<V>(S(0.5) * (v.x + m.x), S(0.5) * (v.y - m.y))
+                  : cplx<V>(S(0.5) * (v.y + m.y), S(0.5) * (v.x - m.x));
     }
-    if (kx0 + p < H) dst[(long long)kz * zs + p] = make_float2(w * v.x, -w * v.y);
+    if (kx0 + p < H) dst[(long long)kz * zs + p] = cplx<V>(w * v.x, -w * v.y);
   }
 }
 
@@ -873,16 +905,18 @@ __global__ __launch_bounds__(kThreads) void k_sat_z(const PT* __restrict__ plane
 struct OverlapGeom {
   int nA[3];   // x, y, z
   int nB[3];
+  int lo[3];   // bounding box of A's eroded mask per axis: [1, nA - 2] without a user mask
+  int hi[3];   // (lo > hi when the mask is empty)
 };
 
-// Exact N(chi) for a fixed side whose eroded mask is the box [1, nA-2]: count the moving
-// mask over the box shifted by chi and clipped to B's grid.
+// Count of the moving mask over A's bounding box shifted by chi and clipped to B's grid: the
+// exact N(chi) when A's eroded mask is that box (no user mask: [1, nA-2]), else an upper bound.
 __device__ __forceinline__ long long box_count(const int* __restrict__ s, const OverlapGeom& g,
                                                int cx, int cy, int cz) {
   const int X = g.nB[0] + 1, Y = g.nB[1] + 1;
-  const int lx = max(1 + cx, 0), hx = min(g.nA[0] - 2 + cx, g.nB[0] - 1);
-  const int ly = max(1 + cy, 0), hy = min(g.nA[1] - 2 + cy, g.nB[1] - 1);
-  const int lz = max(1 + cz, 0), hz = min(g.nA[2] - 2 + cz, g.nB[2] - 1);
+  const int lx = max(g.lo[0] + cx, 0), hx = min(g.hi[0] + cx, g.nB[0] - 1);
+  const int ly = max(g.lo[1] + cy, 0), hy = min(g.hi[1] + cy, g.nB[1] - 1);
+  const int lz = max(g.lo[2] + cz, 0), hz = min(g.hi[2] + cz, g.nB[2] - 1);
   if (lx > hx || ly > hy || lz > hz) return 0;
   auto at = [&](int z, int y, int x) { return (long long)s[((long long)z * Y + y) * X + x]; };
   return at(hz + 1, hy + 1, hx + 1) - at(lz, hy + 1, hx + 1) - at(hz + 1, ly, hx + 1) -
@@ -916,8 +950,8 @@ __device__ __forceinline__ void bounds_row(const int* __restrict__ sat, const Ov
   const long long count_b = s[(long long)(g.nB[2] + 1) * Y * X - 1];
   const long long thr = threshold(count_a, count_b, gamma);
   const int cz = zc - (g.nA[2] - 1), cy = yc - (g.nA[1] - 1);
-  const int lz = max(1 + cz, 0), hz = min(g.nA[2] - 2 + cz, g.nB[2] - 1);
-  const int ly = max(1 + cy, 0), hy = min(g.nA[1] - 2 + cy, g.nB[1] - 1);
+  const int lz = max(g.lo[2] + cz, 0), hz = min(g.hi[2] + cz, g.nB[2] - 1);
+  const int ly = max(g.lo[1] + cy, 0), hy = min(g.hi[1] + cy, g.nB[1] - 1);
   uint8_t* f = flags + slot * flag_sstride;
   auto at = [&](int z, int y) { return (long long)s[((long long)z * Y + y) * X + (X - 1)]; };
   long long rb = 0;
@@ -967,13 +1001,16 @@ __global__ __launch_bounds__(kThreads) void k_bounds(const int* __restrict__ sat
 // builds Z straight from the two rows; the last stage normalises and reduces in registers.
 // Overlaps: for a fixed-side box, N(chi) = D(hx + 1) - D(lx) where D(x) is the 4-corner
 // combination of the SAT over the row's z and y ranges; D rows are built in LDS first.
-template <bool WRITE_MAP, int LC>
+// NCOUNT: the fixed side has a general mask, so N(chi) is read from the exact count rows that
+// k_overlap_x wrote (ncount[slot][zc][yc][cx]) instead of the SAT box sums.
+template <bool WRITE_MAP, int LC, bool NCOUNT = false>
 __global__ __launch_bounds__(kThreadsC) void k_final_x(
     const float2* __restrict__ Y4, const int* __restrict__ sat, unsigned long long* __restrict__ keys,
     OverlapGeom g, int Wx, int Wy, int Wz, int H, int Hp, FftPlan pl, const float2* __restrict__ twtab,
     long long y4_sstride, long long sat_sstride, long long count_a, double gamma,
     float* __restrict__ cmap, long long* __restrict__ nmap, const uint8_t* __restrict__ flags,
-    long long flag_sstride, const unsigned* __restrict__ work, const unsigned* __restrict__ nwork) {
+    long long flag_sstride, const unsigned* __restrict__ work, const unsigned* __restrict__ nwork,
+    const int* __restrict__ ncount, long long ncount_sstride) {
   constexpr int T = kThreadsC;
   constexpr int WP = kRowsC;  // packed pencils
   constexpr int NR = 2 * WP;  // output rows
@@ -1007,13 +1044,13 @@ __global__ __launch_bounds__(kThreadsC) void k_final_x(
   // D rows: for row rr (yc = yc0 + rr), D(x) = sum of the SAT over the row's z and y ranges
   // up to column x (x = 0 .. nB_x); empty ranges give D = 0.  Rows go to groups of DG
   // threads, columns to the threads of a group.
-  {
+  if constexpr (!NCOUNT) {
     constexpr int DG = T < 256 ? T : 256;
     constexpr int RG = T / DG;                  // row groups
     constexpr int RPT = (NR + RG - 1) / RG;     // rows per thread
     const int X = X1, Y = g.nB[1] + 1;
     const int cz = zc - (g.nA[2] - 1);
-    const int lz = max(1 + cz, 0), hz = min(g.nA[2] - 2 + cz, g.nB[2] - 1);
+    const int lz = max(g.lo[2] + cz, 0), hz = min(g.hi[2] + cz, g.nB[2] - 1);
     const RView sv(s, 4LL * (g.nB[2] + 1) * Y * X);
     const int rg = (int)threadIdx.x / DG;
     // byte offsets of the 4 SAT rows of each of this thread's rows (the SAT of one slot is
@@ -1023,7 +1060,7 @@ __global__ __launch_bounds__(kThreadsC) void k_final_x(
     for (int i = 0; i < RPT; ++i) {
       const int rr = rg + i * RG;
       const int cy = yc0 + rr - (g.nA[1] - 1);
-      const int ly = max(1 + cy, 0), hy = min(g.nA[1] - 2 + cy, g.nB[1] - 1);
+      const int ly = max(g.lo[1] + cy, 0), hy = min(g.hi[1] + cy, g.nB[1] - 1);
       // without a map, rows that hold no valid displacement (flag 0) need no counts
       const bool any = rr < NR && lz <= hz && ly <= hy && yc0 + rr < Wy && (WRITE_MAP || ((fmask >> rr) & 1u));
       o[i][0] = any ? 4u * (uint32_t)(((hz + 1) * Y + hy + 1) * X) : kNoOff;
@@ -1048,6 +1085,7 @@ __global__ __launch_bounds__(kThreadsC) void k_final_x(
   const long long count_b = s[(long long)(g.nB[2] + 1) * (g.nB[1] + 1) * (g.nB[0] + 1) - 1];
   // counts and canonical indices fit 32 bits: N <= |M_B| < 2^31, W_x W_y W_z < 2^31
   const int thr = (int)threshold(count_a, count_b, gamma);
+  const int* nrows = NCOUNT ? ncount + slot * ncount_sstride + ((long long)zc * Wy) * Wx : nullptr;
   if (LC == 0) __syncthreads();
   unsigned long long best = 0ull;
   const RView rows(Y4 + slot * y4_sstride + ((long long)zc * Wy) * Hp, 8LL * Wy * Hp);  // rows >= Wy load zero
@@ -1075,14 +1113,18 @@ __global__ __launch_bounds__(kThreadsC) void k_final_x(
     if (cx >= Px) cx -= Px;
     if (cx >= Wx) return;
     const int chx = cx - (g.nA[0] - 1);
-    const int lx = max(1 + chx, 0), hx = min(g.nA[0] - 2 + chx, g.nB[0] - 1);
+    const int lx = max(g.lo[0] + chx, 0), hx = min(g.hi[0] + chx, g.nB[0] - 1);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int rr = 2 * p + h;
       const int yc = yc0 + rr;
       if (yc >= Wy) continue;
       const float sv = h ? zv.y : zv.x;
-      const int n = (lx <= hx) ? drow[rr * X1 + hx + 1] - drow[rr * X1 + lx] : 0;
+      int n;
+      if constexpr (NCOUNT)   // rows without a flag hold no valid displacement and no counts
+        n = (WRITE_MAP || ((fmask >> rr) & 1u)) ? nrows[(long long)yc * Wx + cx] : 0;
+      else
+        n = (lx <= hx) ? drow[rr * X1 + hx + 1] - drow[rr * X1 + lx] : 0;
       const bool valid = n >= thr;
       const float c = valid ? sv / (float)n : -INFINITY;
       const unsigned int canon = (unsigned)((zc * Wy + yc) * Wx + cx);
@@ -1126,6 +1168,123 @@ __global__ __launch_bounds__(kThreadsC) void k_final_x(
   }
 }
 
+// ------------------------------------------------------------------------------ exact overlaps
+// With a general mask on the fixed side, N(chi) is the mask cross-correlation (Sec. 3.1, after
+// Eq. (5)) and no box sum gives it.  The eroded moving mask then goes through the pencil
+// passes as one more field, in FP64 (k_pencil, k_zpass and k_zstore instantiated for double2)
+// against A's FP64 mask spectrum, and the x C2R rounds each count to its integer: the FP64
+// transform error is many orders of magnitude below the 1/2 the rounding tolerates.
+
+// x R2C of the eroded mask: workgroup (row-pair group, interior slice z, slot).  Each pencil
+// packs two interior rows as re = row y, im = row y + 1; the transform (length Px, zero
+// padded) is split into the rows' half spectra with bin 0 = DC + i Nyquist and stored like
+// the product fields: X1m[(z - 1)(ny - 2) + y - 1][k], k < H.
+constexpr int kMaskPairs = 8;
+constexpr int kThreadsM = 256;
+template <int LC, bool HALF>
+__global__ __launch_bounds__(kThreadsM) void k_mask_x(const uint8_t* __restrict__ mask, int nx, int ny, int nz,
+                                                      long long mask_sstride, FftPlan pl,
+                                                      const double2* __restrict__ twtab, double2* __restrict__ out,
+                                                      int H, int Hp, long long out_sstride) {
+  constexpr int W = kMaskPairs;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int Px = pl.L;
+  double2* tw = reinterpret_cast<double2*>(smem);
+  double2* buf = reinterpret_cast<double2*>(smem + align16(sizeof(double2) * Px));
+  const int z = blockIdx.y + 1;
+  const int slot = blockIdx.z;
+  const int q0 = blockIdx.x * W;   // first row pair of this workgroup
+  const int nrow = ny - 2;         // interior rows 1 .. ny - 2
+  load_twiddles(tw, twtab, pl);
+  if (LC == 0) __syncthreads();
+  const RView m(mask + slot * mask_sstride + (long long)z * ny * nx, (long long)ny * nx);
+  auto rows = [&](int i0, int i1, int p) -> double2 {
+    const int x = i0 + i1;
+    const int r = 2 * (q0 + p);
+    const uint32_t o = (uint32_t)((1 + r) * nx + x);
+    const unsigned a = m.ld1(x < nx && r < nrow ? o : kNoOff);
+    const unsigned b = m.ld1(x < nx && r + 1 < nrow ? o + (uint32_t)nx : kNoOff);
+    return cplx<double2>(a ? 1.0 : 0.0, b ? 1.0 : 0.0);
+  };
+  fft_io<LC, W, kThreadsM, false, false, true, W, HALF>(buf, tw, pl, rows, [](int, int, int, double2, int) {});
+  __syncthreads();
+  const RView dst(out + slot * out_sstride, 16LL * (nz - 2) * nrow * Hp);
+  const uint32_t rsb = 16u * (uint32_t)Hp;
+  for (int e = threadIdx.x; e < W * H; e += kThreadsM) {
+    const int p = e / H, k = e - p * H;
+    const double2 zk = buf[k * W + p];
+    const double2 zc = buf[(k ? Px - k : Px / 2) * W + p];
+    const int r = 2 * (q0 + p);
+    const int row = (z - 1) * nrow + r;
+    const double2 fa = k ? cplx<double2>(0.5 * (zk.x + zc.x), 0.5 * (zk.y - zc.y)) : cplx<double2>(zk.x, zc.x);
+    const double2 fb = k ? cplx<double2>(0.5 * (zk.y + zc.y), 0.5 * (zc.x - zk.x)) : cplx<double2>(zk.y, zc.y);
+    dst.stv<double2>(r < nrow ? offv<double2>(row, rsb, k) : kNoOff, fa);
+    dst.stv<double2>(r + 1 < nrow ? offv<double2>(row + 1, rsb, k) : kNoOff, fb);
+  }
+}
+
+// x C2R of the count rows (FP64) and rounding: workgroup (row group, zc, slot) as in the final
+// pass, kRowsC packed row pairs Z = S1 + i S2.  Writes ncount[slot][zc][yc][cx] for the rows
+// whose flag is set (all rows when every flag is set, as for a full map).
+template <int LC>
+__global__ __launch_bounds__(kThreadsC) void k_overlap_x(const double2* __restrict__ Y4, int* __restrict__ ncount,
+                                                         int Wx, int Wy, int Wz, int H, int Hp, int x_off, FftPlan pl,
+                                                         const double2* __restrict__ twtab, long long y4_sstride,
+                                                         long long n_sstride, const uint8_t* __restrict__ flags,
+                                                         long long flag_sstride) {
+  constexpr int T = kThreadsC;
+  constexpr int WP = kRowsC;
+  constexpr int NR = 2 * WP;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int Px = pl.L;
+  double2* tw = reinterpret_cast<double2*>(smem);
+  double2* buf = reinterpret_cast<double2*>(smem + align16(sizeof(double2) * Px));
+  const int slot = blockIdx.z, zc = blockIdx.y, yc0 = blockIdx.x * NR;
+  unsigned fmask = 0;
+  {
+    const RView rf(flags + slot * flag_sstride + Wz + (long long)zc * Wy, Wy);   // rows >= Wy read 0
+    unsigned fl[NR];
+#pragma unroll
+    for (int rr = 0; rr < NR; ++rr) fl[rr] = rf.ld1((uint32_t)(yc0 + rr));
+#pragma unroll
+    for (int rr = 0; rr < NR; ++rr) fmask |= fl[rr] ? 1u << rr : 0u;
+  }
+  if (!fmask) return;
+  load_twiddles(tw, twtab, pl);
+  if (LC == 0) __syncthreads();
+  const int half = Px / 2;
+  const RView rows(Y4 + slot * y4_sstride + ((long long)zc * Wy) * Hp, 16LL * Wy * Hp);
+  const uint32_t rsb = 16u * (uint32_t)Hp;
+  // two rows' half spectra (bin 0 = DC + i Nyquist) as one Hermitian-extended spectrum
+  auto pack = [&](int k0, int k1, int p) -> double2 {
+    const int k = k0 + k1;
+    const int r0 = yc0 + 2 * p;
+    const bool lo = k < half;
+    const int kk = k == half ? 0 : lo ? k : Px - k;
+    const uint32_t o0 = offv<double2>(r0, rsb, kk);
+    const double2 a = rows.ldv<double2, false>((fmask >> (2 * p)) & 1u ? o0 : kNoOff);
+    const double2 c = rows.ldv<double2, false>((fmask >> (2 * p + 1)) & 1u ? o0 + rsb : kNoOff);
+    const double sg = lo ? 1.0 : -1.0;
+    double2 zz = cplx<double2>(fma(-sg, c.y, a.x), fma(sg, a.y, c.x));
+    zz = k == 0 ? cplx<double2>(a.x, c.x) : zz;
+    zz = k == half ? cplx<double2>(a.y, c.y) : zz;
+    return zz;
+  };
+  int* out = ncount + slot * n_sstride + ((long long)zc * Wy) * Wx;
+  auto emit = [&](int j0, int j1, int p, double2 zv, int) {
+    int cx = j0 + j1 + x_off;   // x_off = nA_x - 1 < Px
+    if (cx >= Px) cx -= Px;
+    if (cx >= Wx) return;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int rr = 2 * p + h;
+      const int yc = yc0 + rr;
+      if (yc < Wy && ((fmask >> rr) & 1u)) out[(long long)yc * Wx + cx] = (int)rint(h ? zv.y : zv.x);
+    }
+  };
+  fft_io<LC, WP, T, true, false, false>(buf, tw, pl, pack, emit);
+}
+
 // The final pass's work list: the (slot, zc, row group) items with any row flag set, packed
 // as slot << 24 | zc << 12 | group (slots < 256, Wz and the groups < 4096).  One global atomic
 // per workgroup; the order of the list is not deterministic, the results do not depend on it.
@@ -1155,7 +1314,8 @@ __global__ __launch_bounds__(kThreads) void k_worklist(const uint8_t* __restrict
 // Per-slot result from its key: score bits, canonical index -> displacement, exact N.
 __global__ void k_finalize(const unsigned long long* __restrict__ keys, const int* __restrict__ sat,
                            OverlapGeom g, int Wx, int Wy, long long sat_sstride, int nslots,
-                           RotResultDev* __restrict__ res) {
+                           RotResultDev* __restrict__ res, const int* __restrict__ ncount,
+                           long long ncount_sstride) {
   const int slot = blockIdx.x * blockDim.x + threadIdx.x;
   if (slot >= nslots) return;
   const unsigned long long key = keys[slot];
@@ -1175,7 +1335,8 @@ __global__ void k_finalize(const unsigned long long* __restrict__ keys, const in
     r.shift[0] = cx - (g.nA[0] - 1);
     r.shift[1] = cy - (g.nA[1] - 1);
     r.shift[2] = cz - (g.nA[2] - 1);
-    r.overlap = box_count(sat + slot * sat_sstride, g, r.shift[0], r.shift[1], r.shift[2]);
+    r.overlap = ncount ? (long long)ncount[slot * ncount_sstride + canon]
+                       : box_count(sat + slot * sat_sstride, g, r.shift[0], r.shift[1], r.shift[2]);
     r.valid = 1;
   }
   res[slot] = r;

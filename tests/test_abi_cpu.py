@@ -97,7 +97,6 @@ def test_create_rejects_bad_arguments_before_touching_a_device():
     p = bd.default_params()
     p.pad[0] = 26  # 2 * 13: not built
     assert _create(A, dB, params=p)[0] == bd.E_UNSUPPORTED
-    assert _create(A, dB, mask=np.ones(A.shape, np.uint8))[0] == bd.E_UNSUPPORTED
     assert _create(np.zeros((8, 8, 600), np.float32), dB)[0] == bd.E_UNSUPPORTED
 
 
@@ -120,6 +119,8 @@ def test_no_device_is_reported():
     A = np.random.default_rng(0).random((8, 8, 8)).astype(np.float32)
     rc, h = _create(A, bd.Dims(8, 8, 8))
     assert rc == bd.E_NO_DEVICE
+    # a user mask on A passes argument checking (it is supported) and then needs a device
+    assert _create(A, bd.Dims(8, 8, 8), mask=np.ones(A.shape, np.uint8))[0] == bd.E_NO_DEVICE
     assert b"device" in bd.lib().csngf_last_error()
     with pytest.raises(bd.CsngfError) as ei:
         bd.Context(A, (8, 8, 8))

@@ -149,6 +149,41 @@ def test_map_properties(full):
     assert per[MAP_ROT].score == C.flat[flat] and per[MAP_ROT].overlap == N.flat[flat]
 
 
+def _head_mask(shape, seed=17):
+    """A user mask on A for the paper-scale pair: an ellipsoid over the head region with 2% of
+    its voxels knocked out (so the eroded mask is neither a box nor convex)."""
+    nz, ny, nx = shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    r = (((z - (nz - 1) / 2) / (0.47 * nz)) ** 2 + ((y - (ny - 1) / 2) / (0.45 * ny)) ** 2
+         + ((x - (nx - 1) / 2) / (0.44 * nx)) ** 2)
+    rng = np.random.default_rng(seed)
+    return ((r <= 1.0) & (rng.random(shape) > 0.02)).astype(np.uint8)
+
+
+def test_user_mask_on_a_full_map_and_rotations_against_oracle(full):
+    """Sec. 3.1, Eq. (4)-(5) at paper scale with a user mask on A (FP64 overlap chain, automatic
+    slots, two launch sequences): the whole map of one rotation element by element (N exact,
+    validity identical, 1e-4), and 3 rotations' results against the oracle's maps."""
+    from parity_util import check_against_oracle
+    pair = full["pair"]
+    mask_a = _head_mask(pair.A.shape)
+    idx = [0, MAP_ROT, N_RANDOM]
+    with bd.Context(pair.A, pair.dims_b, pad=pair.pad, mask_a=mask_a) as ctx:
+        info = ctx.info()
+        _say("mask on A at full size: slots", info.batch, "count_a", info.count_a)
+        per, best = ctx.evaluate(pair.B, pair.rotations)
+        Cg, Ng = ctx.evaluate_map(pair.B, pair.rotations[MAP_ROT])
+    res, _ = O.evaluate(pair.A, pair.B, pair.rotations[MAP_ROT:MAP_ROT + 1], mask_a=mask_a.astype(bool),
+                        P_xyz=pair.pad, keep_maps=True)
+    _compare_maps(Cg, Ng, res[0].C, res[0].N, "config2-maskA-map")
+    sub = [per[i] for i in idx]
+    sb = bd.Best()
+    k = max(range(len(idx)), key=lambda j: (sub[j].valid, sub[j].score, -j))
+    sb.rot_index, sb.score = k, sub[k].score
+    sb.shift[:] = list(sub[k].shift)
+    check_against_oracle(pair.A, pair.B, pair.rotations[idx], sub, sb, P=pair.pad, mask_a=mask_a.astype(bool))
+
+
 @pytest.mark.parametrize("r", [0, N_RANDOM])
 def test_per_rotation_results_against_oracle(full, r):
     """Whole-map oracle (FP64 FFT route) for single rotations of the batch, including the

@@ -30,10 +30,10 @@ def _rand_rot(rng, max_deg=40.0):
     return synth.axis_angle_matrix(rng.normal(size=3), math.radians(rng.uniform(0, max_deg)))
 
 
-def _oracle_maps(A, B, R, mask_b=None, gamma=0.5, P=None):
-    fa = O.fixed_fields(A)
+def _oracle_maps(A, B, R, mask_b=None, gamma=0.5, P=None, mask_a=None, measure="squared"):
+    fa = O.fixed_fields(A, mask_a)
     fb = O.moving_fields(B, O.quantize_rotation(R), mask_b)
-    S, N = O.correlation_maps_fft(fa, fb, P)
+    S, N = O.correlation_maps_fft(fa, fb, P, measure=measure)
     C, valid = O.normalise(S, N, int(fa.mask.sum()), int(fb.mask.sum()), gamma)
     return C, N, valid
 
@@ -99,20 +99,21 @@ def _field_bound(vol, n_oracle_g, eps):
     return 1e-6 + 16 * 2.0 ** -24 * scale / np.sqrt(n_oracle_g + eps * eps)
 
 
-@pytest.mark.parametrize("which", ["fixed", "identity", "rotated", "masked"])
+@pytest.mark.parametrize("which", ["fixed", "fixed-masked", "identity", "rotated", "masked"])
 def test_field_stage_against_oracle(which):
     rng = np.random.default_rng(2)
     pair = synth.config0()
     eps = 1e-5
-    vol = pair.A if which == "fixed" else pair.B
-    R = None if which == "fixed" else (np.eye(3) if which == "identity" else _rand_rot(rng, 50))
+    fixed = which.startswith("fixed")
+    vol = pair.A if fixed else pair.B
+    R = None if fixed else (np.eye(3) if which == "identity" else _rand_rot(rng, 50))
     mask = None
-    if which == "masked":
+    if which in ("masked", "fixed-masked"):
         mask = (rng.random(vol.shape) > 0.02).astype(np.uint8)
     _say("fields", which)
     prod, m = bd.debug_fields(vol, R=R, mask=mask, eps=eps)
     if R is None:
-        f = O.fixed_fields(vol, None, eps)
+        f = O.fixed_fields(vol, None if mask is None else mask.astype(bool), eps)
         g = O.gradient(vol)
     else:
         Rq = O.quantize_rotation(R)
@@ -192,6 +193,88 @@ def test_large_xy_extent_full_maps():
         Cg, Ng = ctx.evaluate_map(B, R)
     Co, No, _ = _oracle_maps(A, B, R, None, 0.5, P)
     _compare_maps(Cg, Ng, Co, No, "large-xy")
+
+
+def _mask_of_a(rng, shape, kind):
+    """A user mask on the fixed volume (Sec. 3.1: masks select sub-regions)."""
+    nz, ny, nx = shape
+    if kind == "random":
+        return (rng.random(shape) > 0.1).astype(np.uint8)
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    c = [(n - 1) / 2 for n in shape]
+    r = ((z - c[0]) / (0.5 * nz)) ** 2 + ((y - c[1]) / (0.5 * ny)) ** 2 + ((x - c[2]) / (0.45 * nx)) ** 2
+    m = r <= 1.0
+    if kind == "ellipsoid-holes":
+        m &= rng.random(shape) > 0.05
+    if kind == "two-blocks":   # a mask in two separate pieces, so its bounding box is not its shape
+        m = np.zeros(shape, bool)
+        m[:, : ny // 2, : nx // 2] = True
+        m[nz // 3:, ny // 2 + 1:, nx // 2 + 1:] = True
+    return m.astype(np.uint8)
+
+
+@pytest.mark.parametrize("case", range(7))
+def test_user_mask_on_fixed_volume_full_maps(case):
+    """Sec. 3.1, Eq. (4)-(5) with a user mask on A: N(chi) is then the mask cross-correlation,
+    computed by the FP64 overlap chain and rounded.  N exact, validity identical, |dC| <= 1e-4,
+    over whole maps: random, ellipsoidal, holed and two-piece masks, masks on both volumes,
+    gamma 0.25 / 0.5 / 0.3, the unsquared measure, explicit padding, n_A != n_B."""
+    rng = np.random.default_rng(300 + case)
+    from scipy.ndimage import gaussian_filter
+    sa = tuple(int(v) for v in rng.integers(6, 23, size=3))
+    sb = tuple(int(v) for v in rng.integers(6, 23, size=3))
+    A = gaussian_filter(rng.random(sa), 1.0).astype(np.float32)
+    B = gaussian_filter(rng.random(sb), 1.0).astype(np.float32)
+    kind = ("random", "ellipsoid", "ellipsoid-holes", "two-blocks", "random", "ellipsoid-holes", "random")[case]
+    mask_a = _mask_of_a(rng, sa, kind)
+    mask_b = (rng.random(sb) > 0.03).astype(np.uint8) if case in (3, 5) else None
+    gamma = (0.5, 0.25, 0.5, 0.3, 0.25, 0.25, 0.5)[case]
+    measure = "unsquared" if case == 4 else "squared"
+    R = np.eye(3) if case == 0 else _rand_rot(rng, 60)
+    pad = (0, 0, 0)
+    if case == 6:  # explicit padding above n_A + n_B - 1
+        need = [sa[2] + sb[2] - 1, sa[1] + sb[1] - 1, sa[0] + sb[0] - 1]
+        pad = tuple(next(L for L in range(n + 5, 513) if bd.supported_length(L)) for n in need)
+    _say("mask on A", case, kind, sa, sb, gamma, measure, mask_b is not None)
+    with bd.Context(A, bd.dims_of(B), mask_a=mask_a, gamma=gamma, pad=pad, measure=measure) as ctx:
+        P = tuple(ctx.info().pad)
+        assert ctx.info().count_a == int(O.fixed_fields(A, mask_a.astype(bool)).mask.sum())
+        Cg, Ng = ctx.evaluate_map(B, R, mask_b=mask_b)
+        per, best = ctx.evaluate(B, np.stack([R, np.eye(3)]), mask_b=mask_b)
+    Co, No, _ = _oracle_maps(A, B, R, None if mask_b is None else mask_b.astype(bool), gamma, P,
+                             mask_a=mask_a.astype(bool), measure=measure)
+    _compare_maps(Cg, Ng, Co, No, f"maskA{case}")
+    if np.isfinite(Cg).any():
+        flat = int(np.argmax(np.where(np.isfinite(Cg), Cg, -np.inf)))
+        iz, iy, ix = np.unravel_index(flat, Cg.shape)
+        assert tuple(per[0].shift) == (ix - (sa[2] - 1), iy - (sa[1] - 1), iz - (sa[0] - 1))
+        assert per[0].score == Cg.flat[flat] and per[0].overlap == Ng.flat[flat]
+
+
+def test_all_ones_mask_on_a_equals_no_mask_and_empty_mask_has_no_shift():
+    """A mask of ones erodes to the same box as no mask: the FP64 overlap chain must give the
+    SAT box sums' counts, so maps and results are bit-identical.  An empty mask leaves no
+    valid displacement."""
+    pair = synth.config0()
+    rng = np.random.default_rng(8)
+    rots = np.stack([np.eye(3), _rand_rot(rng, 40), _rand_rot(rng, 40)])
+    with bd.Context(pair.A, pair.dims_b) as c0, \
+            bd.Context(pair.A, pair.dims_b, mask_a=np.ones(pair.A.shape, np.uint8)) as c1:
+        assert c0.info().count_a == c1.info().count_a
+        p0, b0 = c0.evaluate(pair.B, rots)
+        p1, b1 = c1.evaluate(pair.B, rots)
+        C0, N0 = c0.evaluate_map(pair.B, rots[1])
+        C1, N1 = c1.evaluate_map(pair.B, rots[1])
+    assert np.array_equal(N0, N1) and np.array_equal(C0, C1)
+    for a, b in zip(p0, p1):
+        assert a.score == b.score and tuple(a.shift) == tuple(b.shift) and a.overlap == b.overlap
+    assert b0.rot_index == b1.rot_index == 0
+    with bd.Context(pair.A, pair.dims_b, mask_a=np.zeros(pair.A.shape, np.uint8)) as ce:
+        assert ce.info().count_a == 0
+        per, best = ce.evaluate(pair.B, rots)
+        Ce, Ne = ce.evaluate_map(pair.B, rots[0])
+    assert best.rot_index == -1 and not any(p.valid for p in per)
+    assert not np.isfinite(Ce).any() and not Ne.any()
 
 
 @pytest.mark.parametrize("seed", [107, 115, 119])

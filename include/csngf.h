@@ -66,6 +66,16 @@ extern "C" {
  * ignored while profiling is enabled).  Results are identical to the eager launches. */
 #define CSNGF_GRAPHS 4u
 
+/* params.flags: correlate the product fields in FP64 instead of FP32.  The NGF and its products
+ * are the same FP32 values; the zero-padded transforms, the frequency-domain sum against A's
+ * (then FP64) spectra and the inverse run in double precision, so the error of S(chi) is the
+ * FP32 rounding of the products alone.  The FP32 path's S carries an absolute transform error
+ * that grows with the fields' total energy (about 1e-4 on ~20^3 volumes): C = S / N meets
+ * 1e-4 wherever the minimum overlap keeps N large (gamma = 0.5: N is half a mask), but not at
+ * overlaps of a few voxels, which only gamma near 0 admits.  Use this flag there.  It moves
+ * twice the bytes and runs the transforms at the FP64 rate. */
+#define CSNGF_FP64 8u
+
 typedef struct csngf_ctx csngf_ctx;
 
 typedef struct {
@@ -83,7 +93,7 @@ typedef struct {
                            >= n_A + n_B - 1, or the smallest one with a compile-time plan when
                            that is at most 1.5x as long (see csngf_footprint for the result) */
   int32_t batch;        /* rotations in flight per launch sequence, 0 .. 255; 0 = automatic */
-  uint32_t flags;       /* CSNGF_DEVICE_PTRS | CSNGF_UNSQUARED | CSNGF_GRAPHS */
+  uint32_t flags;       /* CSNGF_DEVICE_PTRS | CSNGF_UNSQUARED | CSNGF_GRAPHS | CSNGF_FP64 */
 } csngf_params;
 
 typedef struct {
@@ -146,9 +156,12 @@ int csngf_set_stream(csngf_ctx* ctx, void* hip_stream);
 int csngf_get_info(const csngf_ctx* ctx, csngf_info* out);
 
 /* Score n rotations (R: n x 9 row-major doubles, host) of moving volume B (dims dB of the
- * context; maskB NULL = full domain).  per_rot (host, n entries) may be NULL; best (host)
- * may be NULL.  Returns CSNGF_E_NO_VALID_SHIFT when no rotation has a valid displacement
- * (per_rot still filled).  n == 0 is valid: best->rot_index = -1. */
+ * context; maskB NULL = full domain): for each rotation, B resampled under it (Sec. 3.2),
+ * C(chi) of Sec. 3.1, Eq. (5) at every displacement chi via Eq. (6)-(8), and the argmax over
+ * the chi that meet the minimum overlap (Sec. 3.2); best = the largest over rotations, the
+ * alignment of Sec. 3.2.  per_rot (host, n entries) may be NULL; best (host) may be NULL.
+ * Returns CSNGF_E_NO_VALID_SHIFT when no rotation has a valid displacement (per_rot still
+ * filled).  n == 0 is valid: best->rot_index = -1. */
 int csngf_evaluate(csngf_ctx* ctx, const float* B, const uint8_t* maskB, const double* R,
                    int32_t n, csngf_rot_result* per_rot, csngf_best* best);
 
@@ -165,9 +178,10 @@ int csngf_query(csngf_ctx* ctx);
  * (per_rot: n entries or NULL; best or NULL).  CSNGF_E_INVALID_ARG when none is in flight. */
 int csngf_wait(csngf_ctx* ctx, csngf_rot_result* per_rot, csngf_best* best);
 
-/* Full maps for one rotation (diagnosis and parity): C[Wz][Wy][Wx] float32 with -inf where
- * chi is invalid, and optionally N[Wz][Wy][Wx] int64 (may be NULL).  Index i = chi + n_A - 1
- * per axis.  Host or device pointers per params.flags. */
+/* Full maps for one rotation (diagnosis and parity): C(chi) of Sec. 3.1, Eq. (5) as
+ * C[Wz][Wy][Wx] float32 with -inf where chi misses the minimum overlap of Sec. 3.2, and
+ * optionally the overlap counts N(chi) (Sec. 3.1, after Eq. (5)) as N[Wz][Wy][Wx] int64 (may be
+ * NULL).  Index i = chi + n_A - 1 per axis.  Host or device pointers per params.flags. */
 int csngf_evaluate_map(csngf_ctx* ctx, const float* B, const uint8_t* maskB, const double* R9,
                        float* C, int64_t* N);
 

@@ -24,6 +24,7 @@ E_NO_VALID_SHIFT = -6
 DEVICE_PTRS = 1
 UNSQUARED = 2
 GRAPHS = 4
+FP64 = 8
 
 _NAMES = {0: "OK", -1: "E_INVALID_ARG", -2: "E_UNSUPPORTED", -3: "E_NO_DEVICE", -4: "E_OUT_OF_MEMORY",
           -5: "E_DEVICE", -6: "E_NO_VALID_SHIFT"}
@@ -153,9 +154,10 @@ class Context:
     """Owns a csngf_ctx: A's resident spectra and the rotation workspaces."""
 
     def __init__(self, A, dims_b, *, mask_a=None, eps=1e-5, gamma=0.5, pad=(0, 0, 0), batch=0, stream=None,
-                 measure="squared", graphs=False):
+                 measure="squared", graphs=False, fp64=False):
         """measure: "squared" (Eq. (2), CSNGF) or "unsquared" (Eq. (3), USNGF); graphs: replay
-        each full batch from a recorded HIP graph."""
+        each full batch from a recorded HIP graph; fp64: correlate in double precision
+        (CSNGF_FP64)."""
         if measure not in ("squared", "unsquared"):
             raise ValueError(f"unknown measure {measure!r}")
         self.device = _is_device(A)
@@ -169,7 +171,7 @@ class Context:
         p.pad[:] = list(pad)
         p.batch = batch
         p.flags = ((DEVICE_PTRS if self.device else 0) | (UNSQUARED if measure == "unsquared" else 0)
-                   | (GRAPHS if graphs else 0))
+                   | (GRAPHS if graphs else 0) | (FP64 if fp64 else 0))
         h = C.c_void_p()
         if isinstance(dims_b, tuple):
             dims_b = Dims(*dims_b)

@@ -118,9 +118,9 @@ size_t a16(size_t b) { return (b + 15) & ~size_t(15); }
 
 // twiddles, transform rows, ring of 3 halo planes, NGF of one slice (+ Px floats of padding
 // for the producer's reads past the last row)
-size_t lds_fields(int Px, int nx) {
-  return a16(sizeof(float2) * Px) + a16(sizeof(float2) * Px * (kRowsX + 1)) + a16(sizeof(float) * 3 * (kRowsX + 2) * nx) +
-         a16(sizeof(float) * (3 * kRowsX * nx + Px));
+size_t lds_fields(int Px, int nx, size_t el = sizeof(float2)) {
+  return a16(el * Px) + a16(el * Px * (kRowsX + 1)) + a16(sizeof(float) * 3 * (kRowsX + 2) * nx) +
+         a16(sizeof(float) * (3 * kRowsX * ng_stride(nx) + Px));
 }
 
 // slices per field-stage workgroup (z march); each new slice costs one resampled halo plane
@@ -129,8 +129,8 @@ size_t lds_fields(int Px, int nx) {
 #endif
 constexpr int kSlicesX = CSNGF_SLICES;
 size_t lds_pencil(int L, int W = kTileW, size_t el = sizeof(float2)) { return a16(el * L) + a16(el * L * W); }
-size_t lds_final(int Px, int nxB) {
-  return a16(sizeof(float2) * Px) + a16(sizeof(float2) * Px * (kRowsC + 1)) + a16(sizeof(int) * 2 * kRowsC * (nxB + 1));
+size_t lds_final(int Px, int nxB, size_t el = sizeof(float2)) {
+  return a16(el * Px) + a16(el * Px * (kRowsC + 1)) + a16(sizeof(int) * 2 * kRowsC * (nxB + 1));
 }
 
 // Call fn with std::integral_constant<int, L> for lengths that have a compile-time instance
@@ -263,6 +263,8 @@ struct csngf_ctx {
   // a user mask on A: its eroded mask's bounding box (without one: [1, n_A - 2]), and the
   // FP64 chain that counts overlaps exactly
   bool masked = false;
+  // CSNGF_FP64: the product fields are correlated in FP64 (buffers and spectra hold double2)
+  bool fp64 = false;
   int lo[3] = {1, 1, 1}, hi[3] = {0, 0, 0};
   double2* d_twd = nullptr;     // FP64 twiddles, same offsets as d_tw
   double2* d_mspec = nullptr;   // conj of A's mask spectrum / (Px Py Pz), [Pz][Py][Hp]
@@ -480,33 +482,51 @@ int launch_zpass(csngf_ctx* c, const V* X2, const V* spec, V* Y3, int nf, long l
   return CSNGF_OK;
 }
 
+// Field stage of `slots` volumes: FP32 NGF and products, x transform in V (float2, or double2
+// for CSNGF_FP64); dbg (FP32 only) also copies the products out.
+template <typename V>
 int launch_fields(csngf_ctx* c, bool moving, const float* vol, const uint8_t* um, const int* n3, const int* rotq,
-                  float2* out, long long out_slot, uint8_t* mask_out, long long mask_slot, float* dbg, int slots) {
+                  V* out, long long out_slot, uint8_t* mask_out, long long mask_slot, float* dbg, int slots) {
   const int tz = kSlicesX;
   const int nreal = (n3[1] + kRowsX - 1) / kRowsX * ((n3[2] + tz - 1) / tz) * slots;
   const dim3 grid((nreal + 7) / 8 * 8);
-  const size_t lds = lds_fields(c->plx.L, n3[0]);
+  const size_t lds = lds_fields(c->plx.L, n3[0], sizeof(V));
   if (lds > kLdsMax) return fail(CSNGF_E_UNSUPPORTED, "x extent too large for the field stage");
   hipError_t ae = hipSuccess;
   hipEvent_t ev = prof_begin(c);
   // inputs x >= Px/2 are zero when nx <= Px/2: the transform's first stage is pruned
   const bool half = 2 * n3[0] <= c->plx.L;
-  with_len(c->plx.L, [&](auto lc) {
-    constexpr int LC = decltype(lc)::value;
-    auto go = [&](auto kern) {
-      ae = allow_lds(kern, lds);
-      if (ae == hipSuccess)
-        hipLaunchKernelGGL(kern, grid, dim3(kThreadsF), lds, c->stream, vol, um, n3[0], n3[1], n3[2], tz, slots, c->nf,
-                           rotq, c->eps, c->plx, c->d_tw, out, c->H, c->Hp, out_slot, mask_out, mask_slot, dbg);
-    };
-    if (moving) {
-      if (half) go(k_fields_x<true, LC, true>);
-      else go(k_fields_x<true, LC, false>);
-    } else {
-      if (half) go(k_fields_x<false, LC, true>);
-      else go(k_fields_x<false, LC, false>);
+  auto go = [&](auto kern) {
+    ae = allow_lds(kern, lds);
+    if (ae == hipSuccess)
+      hipLaunchKernelGGL(kern, grid, dim3(kThreadsF), lds, c->stream, vol, um, n3[0], n3[1], n3[2], tz, slots, c->nf,
+                         rotq, c->eps, c->plx, twiddle_table<V>(c), out, c->H, c->Hp, out_slot, mask_out, mask_slot, dbg);
+  };
+  bool done = false;
+  if constexpr (std::is_same<V, float2>::value) {
+    if (dbg) {   // the debug copy of the products: the run-time-plan instance
+      if (moving) {
+        if (half) go(k_fields_x<true, 0, true, true>);
+        else go(k_fields_x<true, 0, false, true>);
+      } else {
+        if (half) go(k_fields_x<false, 0, true, true>);
+        else go(k_fields_x<false, 0, false, true>);
+      }
+      done = true;
     }
-  });
+  }
+  if (!done) {
+    with_len(c->plx.L, [&](auto lc) {
+      constexpr int LC = decltype(lc)::value;
+      if (moving) {
+        if (half) go(k_fields_x<true, LC, true, false, V>);
+        else go(k_fields_x<true, LC, false, false, V>);
+      } else {
+        if (half) go(k_fields_x<false, LC, true, false, V>);
+        else go(k_fields_x<false, LC, false, false, V>);
+      }
+    });
+  }
   prof_end(c, KT_FIELDS, ev);
   if (ae != hipSuccess) return hip_fail(ae, "hipFuncSetAttribute(k_fields_x)");
   LAUNCHCHK("k_fields_x");
@@ -663,12 +683,16 @@ int fixed_mask_spectrum(csngf_ctx* c, const uint8_t* meff, const int* nA) {
 }
 
 // One launch sequence over `slots` rotations whose Q16 tables start at rotq (device).
-int run_batch(csngf_ctx* c, const float* dB, const uint8_t* dmB, const int* rotq, int slots, RotResultDev* res,
-              float* cmap, long long* nmap) {
+template <typename V>
+int run_batch_t(csngf_ctx* c, const float* dB, const uint8_t* dmB, const int* rotq, int slots, RotResultDev* res,
+                float* cmap, long long* nmap) {
   int rc;
   hipEvent_t ev;
+  V* buf1 = reinterpret_cast<V*>(c->d_buf1);
+  V* buf2 = reinterpret_cast<V*>(c->d_buf2);
+  const V* spec = reinterpret_cast<const V*>(c->d_spec);
   // (the per-slot argmax keys are cleared by k_bounds on the side stream, before the join)
-  rc = launch_fields(c, true, dB, dmB, c->nB, rotq, c->d_buf1, c->buf1_slot, c->d_mask, c->mask_slot, nullptr, slots);
+  rc = launch_fields(c, true, dB, dmB, c->nB, rotq, buf1, c->buf1_slot, c->d_mask, c->mask_slot, nullptr, slots);
   if (rc) return rc;
   // overlap table on the side stream, concurrent with the y forward pass
   HIPCHK(hipEventRecord(c->ev_fork, c->stream));
@@ -706,7 +730,7 @@ int run_batch(csngf_ctx* c, const float* dB, const uint8_t* dmB, const int* rotq
   }
   // y forward: X1 [slot][f][z][y] -> X2 [slot][f][z][ky]
   // (X1 holds the interior rows and slices only: the fields vanish on the border planes)
-  rc = launch_pencil(c, false, c->d_buf1, c->d_buf2, c->nB[1] - 2, c->P[1], 0, c->ply,
+  rc = launch_pencil(c, false, buf1, buf2, c->nB[1] - 2, c->P[1], 0, c->ply,
                      (long long)(c->nB[1] - 2) * c->Hp, (long long)c->P[1] * c->Hp, c->nf * (c->nB[2] - 2),
                      c->buf1_slot, c->buf2_slot, slots);
   if (rc) return rc;
@@ -718,13 +742,12 @@ int run_batch(csngf_ctx* c, const float* dB, const uint8_t* dmB, const int* rotq
   HIPCHK(hipStreamWaitEvent(c->stream, c->ev_join, 0));
   // the packed DC/Nyquist tiles (tile 0 at ky = 0 and Py/2) on the side stream, all other
   // tiles here
-  rc = launch_zpass(c, c->d_buf2, c->d_spec, c->d_buf1, c->nf, c->buf2_slot, c->buf1_slot, c->d_flags, c->flag_slot,
-                    slots, c->side);
+  rc = launch_zpass(c, buf2, spec, buf1, c->nf, c->buf2_slot, c->buf1_slot, c->d_flags, c->flag_slot, slots, c->side);
   if (rc) return rc;
   HIPCHK(hipEventRecord(c->ev_zpack, c->side));
   HIPCHK(hipStreamWaitEvent(c->stream, c->ev_zpack, 0));
   // y inverse: Y3 [slot][zc][ky] -> Y4 [slot][zc][yc]
-  rc = launch_pencil(c, true, c->d_buf1, c->d_buf2, c->P[1], c->Wd[1], c->P[1] - (c->nA[1] - 1), c->ply,
+  rc = launch_pencil(c, true, buf1, buf2, c->P[1], c->Wd[1], c->P[1] - (c->nA[1] - 1), c->ply,
                      (long long)c->P[1] * c->Hp, (long long)c->Wd[1] * c->Hp, c->Wd[2], c->buf1_slot, c->buf2_slot,
                      slots, c->d_flags, c->flag_slot);
   if (rc) return rc;
@@ -740,7 +763,7 @@ int run_batch(csngf_ctx* c, const float* dB, const uint8_t* dmB, const int* rotq
     // displacement (most do not at gamma = 0.5)
     const int items = (int)(grid.x * grid.y * grid.z);
     const dim3 lgrid(std::min(items, 8192));   // 8192 measured best of 1024 .. 16384
-    const size_t lds = lds_final(c->plx.L, c->nB[0]);
+    const size_t lds = lds_final(c->plx.L, c->nB[0], sizeof(V));
     hipError_t ae = hipSuccess;
     ev = prof_begin(c);
     with_len(c->plx.L, [&](auto lc) {
@@ -748,15 +771,16 @@ int run_batch(csngf_ctx* c, const float* dB, const uint8_t* dmB, const int* rotq
       auto go = [&](auto kern, dim3 gr, const unsigned* work, const unsigned* nwork) {
         ae = allow_lds(kern, lds);
         if (ae == hipSuccess)
-          hipLaunchKernelGGL(kern, gr, dim3(kThreadsC), lds, c->stream, c->d_buf2, c->d_sat, c->d_keys, g, c->Wd[0],
-                             c->Wd[1], c->Wd[2], c->H, c->Hp, c->plx, c->d_tw, c->buf2_slot, c->sat_slot, c->count_a,
-                             c->gamma, cmap, nmap, c->d_flags, c->flag_slot, work, nwork, ncount, c->ncount_slot);
+          hipLaunchKernelGGL(kern, gr, dim3(kThreadsC), lds, c->stream, buf2, c->d_sat, c->d_keys, g, c->Wd[0],
+                             c->Wd[1], c->Wd[2], c->H, c->Hp, c->plx, twiddle_table<V>(c), c->buf2_slot, c->sat_slot,
+                             c->count_a, c->gamma, cmap, nmap, c->d_flags, c->flag_slot, work, nwork, ncount,
+                             c->ncount_slot);
       };
       // with a map every row group gets a workgroup; without, a fixed grid walks the work list
-      if (cmap && ncount) go(k_final_x<true, LC, true>, grid, nullptr, nullptr);
-      else if (cmap) go(k_final_x<true, LC, false>, grid, nullptr, nullptr);
-      else if (ncount) go(k_final_x<false, LC, true>, lgrid, c->d_work + 64, c->d_work);
-      else go(k_final_x<false, LC, false>, lgrid, c->d_work + 64, c->d_work);
+      if (cmap && ncount) go(k_final_x<true, LC, true, V>, grid, nullptr, nullptr);
+      else if (cmap) go(k_final_x<true, LC, false, V>, grid, nullptr, nullptr);
+      else if (ncount) go(k_final_x<false, LC, true, V>, lgrid, c->d_work + 64, c->d_work);
+      else go(k_final_x<false, LC, false, V>, lgrid, c->d_work + 64, c->d_work);
     });
     if (ae != hipSuccess) return hip_fail(ae, "hipFuncSetAttribute(k_final_x)");
     prof_end(c, KT_FINAL, ev);
@@ -768,6 +792,50 @@ int run_batch(csngf_ctx* c, const float* dB, const uint8_t* dmB, const int* rotq
     LAUNCHCHK("k_finalize");
   }
   return CSNGF_OK;
+}
+
+// A's side: fields (with its eroded mask written to meff when given), y forward, z forward
+// stored as w_f conj(.) / (Px Py Pz) in d_spec, in the context's precision V.
+template <typename V>
+int fixed_spectra(csngf_ctx* c, const float* dA, const uint8_t* dmA, const int* nA, uint8_t* meff) {
+  using S = scalar_t<V>;
+  const int* P = c->P;
+  const long long Hp = c->Hp;
+  V *x1 = nullptr, *x2 = nullptr;
+  const long long x1e = (long long)c->nf * nA[2] * nA[1] * Hp, x2e = (long long)c->nf * nA[2] * P[1] * Hp;
+  int rc = dalloc(&x1, sizeof(V) * x1e);
+  if (!rc) rc = dalloc(&x2, sizeof(V) * x2e);
+  if (!rc) rc = launch_fields(c, false, dA, dmA, nA, nullptr, x1, 0, meff, 0, nullptr, 1);
+  if (!rc)
+    rc = launch_pencil(c, false, x1, x2, nA[1] - 2, P[1], 0, c->ply, (long long)(nA[1] - 2) * Hp, (long long)P[1] * Hp,
+                       c->nf * (nA[2] - 2), 0, 0, 1);
+  if (!rc) {
+    const S scale = (S)(1.0 / ((double)P[0] * (double)P[1] * (double)P[2]));
+    const dim3 grid(c->tiles, P[1], c->nf);
+    const size_t lds = lds_pencil(P[2], kTileW, sizeof(V));
+    hipError_t ae = hipSuccess;
+    with_len(P[2], [&](auto lc) {
+      constexpr int LC = decltype(lc)::value;
+      ae = allow_lds(k_zstore<LC, V>, lds);
+      if (ae == hipSuccess)
+        hipLaunchKernelGGL((k_zstore<LC, V>), grid, dim3(kThreads), lds, c->stream, x2, reinterpret_cast<V*>(c->d_spec),
+                           nA[2] - 2, P[1], c->H, c->Hp, c->plz, twiddle_table<V>(c), scale, c->nf);
+    });
+    const hipError_t e = ae != hipSuccess ? ae : hipGetLastError();
+    if (e != hipSuccess) rc = hip_fail(e, "k_zstore");
+  }
+  const hipError_t se = hipStreamSynchronize(c->stream);
+  if (!rc && se != hipSuccess) rc = hip_fail(se, "fixed-side precompute");
+  if (x1) hipFree(x1);
+  if (x2) hipFree(x2);
+  return rc;
+}
+
+// One launch sequence in the context's precision.
+int run_batch(csngf_ctx* c, const float* dB, const uint8_t* dmB, const int* rotq, int slots, RotResultDev* res,
+              float* cmap, long long* nmap) {
+  return c->fp64 ? run_batch_t<double2>(c, dB, dmB, rotq, slots, res, cmap, nmap)
+                 : run_batch_t<float2>(c, dB, dmB, rotq, slots, res, cmap, nmap);
 }
 
 // A full batch through a captured graph: the launch sequence of run_batch is recorded once
@@ -900,7 +968,7 @@ int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims
   if (!(prm.gamma >= 0.0 && prm.gamma <= 1.0)) return fail(CSNGF_E_INVALID_ARG, "gamma must lie in [0, 1]");
   if (prm.batch < 0 || prm.batch > 255)   // (the final pass's work list packs the slot in 8 bits)
     return fail(CSNGF_E_INVALID_ARG, "batch must lie in [0, 255]");
-  if (prm.flags & ~(CSNGF_DEVICE_PTRS | CSNGF_UNSQUARED | CSNGF_GRAPHS))
+  if (prm.flags & ~(CSNGF_DEVICE_PTRS | CSNGF_UNSQUARED | CSNGF_GRAPHS | CSNGF_FP64))
     return fail(CSNGF_E_INVALID_ARG, "unknown flag bits");
   const int nA[3] = {dA.nx, dA.ny, dA.nz}, nB[3] = {dB.nx, dB.ny, dB.nz};
   int P[3];
@@ -949,6 +1017,8 @@ int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims
   factor_plan(P[1], c->ply);
   factor_plan(P[2], c->plz);
   c->masked = maskA != nullptr;
+  c->fp64 = (prm.flags & CSNGF_FP64) != 0;
+  const size_t el = c->fp64 ? sizeof(double2) : sizeof(float2);   // complex element of the fields' passes
   {
     std::vector<float2> tw;
     std::vector<double2> twd;
@@ -964,7 +1034,7 @@ int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims
     if ((rc = dalloc(&c->d_tw, sizeof(float2) * tw.size()))) return bail(rc);
     if (hipMemcpy(c->d_tw, tw.data(), sizeof(float2) * tw.size(), hipMemcpyHostToDevice) != hipSuccess)
       return bail(hip_fail(hipGetLastError(), "twiddle upload"));
-    if (c->masked) {   // same offsets as the FP32 table
+    if (c->masked || c->fp64) {   // same offsets as the FP32 table
       if ((rc = dalloc(&c->d_twd, sizeof(double2) * twd.size()))) return bail(rc);
       if (hipMemcpy(c->d_twd, twd.data(), sizeof(double2) * twd.size(), hipMemcpyHostToDevice) != hipSuccess)
         return bail(hip_fail(hipGetLastError(), "twiddle upload"));
@@ -978,7 +1048,7 @@ int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims
     c->lo[i] = 1;
     c->hi[i] = nA[i] - 2;
   }
-  c->spec_bytes = (long long)sizeof(float2) * c->nf * P[2] * P[1] * Hp;
+  c->spec_bytes = (long long)el * c->nf * P[2] * P[1] * Hp;
   if ((rc = dalloc(&c->d_spec, (size_t)c->spec_bytes))) return bail(rc);
   if ((rc = dalloc(&c->d_flag, sizeof(int)))) return bail(rc);
 
@@ -994,13 +1064,9 @@ int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims
       }
       dA_ptr = tmpA;
     }
-    float2 *x1 = nullptr, *x2 = nullptr;
     uint8_t *um = nullptr, *meff = nullptr;   // user mask on the device, A's eroded mask
     const uint8_t* dmA = maskA;
-    const long long x1e = (long long)c->nf * nA[2] * nA[1] * Hp, x2e = (long long)c->nf * nA[2] * P[1] * Hp;
-    rc = dalloc(&x1, sizeof(float2) * x1e);
-    if (!rc) rc = dalloc(&x2, sizeof(float2) * x2e);
-    if (!rc && c->masked) {
+    if (c->masked) {
       rc = dalloc(&meff, nvA);
       if (!rc && !(prm.flags & CSNGF_DEVICE_PTRS)) {
         rc = dalloc(&um, nvA);
@@ -1013,30 +1079,11 @@ int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims
       HIPCHK(hipMemsetAsync(c->d_flag, 0, sizeof(int), c->stream));
       hipLaunchKernelGGL(k_check_finite, dim3(1024), dim3(256), 0, c->stream, A, (long long)nvA, c->d_flag);
     }
-    if (!rc) rc = launch_fields(c, false, dA_ptr, dmA, nA, nullptr, x1, 0, meff, 0, nullptr, 1);
     if (!rc)
-      rc = launch_pencil(c, false, x1, x2, nA[1] - 2, P[1], 0, c->ply, (long long)(nA[1] - 2) * Hp,
-                         (long long)P[1] * Hp, c->nf * (nA[2] - 2), 0, 0, 1);
-    if (!rc) {
-      const float scale = (float)(1.0 / ((double)P[0] * (double)P[1] * (double)P[2]));
-      const dim3 grid(c->tiles, P[1], c->nf);
-      const size_t lds = lds_pencil(P[2]);
-      hipError_t ae = hipSuccess;
-      with_len(P[2], [&](auto lc) {
-        constexpr int LC = decltype(lc)::value;
-        ae = allow_lds(k_zstore<LC>, lds);
-        if (ae == hipSuccess)
-          hipLaunchKernelGGL((k_zstore<LC>), grid, dim3(kThreads), lds, c->stream, x2, c->d_spec, nA[2] - 2, P[1],
-                             c->H, c->Hp, c->plz, c->d_tw, scale, c->nf);
-      });
-      hipError_t e = ae != hipSuccess ? ae : hipGetLastError();
-      if (e != hipSuccess) rc = hip_fail(e, "k_zstore");
-    }
+      rc = c->fp64 ? fixed_spectra<double2>(c, dA_ptr, dmA, nA, meff) : fixed_spectra<float2>(c, dA_ptr, dmA, nA, meff);
     if (!rc && c->masked) rc = fixed_mask_spectrum(c, meff, nA);
     hipError_t se = hipStreamSynchronize(c->stream);
     if (!rc && se != hipSuccess) rc = hip_fail(se, "fixed-side precompute");
-    if (x1) hipFree(x1);
-    if (x2) hipFree(x2);
     if (tmpA) hipFree(tmpA);
     if (um) hipFree(um);
     if (meff) hipFree(meff);
@@ -1062,7 +1109,7 @@ int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims
       c->mbuf2_slot = std::max((long long)(nB[2] - 2) * P[1], (long long)c->Wd[2] * c->Wd[1]) * Hp;
       c->ncount_slot = ((long long)c->Wd[0] * c->Wd[1] * c->Wd[2] + 63) / 64 * 64;
     }
-    const long long per = sizeof(float2) * (c->buf1_slot + c->buf2_slot) + c->mask_slot + 4 * c->sat_slot +
+    const long long per = (long long)el * (c->buf1_slot + c->buf2_slot) + c->mask_slot + 4 * c->sat_slot +
                           4 * c->plane_slot + c->flag_slot + 4 * c->work_slot +
                           (long long)sizeof(double2) * (c->mbuf1_slot + c->mbuf2_slot) + 4 * c->ncount_slot;
     int batch = prm.batch;
@@ -1073,8 +1120,8 @@ int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims
       batch = (int)std::max(1LL, std::min(64LL, budget / per));
     }
     c->batch = batch;
-    if ((rc = dalloc(&c->d_buf1, sizeof(float2) * c->buf1_slot * batch))) return bail(rc);
-    if ((rc = dalloc(&c->d_buf2, sizeof(float2) * c->buf2_slot * batch))) return bail(rc);
+    if ((rc = dalloc(&c->d_buf1, el * c->buf1_slot * batch))) return bail(rc);
+    if ((rc = dalloc(&c->d_buf2, el * c->buf2_slot * batch))) return bail(rc);
     if ((rc = dalloc(&c->d_plane, 4 * (size_t)c->plane_slot * batch))) return bail(rc);
     if ((rc = dalloc(&c->d_work, 4 * (64 + (size_t)c->work_slot * batch)))) return bail(rc);
     if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
@@ -1446,17 +1493,18 @@ extern "C" int csngf_footprint(csngf_dims dA, csngf_dims dB, const csngf_params*
     Wd[i] = need;
   }
   const int nf = (prm.flags & CSNGF_UNSQUARED) ? 3 : 6;
+  const long long el = (prm.flags & CSNGF_FP64) ? (long long)sizeof(double2) : (long long)sizeof(float2);
   const long long H = P[0] / 2, Hp = (H + kTileW - 1) / kTileW * kTileW;
   const long long nvB = (long long)nB[0] * nB[1] * nB[2];
   const long long buf1 = std::max((long long)nf * nB[2] * nB[1], (long long)Wd[2] * P[1]) * Hp;
   const long long buf2 = std::max((long long)nf * nB[2] * P[1], (long long)Wd[2] * Wd[1]) * Hp;
   const int plane_bytes = (long long)nB[0] * nB[1] < 65536 ? 2 : 4;
-  const long long per = (long long)sizeof(float2) * (buf1 + buf2) + (nvB + 255) / 256 * 256 +
+  const long long per = el * (buf1 + buf2) + (nvB + 255) / 256 * 256 +
                         4 * (((long long)(nB[0] + 1) * (nB[1] + 1) * (nB[2] + 1) + 63) / 64 * 64) +
                         4 * (((nvB * plane_bytes + 3) / 4 + 63) / 64 * 64) +
                         ((long long)Wd[2] * (1 + Wd[1]) + 255) / 256 * 256 +
                         4LL * Wd[2] * ((Wd[1] + 2 * kRowsC - 1) / (2 * kRowsC));
-  if (spectra_bytes) *spectra_bytes = (long long)sizeof(float2) * nf * P[2] * P[1] * Hp;
+  if (spectra_bytes) *spectra_bytes = el * nf * P[2] * P[1] * Hp;
   if (slot_bytes) *slot_bytes = per;
   if (pad_out)
     for (int i = 0; i < 3; ++i) pad_out[i] = P[i];

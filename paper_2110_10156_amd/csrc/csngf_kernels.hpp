@@ -205,12 +205,18 @@ __device__ __forceinline__ uint32_t offv(int row, uint32_t rsb, int col) {
 // element's source coordinate, so a plane costs 3 integer adds per sample before the gather.
 template <int LC>
 constexpr int xrow_stride() { return LC > 0 ? kRowsX + 1 : kRowsX; }
+// row stride (floats) of the field stage's NGF rows in LDS: nx rounded up to 4 mod 32
+__host__ __device__ constexpr int ng_stride(int nx) { return nx + (36 - nx % 32) % 32; }
 
-template <bool MOVING, int LC, bool HALF>
+// DBG: also copy the product fields to dbg_prod (the field-stage parity check; built only with
+// the run-time plan, LC = 0, whose fields are the same).  The hot instances then hold no global
+// stores beside their half-spectrum stores: the compiler waits for pending stores before
+// reusing their registers, which would stall the transforms.
+template <bool MOVING, int LC, bool HALF, bool DBG = false, typename V = float2>
 __global__ __launch_bounds__(kThreadsF) void k_fields_x(
     const float* __restrict__ vol, const uint8_t* __restrict__ umask, int nx, int ny, int nz, int tz, int nslots,
-    int nf, const int* __restrict__ rotq, float eps, FftPlan pl, const float2* __restrict__ twtab,
-    float2* __restrict__ out, int H, int Hp, long long out_slot_stride,
+    int nf, const int* __restrict__ rotq, float eps, FftPlan pl, const V* __restrict__ twtab,
+    V* __restrict__ out, int H, int Hp, long long out_slot_stride,
     uint8_t* __restrict__ mask_out, long long mask_slot_stride, float* __restrict__ dbg_prod) {
   constexpr int T = kThreadsF;
   constexpr int TY = kRowsX;
@@ -226,10 +232,14 @@ __global__ __launch_bounds__(kThreadsF) void k_fields_x(
   extern __shared__ __align__(16) unsigned char smem[];
   const int Px = pl.L;
   const int plane = HR * nx;
-  float2* tw = reinterpret_cast<float2*>(smem);
-  float2* buf = reinterpret_cast<float2*>(smem + align16(sizeof(float2) * Px));
-  float* val = reinterpret_cast<float*>(smem + align16(sizeof(float2) * Px) + align16(sizeof(float2) * Px * (TY + 1)));
+  using S = scalar_t<V>;
+  V* tw = reinterpret_cast<V*>(smem);
+  V* buf = reinterpret_cast<V*>(smem + align16(sizeof(V) * Px));
+  float* val = reinterpret_cast<float*>(smem + align16(sizeof(V) * Px) + align16(sizeof(V) * Px * (TY + 1)));
   float* ng = reinterpret_cast<float*>(reinterpret_cast<unsigned char*>(val) + align16(sizeof(float) * 3 * plane));
+  // NGF rows are nxs = nx padded to 4 mod 32 floats apart: the transform's producer reads 8
+  // rows x 4 columns per half wave, which then fall into 32 distinct LDS banks
+  const int nxs = ng_stride(nx);
   // XCD-aware order (hardware deals block b to XCD b % 8): each XCD walks a contiguous run
   // of (y tile, z chunk, slot) with the y tile fastest, so neighbouring tiles' source
   // footprints in B meet in the same L2.
@@ -367,7 +377,7 @@ __global__ __launch_bounds__(kThreadsF) void k_fields_x(
     bk[u] = e % H;
     br[u] = e / H;
   }
-  const uint32_t hp8 = 8u * (uint32_t)Hp;
+  const uint32_t hpb = (uint32_t)sizeof(V) * (uint32_t)Hp;
 
   // zi = -2, -1 only sample the first two halo planes (z0 - 1, z0)
 #pragma unroll 1
@@ -423,9 +433,10 @@ __global__ __launch_bounds__(kThreadsF) void k_fields_x(
             n1 = gy * inv;
             n2 = gz * inv;
           }
-          ng[e] = n0;
-          ng[TY * nx + e] = n1;
-          ng[2 * TY * nx + e] = n2;
+          const int q = r * nxs + x;
+          ng[q] = n0;
+          ng[TY * nxs + q] = n1;
+          ng[2 * TY * nxs + q] = n2;
           if (mask_out) {
             const int yy = y0 + r;
             RView(mask_out + slot * mask_slot_stride, nv).st1(yy < ny ? (unsigned)((z * ny + yy) * nx + x) : kNoOff,
@@ -436,12 +447,13 @@ __global__ __launch_bounds__(kThreadsF) void k_fields_x(
     }
     __syncthreads();
     const bool sq = nf != 3;
-    if (dbg_prod && slot == 0) {
+    if (DBG && dbg_prod && slot == 0) {
       // debug copy of the product fields of slot 0 (same arithmetic as the transform's inputs)
       for (int e = tid; e < TY * nx; e += T) {
         const int r = e / nx, x = e - r * nx, yy = y0 + r;
         if (yy >= ny) continue;
-        const float n0 = ng[e], n1 = ng[TY * nx + e], n2 = ng[2 * TY * nx + e];
+        const int q = r * nxs + x;
+        const float n0 = ng[q], n1 = ng[TY * nxs + q], n2 = ng[2 * TY * nxs + q];
         const long vox = ((long)z * ny + yy) * nx + x;
         if (sq) {
           const float f[6] = {n0 * n0, n1 * n1, n2 * n2, n0 * n1, n0 * n2, n1 * n2};
@@ -466,27 +478,28 @@ __global__ __launch_bounds__(kThreadsF) void k_fields_x(
       //   squared:   fa = (p1 ? n2 : n0) (p0 ? n0 : n2),  fb = n1 (p0 ? n1 : p1 ? n0 : n2)
       //   unsquared: fa = (p1 ? n2 : n0),                 fb = n1 (p0 ? 1 : 0)
       const bool p0 = pair == 0, p1 = pair == 1;
-      auto products = [&](int x0, int x1, int r) -> float2 {
+      auto products = [&](int x0, int x1, int r) -> V {
         const int x = x0 + x1;
         // x >= nx reads past the row (at most Px floats past ng: the LDS layout pads it) and
         // is replaced by zero below
-        const unsigned b = opaque_base((unsigned)(r * nx + x0));
-        const float n0 = ng[b + x1], n1 = ng[TY * nx + b + x1], n2 = ng[2 * TY * nx + b + x1];
+        const unsigned b = opaque_base((unsigned)(r * nxs + x0));
+        const float n0 = ng[b + x1], n1 = ng[TY * nxs + b + x1], n2 = ng[2 * TY * nxs + b + x1];
         const float a1 = p1 ? n2 : n0;
         const float a2 = sq ? (p0 ? n0 : n2) : 1.0f;
         const float b2 = sq ? (p0 ? n1 : p1 ? n0 : n2) : (p0 ? 1.0f : 0.0f);
         const float fa = a1 * a2, fb = n1 * b2;
-        return x < nx ? make_float2(fa, fb) : make_float2(0.f, 0.f);
+        return x < nx ? cplx<V>(fa, fb) : czero<V>();
       };
-      auto none = [](int, int, int, float2, int) {};
+      auto none = [](int, int, int, V, int) {};
       fft_io<LC, TY, T, false, false, true, WS, HALF>(buf, tw, pl, products, none);
       __syncthreads();
       // split the packed transform: Fa = (Z_k + conj Z_{P-k}) / 2, Fb = -i (Z_k - conj Z_{P-k}) / 2
       // for bins 1 .. Px/2 - 1; bin 0 stores DC + i Nyquist of each field (Fa: Z_0.x + i Z_h.x,
       // Fb: Z_0.y + i Z_h.y with h = Px/2)
       const long long fbase = (long long)(nz - 2) * (ny - 2) * Hp;   // elements per field
-      const RView oa(out + slot * out_slot_stride + (2 * pair) * fbase, 8 * fbase);
-      const RView ob(out + slot * out_slot_stride + (2 * pair + 1) * fbase, 2 * pair + 1 < nf ? 8 * fbase : 0);
+      const long long fbytes = (long long)sizeof(V) * fbase;
+      const RView oa(out + slot * out_slot_stride + (2 * pair) * fbase, fbytes);
+      const RView ob(out + slot * out_slot_stride + (2 * pair + 1) * fbase, 2 * pair + 1 < nf ? fbytes : 0);
       const int row0 = (z - 1) * (ny - 2) + y0 - 1;   // X1 row of grid row y0 (interior rows)
       // predicated rather than branched, so the LDS reads of all of a thread's bins are in
       // flight together: elements past TY * H read row 0 and store nothing
@@ -496,12 +509,12 @@ __global__ __launch_bounds__(kThreadsF) void k_fields_x(
         const int e = (int)tid + u * T;
         const bool ok = e < TY * H;
         const int k = ok ? bk[u] : 0, r = ok ? br[u] : 0;
-        const float2 zk = buf[k * WS + r];
-        const float2 zc = buf[(k ? Px - k : Px / 2) * WS + r];
+        const V zk = buf[k * WS + r];
+        const V zc = buf[(k ? Px - k : Px / 2) * WS + r];
         const int yy = y0 + r;
-        const uint32_t off = ok && yy >= 1 && yy <= ny - 2 ? off2(row0 + r, hp8, k) : kNoOff;
-        oa.st2(off, k ? make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y - zc.y)) : make_float2(zk.x, zc.x));
-        ob.st2(off, k ? make_float2(0.5f * (zk.y + zc.y), 0.5f * (zc.x - zk.x)) : make_float2(zk.y, zc.y));
+        const uint32_t off = ok && yy >= 1 && yy <= ny - 2 ? offv<V>(row0 + r, hpb, k) : kNoOff;
+        oa.template stv<V>(off, k ? cplx<V>(S(0.5) * (zk.x + zc.x), S(0.5) * (zk.y - zc.y)) : cplx<V>(zk.x, zc.x));
+        ob.template stv<V>(off, k ? cplx<V>(S(0.5) * (zk.y + zc.y), S(0.5) * (zc.x - zk.x)) : cplx<V>(zk.y, zc.y));
       }
       __syncthreads();
     }
@@ -1003,10 +1016,10 @@ __global__ __launch_bounds__(kThreads) void k_bounds(const int* __restrict__ sat
 // combination of the SAT over the row's z and y ranges; D rows are built in LDS first.
 // NCOUNT: the fixed side has a general mask, so N(chi) is read from the exact count rows that
 // k_overlap_x wrote (ncount[slot][zc][yc][cx]) instead of the SAT box sums.
-template <bool WRITE_MAP, int LC, bool NCOUNT = false>
+template <bool WRITE_MAP, int LC, bool NCOUNT = false, typename V = float2>
 __global__ __launch_bounds__(kThreadsC) void k_final_x(
-    const float2* __restrict__ Y4, const int* __restrict__ sat, unsigned long long* __restrict__ keys,
-    OverlapGeom g, int Wx, int Wy, int Wz, int H, int Hp, FftPlan pl, const float2* __restrict__ twtab,
+    const V* __restrict__ Y4, const int* __restrict__ sat, unsigned long long* __restrict__ keys,
+    OverlapGeom g, int Wx, int Wy, int Wz, int H, int Hp, FftPlan pl, const V* __restrict__ twtab,
     long long y4_sstride, long long sat_sstride, long long count_a, double gamma,
     float* __restrict__ cmap, long long* __restrict__ nmap, const uint8_t* __restrict__ flags,
     long long flag_sstride, const unsigned* __restrict__ work, const unsigned* __restrict__ nwork,
@@ -1019,9 +1032,10 @@ __global__ __launch_bounds__(kThreadsC) void k_final_x(
   __shared__ unsigned long long red[T / 64];
   const int Px = pl.L;
   const int X1 = g.nB[0] + 1;
-  float2* tw = reinterpret_cast<float2*>(smem);
-  float2* buf = reinterpret_cast<float2*>(smem + align16(sizeof(float2) * Px));
-  int* drow = reinterpret_cast<int*>(smem + align16(sizeof(float2) * Px) + align16(sizeof(float2) * Px * (WP + 1)));
+  using S = scalar_t<V>;
+  V* tw = reinterpret_cast<V*>(smem);
+  V* buf = reinterpret_cast<V*>(smem + align16(sizeof(V) * Px));
+  int* drow = reinterpret_cast<int*>(smem + align16(sizeof(V) * Px) + align16(sizeof(V) * Px * (WP + 1)));
   // one group of NR displacement rows (slot, zc, yc0 .. yc0 + NR - 1)
   auto run = [&](const int slot, const int zc, const int yc0) {
   const int* s = sat + slot * sat_sstride;
@@ -1088,27 +1102,27 @@ __global__ __launch_bounds__(kThreadsC) void k_final_x(
   const int* nrows = NCOUNT ? ncount + slot * ncount_sstride + ((long long)zc * Wy) * Wx : nullptr;
   if (LC == 0) __syncthreads();
   unsigned long long best = 0ull;
-  const RView rows(Y4 + slot * y4_sstride + ((long long)zc * Wy) * Hp, 8LL * Wy * Hp);  // rows >= Wy load zero
-  const uint32_t hp8 = 8u * (uint32_t)Hp;
-  auto pack = [&](int k0, int k1, int p) -> float2 {
+  const RView rows(Y4 + slot * y4_sstride + ((long long)zc * Wy) * Hp, (long long)sizeof(V) * Wy * Hp);  // rows >= Wy load zero
+  const uint32_t hpb = (uint32_t)sizeof(V) * (uint32_t)Hp;
+  auto pack = [&](int k0, int k1, int p) -> V {
     const int k = k0 + k1;
     const int r0 = yc0 + 2 * p;
     // bin 0 holds DC + i Nyquist of each row.  Branch-free, so the loads of a butterfly's
     // elements are all in flight together.
     const bool lo = k < half;
     const int kk = k == half ? 0 : lo ? k : Px - k;
-    const uint32_t o0 = off2(r0, hp8, kk);
+    const uint32_t o0 = offv<V>(r0, hpb, kk);
     // (cached loads: each bin is read twice, for k and Px - k)
-    const float2 a = rows.ld2((fmask >> (2 * p)) & 1u ? o0 : kNoOff);
-    const float2 c = rows.ld2((fmask >> (2 * p + 1)) & 1u ? o0 + hp8 : kNoOff);
+    const V a = rows.template ldv<V, false>((fmask >> (2 * p)) & 1u ? o0 : kNoOff);
+    const V c = rows.template ldv<V, false>((fmask >> (2 * p + 1)) & 1u ? o0 + hpb : kNoOff);
     // k < half: S1 + i S2; k > half: conj(S1) + i conj(S2); k = 0 / half: DC / Nyquist
-    const float sg = lo ? 1.0f : -1.0f;
-    float2 z = make_float2(fmaf(-sg, c.y, a.x), fmaf(sg, a.y, c.x));
-    z = k == 0 ? make_float2(a.x, c.x) : z;
-    z = k == half ? make_float2(a.y, c.y) : z;
+    const S sg = lo ? S(1) : S(-1);
+    V z = cplx<V>(fmadd(-sg, c.y, a.x), fmadd(sg, a.y, c.x));
+    z = k == 0 ? cplx<V>(a.x, c.x) : z;
+    z = k == half ? cplx<V>(a.y, c.y) : z;
     return z;
   };
-  auto emit = [&](int j0, int j1, int p, float2 zv, int) {
+  auto emit = [&](int j0, int j1, int p, V zv, int) {
     int cx = j0 + j1 + g.nA[0] - 1;   // < 2 Px
     if (cx >= Px) cx -= Px;
     if (cx >= Wx) return;
@@ -1119,14 +1133,14 @@ __global__ __launch_bounds__(kThreadsC) void k_final_x(
       const int rr = 2 * p + h;
       const int yc = yc0 + rr;
       if (yc >= Wy) continue;
-      const float sv = h ? zv.y : zv.x;
+      const S sv = h ? zv.y : zv.x;
       int n;
       if constexpr (NCOUNT)   // rows without a flag hold no valid displacement and no counts
         n = (WRITE_MAP || ((fmask >> rr) & 1u)) ? nrows[(long long)yc * Wx + cx] : 0;
       else
         n = (lx <= hx) ? drow[rr * X1 + hx + 1] - drow[rr * X1 + lx] : 0;
       const bool valid = n >= thr;
-      const float c = valid ? sv / (float)n : -INFINITY;
+      const float c = valid ? (float)(sv / (S)n) : -INFINITY;
       const unsigned int canon = (unsigned)((zc * Wy + yc) * Wx + cx);
       if (valid) {
         const unsigned long long key = ((unsigned long long)ordered_bits(c) << 32) | (0xFFFFFFFFu - canon);

@@ -184,6 +184,18 @@ def test_user_mask_on_a_full_map_and_rotations_against_oracle(full):
     check_against_oracle(pair.A, pair.B, pair.rotations[idx], sub, sb, P=pair.pad, mask_a=mask_a.astype(bool))
 
 
+def test_fp64_correlation_at_paper_scale(full, oracle_map):
+    """CSNGF_FP64 at 176x176x110 (FFT 352x352x220, FP64 spectra): the whole map of one rotation
+    element by element against the oracle, and against the FP32 map of the same rotation."""
+    pair = full["pair"]
+    with bd.Context(pair.A, pair.dims_b, pad=pair.pad, fp64=True) as ctx:
+        Cg, Ng = ctx.evaluate_map(pair.B, pair.rotations[MAP_ROT])
+    _compare_maps(Cg, Ng, oracle_map.C, oracle_map.N, "config2-fp64-map")
+    v = np.isfinite(Cg)
+    assert np.array_equal(v, np.isfinite(full["C"]))
+    assert float(np.max(np.abs(Cg[v] - full["C"][v]))) <= 1e-6
+
+
 @pytest.mark.parametrize("r", [0, N_RANDOM])
 def test_per_rotation_results_against_oracle(full, r):
     """Whole-map oracle (FP64 FFT route) for single rotations of the batch, including the

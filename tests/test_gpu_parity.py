@@ -279,10 +279,11 @@ def test_all_ones_mask_on_a_equals_no_mask_and_empty_mask_has_no_shift():
 
 @pytest.mark.parametrize("seed", [107, 115, 119])
 def test_gamma_zero_small_overlaps(seed):
-    """gamma = 0 admits every displacement with N >= 1.  S comes from an FP32 FFT whose absolute
-    error follows the fields' energy, and C = S / N passes it on undivided where N is tiny, so
-    the 1e-4 bar is checked where N >= 10; below that the absolute error of S (= dC * N) is
-    bounded instead.  N and validity are exact everywhere."""
+    """gamma = 0 admits every displacement with N >= 1.  On the FP32 path S comes from an FP32
+    FFT whose absolute error follows the fields' energy, and C = S / N passes it on undivided
+    where N is tiny, so the 1e-4 bar is checked where N >= 10; below that the absolute error of S
+    (= dC * N) is bounded instead.  N and validity are exact everywhere.  (The FP64 correlation,
+    CSNGF_FP64, meets 1e-4 at every overlap of these pairs: the next test.)"""
     from scipy.ndimage import gaussian_filter
     rng = np.random.default_rng(seed)
     sa = tuple(int(v) for v in rng.integers(3, 30, size=3))
@@ -393,6 +394,59 @@ def test_kept_row_counts_match_overlap_bounds():
                     assert not np.isfinite(Cg[zc, yc]).any(), (zc, yc)
     _say("kept rows", kz, kr, "expected", want_z, want_r)
     assert (kz, kr) == (want_z, want_r)
+
+
+@pytest.mark.parametrize("seed", [107, 115, 119])
+def test_fp64_correlation_meets_the_bar_at_every_overlap(seed):
+    """With CSNGF_FP64 the transforms, the frequency-domain sum and the inverse run in double
+    precision, so the small-overlap displacements that gamma = 0 admits (N down to 1) meet
+    |dC| <= 1e-4 like all others: the pairs of test_gamma_zero_small_overlaps, every valid chi."""
+    from scipy.ndimage import gaussian_filter
+    rng = np.random.default_rng(seed)
+    sa = tuple(int(v) for v in rng.integers(3, 30, size=3))
+    sb = tuple(int(v) for v in rng.integers(3, 30, size=3))
+    A = gaussian_filter(rng.random(sa), 1.0).astype(np.float32)
+    B = gaussian_filter(rng.random(sb), 1.0).astype(np.float32)
+    R = _rand_rot(rng, 60)
+    _say("fp64 gamma 0", seed, sa, sb)
+    with bd.Context(A, bd.dims_of(B), gamma=0.0, fp64=True) as ctx:
+        P = tuple(ctx.info().pad)
+        Cg, Ng = ctx.evaluate_map(B, R)
+    Co, No, _ = _oracle_maps(A, B, R, None, 0.0, P)
+    _compare_maps(Cg, Ng, Co, No, f"fp64-gamma0-{seed}")
+    n = No[np.isfinite(Co)]
+    assert n.min() <= 3   # the case really holds tiny overlaps
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_fp64_correlation_full_maps(case):
+    """CSNGF_FP64 against the oracle: whole maps for random uneven pairs, both measures, a user
+    mask on A, a mask on B, and the 32^3 pair with its known shift."""
+    rng = np.random.default_rng(400 + case)
+    from scipy.ndimage import gaussian_filter
+    if case == 3:
+        pair = synth.config0()
+        A, B, R, P, mask_a, mask_b, measure = pair.A, pair.B, np.eye(3), pair.pad, None, None, "squared"
+    else:
+        sa = tuple(int(v) for v in rng.integers(5, 23, size=3))
+        sb = tuple(int(v) for v in rng.integers(5, 23, size=3))
+        A = gaussian_filter(rng.random(sa), 1.0).astype(np.float32)
+        B = gaussian_filter(rng.random(sb), 1.0).astype(np.float32)
+        R, P = _rand_rot(rng, 50), (0, 0, 0)
+        mask_a = _mask_of_a(rng, sa, "ellipsoid-holes") if case == 1 else None
+        mask_b = (rng.random(sb) > 0.03).astype(np.uint8) if case == 2 else None
+        measure = "unsquared" if case == 2 else "squared"
+    gamma = 0.25 if case == 2 else 0.5
+    _say("fp64 map", case, A.shape, B.shape, measure, gamma)
+    with bd.Context(A, bd.dims_of(B), pad=P, mask_a=mask_a, measure=measure, gamma=gamma, fp64=True) as ctx:
+        Pused = tuple(ctx.info().pad)
+        Cg, Ng = ctx.evaluate_map(B, R, mask_b=mask_b)
+        per, best = ctx.evaluate(B, np.stack([R, np.eye(3)]), mask_b=mask_b)
+    Co, No, _ = _oracle_maps(A, B, R, None if mask_b is None else mask_b.astype(bool), gamma, Pused,
+                             mask_a=None if mask_a is None else mask_a.astype(bool), measure=measure)
+    _compare_maps(Cg, Ng, Co, No, f"fp64-{case}")
+    if case == 3:
+        assert tuple(per[0].shift) == pair.true_shift
 
 
 def test_padding_invariance_and_minimum_extent():

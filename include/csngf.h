@@ -83,7 +83,7 @@ typedef struct {
 } csngf_dims;
 
 typedef struct {
-  uint32_t struct_size; /* sizeof(csngf_params) (40 bytes) */
+  uint32_t struct_size; /* sizeof(csngf_params) (48 bytes) */
   float eps;            /* NGF regulariser, Eq. (1); default 1e-5 */
   double gamma;         /* minimum overlap fraction in [0, 1], Sec. 3.2; default 0.5.  chi is
                            valid iff N >= 1 and N >= gamma * m with m = min(|M_A|, |M_B^|), the
@@ -94,6 +94,12 @@ typedef struct {
                            that is at most 1.5x as long (see csngf_footprint for the result) */
   int32_t batch;        /* rotations in flight per launch sequence, 0 .. 255; 0 = automatic */
   uint32_t flags;       /* CSNGF_DEVICE_PTRS | CSNGF_UNSQUARED | CSNGF_GRAPHS | CSNGF_FP64 */
+  int32_t slices;       /* z slices per field-stage workgroup, 0 .. 64; 0 = automatic (8).  More
+                           slices re-sample fewer halo planes, fewer give more workgroups */
+  int32_t final_groups; /* workgroups of the final pass when no map is written, 0 .. 65535;
+                           0 = automatic (8192); they walk the list of row groups that hold a
+                           valid displacement */
+  int32_t reserved;     /* must be 0 */
 } csngf_params;
 
 typedef struct {
@@ -222,10 +228,12 @@ int csngf_footprint(csngf_dims dA, csngf_dims dB, const csngf_params* p, int64_t
 /* Autotuner: for the shapes of A and B and the base params (eps, gamma, flags), time the
  * candidate configurations - FFT size per axis (the smallest supported length and, if that
  * has no compile-time plan, the smallest one that has, within 1.5x) and rotation slots in
- * flight (the automatic choice, half and double) - on n_probe deterministic random
- * rotations, and return the fastest in *best (pad and batch set) and its rate in rotations/s
- * (*best_rate may be NULL).  Creates and destroys contexts; results do not depend on the
- * choice (any FFT size >= n_A + n_B - 1 gives the same linear correlation). */
+ * flight (the automatic choice, half and double), then, holding the best of those, z slices
+ * per field-stage workgroup (4, 8, 16) and then final-pass workgroups (2048 .. 16384) - on
+ * n_probe deterministic random rotations, and return the fastest in *best (pad, batch,
+ * slices and final_groups set) and its rate in rotations/s (*best_rate may be NULL).  Creates
+ * and destroys contexts; results do not depend on the choice (any FFT size >= n_A + n_B - 1
+ * gives the same linear correlation, and the launch shapes only split the same work). */
 int csngf_autotune(const float* A, csngf_dims dA, const float* B, csngf_dims dB, const csngf_params* base,
                    int32_t n_probe, csngf_params* best, double* best_rate);
 

@@ -36,7 +36,8 @@ class Dims(C.Structure):
 
 class Params(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("eps", C.c_float), ("gamma", C.c_double),
-                ("pad", C.c_int32 * 3), ("batch", C.c_int32), ("flags", C.c_uint32)]
+                ("pad", C.c_int32 * 3), ("batch", C.c_int32), ("flags", C.c_uint32),
+                ("slices", C.c_int32), ("final_groups", C.c_int32), ("reserved", C.c_int32)]
 
 
 class RotResult(C.Structure):
@@ -154,10 +155,10 @@ class Context:
     """Owns a csngf_ctx: A's resident spectra and the rotation workspaces."""
 
     def __init__(self, A, dims_b, *, mask_a=None, eps=1e-5, gamma=0.5, pad=(0, 0, 0), batch=0, stream=None,
-                 measure="squared", graphs=False, fp64=False):
+                 measure="squared", graphs=False, fp64=False, slices=0, final_groups=0):
         """measure: "squared" (Eq. (2), CSNGF) or "unsquared" (Eq. (3), USNGF); graphs: replay
         each full batch from a recorded HIP graph; fp64: correlate in double precision
-        (CSNGF_FP64)."""
+        (CSNGF_FP64); slices, final_groups: launch shapes (0 = automatic), as autotune returns."""
         if measure not in ("squared", "unsquared"):
             raise ValueError(f"unknown measure {measure!r}")
         self.device = _is_device(A)
@@ -170,6 +171,8 @@ class Context:
         p.gamma = gamma
         p.pad[:] = list(pad)
         p.batch = batch
+        p.slices = slices
+        p.final_groups = final_groups
         p.flags = ((DEVICE_PTRS if self.device else 0) | (UNSQUARED if measure == "unsquared" else 0)
                    | (GRAPHS if graphs else 0) | (FP64 if fp64 else 0))
         h = C.c_void_p()
@@ -302,7 +305,8 @@ def _check_query(rc):
 
 
 def autotune(A, B, *, n_probe=64, measure="squared", gamma=0.5, eps=1e-5, graphs=False):
-    """Fastest (pad, batch) for this pair's shapes; returns (dict(pad=..., batch=...), rotations/s)."""
+    """Fastest configuration for this pair's shapes; returns (dict(pad=..., batch=..., slices=...,
+    final_groups=...), rotations/s), the dict's keys being Context keywords."""
     dev = _is_device(A)
     if not dev:
         A = np.ascontiguousarray(A, dtype=np.float32)
@@ -315,7 +319,8 @@ def autotune(A, B, *, n_probe=64, measure="squared", gamma=0.5, eps=1e-5, graphs
     rate = C.c_double()
     _check(lib().csngf_autotune(_ptr(A), dims_of(A), _ptr(B), dims_of(B), C.byref(p), n_probe, C.byref(out),
                                 C.byref(rate)))
-    return {"pad": tuple(out.pad), "batch": out.batch}, rate.value
+    return ({"pad": tuple(out.pad), "batch": out.batch, "slices": out.slices, "final_groups": out.final_groups},
+            rate.value)
 
 
 def footprint(dims_a, dims_b, *, pad=(0, 0, 0), measure="squared"):

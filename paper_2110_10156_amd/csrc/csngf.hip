@@ -128,6 +128,8 @@ size_t lds_fields(int Px, int nx, size_t el = sizeof(float2)) {
 #define CSNGF_SLICES 8
 #endif
 constexpr int kSlicesX = CSNGF_SLICES;
+// final-pass workgroups walking the work list (8192 measured best of 1024 .. 16384 at 176^3/110^3)
+constexpr int kFinalGroups = 8192;
 size_t lds_pencil(int L, int W = kTileW, size_t el = sizeof(float2)) { return a16(el * L) + a16(el * L * W); }
 size_t lds_final(int Px, int nxB, size_t el = sizeof(float2)) {
   return a16(el * Px) + a16(el * Px * (kRowsC + 1)) + a16(sizeof(int) * 2 * kRowsC * (nxB + 1));
@@ -203,6 +205,8 @@ struct csngf_ctx {
   uint32_t flags = 0;
   int nf = 6;  // separable fields: 6 (squared measure) or 3 (unsquared)
   int batch = 1;
+  int slices = kSlicesX;            // z slices per field-stage workgroup
+  int final_groups = kFinalGroups;  // final-pass workgroups without a map
   FftPlan plx{}, ply{}, plz{};
   float2* d_tw = nullptr;
   float2* d_spec = nullptr;
@@ -487,7 +491,7 @@ int launch_zpass(csngf_ctx* c, const V* X2, const V* spec, V* Y3, int nf, long l
 template <typename V>
 int launch_fields(csngf_ctx* c, bool moving, const float* vol, const uint8_t* um, const int* n3, const int* rotq,
                   V* out, long long out_slot, uint8_t* mask_out, long long mask_slot, float* dbg, int slots) {
-  const int tz = kSlicesX;
+  const int tz = c->slices;
   const int nreal = (n3[1] + kRowsX - 1) / kRowsX * ((n3[2] + tz - 1) / tz) * slots;
   const dim3 grid((nreal + 7) / 8 * 8);
   const size_t lds = lds_fields(c->plx.L, n3[0], sizeof(V));
@@ -762,7 +766,7 @@ int run_batch_t(csngf_ctx* c, const float* dB, const uint8_t* dmB, const int* ro
     // without a map: a fixed grid over the work list of row groups that hold a valid
     // displacement (most do not at gamma = 0.5)
     const int items = (int)(grid.x * grid.y * grid.z);
-    const dim3 lgrid(std::min(items, 8192));   // 8192 measured best of 1024 .. 16384
+    const dim3 lgrid(std::min(items, c->final_groups));
     const size_t lds = lds_final(c->plx.L, c->nB[0], sizeof(V));
     hipError_t ae = hipSuccess;
     ev = prof_begin(c);
@@ -970,6 +974,10 @@ int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims
     return fail(CSNGF_E_INVALID_ARG, "batch must lie in [0, 255]");
   if (prm.flags & ~(CSNGF_DEVICE_PTRS | CSNGF_UNSQUARED | CSNGF_GRAPHS | CSNGF_FP64))
     return fail(CSNGF_E_INVALID_ARG, "unknown flag bits");
+  if (prm.slices < 0 || prm.slices > 64) return fail(CSNGF_E_INVALID_ARG, "slices must lie in [0, 64]");
+  if (prm.final_groups < 0 || prm.final_groups > 65535)
+    return fail(CSNGF_E_INVALID_ARG, "final_groups must lie in [0, 65535]");
+  if (prm.reserved != 0) return fail(CSNGF_E_INVALID_ARG, "params.reserved must be 0");
   const int nA[3] = {dA.nx, dA.ny, dA.nz}, nB[3] = {dB.nx, dB.ny, dB.nz};
   int P[3];
   for (int i = 0; i < 3; ++i) {
@@ -1008,6 +1016,8 @@ int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims
   }
   c->eps = prm.eps;
   c->gamma = prm.gamma;
+  if (prm.slices) c->slices = prm.slices;
+  if (prm.final_groups) c->final_groups = prm.final_groups;
   c->flags = prm.flags;
   c->nf = (prm.flags & CSNGF_UNSQUARED) ? 3 : 6;
   c->H = P[0] / 2;   // bins 0 .. Px/2 - 1, bin 0 packing DC + i Nyquist
@@ -1594,6 +1604,27 @@ extern "C" int csngf_autotune(const float* A, csngf_dims dA, const float* B, csn
         }
       }
   if (best_r <= 0) return fail(CSNGF_E_DEVICE, "no candidate configuration could be evaluated");
+  // launch shapes, one knob at a time from the best FFT size and slot count
+  {
+    const csngf_params base_p = best_p;
+    for (int sl : {4, 16}) {
+      csngf_params q = base_p;
+      q.slices = sl;
+      int bu = 0;
+      const double r = probe(q, &bu);
+      if (r > best_r) { best_r = r; best_p = q; }
+    }
+    const csngf_params base_f = best_p;
+    for (int fg : {2048, 4096, 16384}) {
+      csngf_params q = base_f;
+      q.final_groups = fg;
+      int bu = 0;
+      const double r = probe(q, &bu);
+      if (r > best_r) { best_r = r; best_p = q; }
+    }
+  }
+  if (best_p.slices == 0) best_p.slices = kSlicesX;
+  if (best_p.final_groups == 0) best_p.final_groups = kFinalGroups;
   *best = best_p;
   if (best_rate) *best_rate = best_r;
   return CSNGF_OK;

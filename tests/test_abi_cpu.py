@@ -39,8 +39,9 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_sizes_match_header_layout():
-    assert C.sizeof(bd.Params) == 40
+    assert C.sizeof(bd.Params) == 48
     assert bd.Params.gamma.offset == 8 and bd.Params.pad.offset == 16 and bd.Params.flags.offset == 32
+    assert bd.Params.slices.offset == 36 and bd.Params.final_groups.offset == 40 and bd.Params.reserved.offset == 44
     assert C.sizeof(bd.RotResult) == 32
     assert C.sizeof(bd.Best) == 32 + 72
     assert C.sizeof(bd.Dims) == 12
@@ -51,6 +52,7 @@ def test_default_params():
     assert p.struct_size == C.sizeof(bd.Params)
     assert abs(p.eps - 1e-5) < 1e-12 and p.gamma == 0.5
     assert list(p.pad) == [0, 0, 0] and p.batch == 0 and p.flags == 0
+    assert p.slices == 0 and p.final_groups == 0 and p.reserved == 0
 
 
 @pytest.mark.parametrize("L,ok", [(8, 1), (64, 1), (220, 1), (352, 1), (192, 1), (110, 1), (440, 1), (512, 1),
@@ -91,6 +93,12 @@ def test_create_rejects_bad_arguments_before_touching_a_device():
         p = bd.default_params()
         p.batch = batch
         assert _create(A, dB, params=p)[0] == bd.E_INVALID_ARG
+    for field, bad in (("slices", -1), ("slices", 65), ("final_groups", -1), ("final_groups", 65536),
+                       ("reserved", 1)):
+        p = bd.default_params()
+        setattr(p, field, bad)
+        assert _create(A, dB, params=p)[0] == bd.E_INVALID_ARG, field
+        assert field.encode() in bd.lib().csngf_last_error()
     p = bd.default_params()
     p.pad[0] = 10  # < 8 + 8 - 1
     assert _create(A, dB, params=p)[0] == bd.E_INVALID_ARG

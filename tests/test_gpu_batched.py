@@ -79,6 +79,7 @@ def test_autotune_returns_an_equivalent_configuration():
     cfg, rate = bd.autotune(pair.A, pair.B, n_probe=48)
     _say("autotune 48^3", cfg, round(rate, 1))
     assert rate > 0 and cfg["batch"] >= 1 and all(p >= 95 for p in cfg["pad"])
+    assert cfg["slices"] in (4, 8, 16) and cfg["final_groups"] in (2048, 4096, 8192, 16384)
     with bd.Context(pair.A, pair.dims_b) as c0, bd.Context(pair.A, pair.dims_b, **cfg) as c1:
         p0, b0 = c0.evaluate(pair.B, pair.rotations)
         p1, b1 = c1.evaluate(pair.B, pair.rotations)

@@ -517,6 +517,29 @@ def test_batch_invariance_bit_identical():
     assert b1.rot_index == b7.rot_index == pair.true_index
 
 
+@pytest.mark.parametrize("shape", [dict(slices=1), dict(slices=3), dict(slices=64), dict(final_groups=1),
+                                   dict(final_groups=7), dict(final_groups=65535), dict(slices=5, final_groups=300)])
+def test_launch_shapes_bit_identical(shape):
+    # the launch shapes only split the same work: z slices per field-stage workgroup re-sample
+    # the halo planes with the same arithmetic, and final-pass workgroups walk the same list
+    pair = synth.config1(n_random=12)
+    rng = np.random.default_rng(31)
+    mask_a = (rng.random(pair.A.shape) < 0.9).astype(np.uint8)
+    for ma in (None, mask_a):
+        with bd.Context(pair.A, pair.dims_b, mask_a=ma) as c0, \
+                bd.Context(pair.A, pair.dims_b, mask_a=ma, **shape) as c1:
+            p0, b0 = c0.evaluate(pair.B, pair.rotations)
+            p1, b1 = c1.evaluate(pair.B, pair.rotations)
+            C0, N0 = c0.evaluate_map(pair.B, pair.rotations[3])
+            C1, N1 = c1.evaluate_map(pair.B, pair.rotations[3])
+        for a, b in zip(p0, p1):
+            assert a.valid == b.valid and a.score == b.score and tuple(a.shift) == tuple(b.shift)
+            assert a.overlap == b.overlap
+        assert b0.rot_index == b1.rot_index and tuple(b0.shift) == tuple(b1.shift)
+        assert np.array_equal(C0, C1) and np.array_equal(N0, N1)
+    assert b0.rot_index >= 0
+
+
 def test_edge_cases():
     rng = np.random.default_rng(4)
     A = rng.random((6, 6, 6)).astype(np.float32)

@@ -269,6 +269,30 @@ __device__ __forceinline__ void fft_stage(V* __restrict__ buf, const V* __restri
   __syncthreads();
 }
 
+// ---------------------------------------------------------------- 24-bit index arithmetic
+// Full-rate 24-bit integer multiplies (operands < 2^24).  Written as instructions: the
+// compiler turns __umul24 into a general 32-bit multiply, a quarter-rate instruction,
+// wherever it can prove the operands small but loses that fact before choosing the
+// instruction.
+// a * C for a compile-time C (a literal operand; powers of two are shifts)
+template <unsigned C>
+__device__ __forceinline__ unsigned mul24c(unsigned a) {
+  static_assert(C < (1u << 24), "24-bit constant");
+  if constexpr ((C & (C - 1)) == 0) {
+    return a * C;
+  } else {
+    unsigned r;
+    asm("v_mul_u32_u24 %0, %1, %2" : "=v"(r) : "i"(C), "v"(a));
+    return r;
+  }
+}
+// a * b + c with a workgroup-uniform b (held in a scalar register)
+__device__ __forceinline__ unsigned mad24u(unsigned a, unsigned b, unsigned c) {
+  unsigned r;
+  asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(c));
+  return r;
+}
+
 // ---------------------------------------------------------------- compile-time plans
 // floor(j / D) for 0 <= j < MAXJ with one full-rate 24-bit multiply and a shift instead of
 // the quarter-rate 32-bit multiplies of a general division: with M = ceil(2^S / D) and
@@ -282,7 +306,7 @@ __device__ __forceinline__ unsigned div_small(unsigned j) {
     constexpr unsigned long long M = ((1ull << S) + D - 1) / D;
     static_assert((unsigned long long)(MAXJ - 1) * (M * D - (1ull << S)) < (1ull << S), "inexact");
     static_assert(M < (1u << 24) && (unsigned long long)(MAXJ - 1) * M < (1ull << 32), "24-bit range");
-    return __umul24(j, (unsigned)M) >> S;
+    return mul24c<(unsigned)M>(j) >> S;
   }
 }
 
@@ -307,78 +331,55 @@ constexpr CPlan make_cplan(int L) {
   return p;
 }
 
-// One stage with everything known at compile time (exact butterflies per thread, no
-// run-time division).
-template <int L, int R, int NS, int W, int T, bool INV, typename V>
-__device__ __forceinline__ void fft_stage_fixed(V* __restrict__ buf, const V* __restrict__ tw) {
-  constexpr int LR = L / R;
-  constexpr int NBF = LR * W;
-  constexpr int NB = (NBF + T - 1) / T;
-  constexpr int TWSTEP = L / (NS * R);
-  V v[NB][R];
-#pragma unroll
-  for (int u = 0; u < NB; ++u) {
-    const unsigned bf = threadIdx.x + u * T;
-    if (NBF % T == 0 || bf < NBF) {
-      const unsigned p = bf % W, j = bf / W;
-#pragma unroll
-      for (int t = 0; t < R; ++t) v[u][t] = buf[(j + t * LR) * W + p];
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int u = 0; u < NB; ++u) {
-    const unsigned bf = threadIdx.x + u * T;
-    if (NBF % T == 0 || bf < NBF) {
-      const unsigned p = bf % W, j = bf / W;
-      const unsigned q = div_small<NS, LR>(j), k = j - q * NS;
-      if constexpr (NS > 1) {
-#pragma unroll
-        for (int t = 1; t < R; ++t) {
-          V w = tw[t * k * TWSTEP];
-          if (INV) w.y = -w.y;
-          v[u][t] = cmul(v[u][t], w);
-        }
-      }
-      dft<R, INV>(v[u]);
-      const int base = q * NS * R + k;
-#pragma unroll
-      for (int t = 0; t < R; ++t) buf[(base + t * NS) * W + p] = v[u][t];
-    }
-  }
-  __syncthreads();
+// Twiddles of a compile-time plan, stored by stage so that the R - 1 factors of a butterfly
+// are adjacent (one address per butterfly, the factors at constant offsets): stage s >= 1,
+// with radix R and stride NS, holds w^(t k L / (NS R)) for k = 0 .. NS - 1, t = 1 .. R - 1
+// at NS - R_0 + k (R - 1) + t - 1, where R_0 is the first stage's radix.  (Stage 0 has
+// NS = 1, so k = 0 and no factors; the earlier stages' blocks NS_s (R_s - 1) sum to
+// NS - R_0.)  The whole table has L - R_0 entries, fewer than the plain table's L.
+template <int L, int NS>
+constexpr int staged_tw_first() {
+  return NS - make_cplan(L).r[0];
 }
-
-template <int L, int S, int W, int T, bool INV, typename V>
-__device__ __forceinline__ void fft_fixed(V* __restrict__ buf, const V* __restrict__ tw) {
+template <int L>
+constexpr int staged_tw_size() {
+  return L - make_cplan(L).r[0];
+}
+// index into the plain table (w^i at i) of staged entry e, for the stages S, S + 1, ...
+template <int L, int S>
+__device__ __forceinline__ unsigned staged_tw_source(unsigned e) {
   constexpr CPlan P = make_cplan(L);
-  if constexpr (S < P.nst) {
-    fft_stage_fixed<L, P.r[S], P.ns[S], W, T, INV>(buf, tw);
-    fft_fixed<L, S + 1, W, T, INV>(buf, tw);
+  if constexpr (S >= P.nst) {
+    return 0;
+  } else {
+    constexpr int R = P.r[S], NS = P.ns[S];
+    constexpr unsigned end = (unsigned)(NS * R - P.r[0]);
+    if (e < end) {
+      const unsigned d = e - (unsigned)staged_tw_first<L, NS>();
+      const unsigned k = div_small<R - 1, NS * (R - 1)>(d), t = d - k * (R - 1) + 1;
+      return t * k * (unsigned)(L / (NS * R));
+    }
+    return staged_tw_source<L, S + 1>(e);
   }
 }
 
-// Whole transform.  LC > 0: the length is LC, planned at compile time.  LC == 0: run-time
-// plan pl (any supported length up to kMaxLen).  Caller has synchronised after filling buf;
-// on return buf holds the result in natural order and the group is synchronised.
-template <int W, int T, int LC, bool INV, typename V>
+// Whole transform on the run-time plan pl (any supported length up to kMaxLen) with the
+// plain twiddle table.  Caller has synchronised after filling buf; on return buf holds the
+// result in natural order and the group is synchronised.
+template <int W, int T, bool INV, typename V>
 __device__ void fft_lds(V* __restrict__ buf, const V* __restrict__ tw, const FftPlan& pl) {
-  if constexpr (LC > 0) {
-    fft_fixed<LC, 0, W, T, INV>(buf, tw);
-  } else {
-    constexpr int LW = kMaxLen * W;
-    for (int s = 0; s < pl.nst; ++s) {
-      const int ns = pl.ns[s];
-      switch (pl.radix[s]) {
-        case 2: fft_stage<2, W, T, LW, INV>(buf, tw, pl.L, ns); break;
-        case 3: fft_stage<3, W, T, LW, INV>(buf, tw, pl.L, ns); break;
-        case 4: fft_stage<4, W, T, LW, INV>(buf, tw, pl.L, ns); break;
-        case 5: fft_stage<5, W, T, LW, INV>(buf, tw, pl.L, ns); break;
-        case 7: fft_stage<7, W, T, LW, INV>(buf, tw, pl.L, ns); break;
-        case 8: fft_stage<8, W, T, LW, INV>(buf, tw, pl.L, ns); break;
-        case 11: fft_stage<11, W, T, LW, INV>(buf, tw, pl.L, ns); break;
-        default: break;
-      }
+  constexpr int LW = kMaxLen * W;
+  for (int s = 0; s < pl.nst; ++s) {
+    const int ns = pl.ns[s];
+    switch (pl.radix[s]) {
+      case 2: fft_stage<2, W, T, LW, INV>(buf, tw, pl.L, ns); break;
+      case 3: fft_stage<3, W, T, LW, INV>(buf, tw, pl.L, ns); break;
+      case 4: fft_stage<4, W, T, LW, INV>(buf, tw, pl.L, ns); break;
+      case 5: fft_stage<5, W, T, LW, INV>(buf, tw, pl.L, ns); break;
+      case 7: fft_stage<7, W, T, LW, INV>(buf, tw, pl.L, ns); break;
+      case 8: fft_stage<8, W, T, LW, INV>(buf, tw, pl.L, ns); break;
+      case 11: fft_stage<11, W, T, LW, INV>(buf, tw, pl.L, ns); break;
+      default: break;
     }
   }
 }
@@ -428,24 +429,25 @@ __device__ __forceinline__ void fft_stage_io(V* __restrict__ buf, const V* __res
   constexpr int LR = L / R;
   constexpr int NBF = LR * W;
   constexpr int NB = (NBF + T - 1) / T;
-  constexpr int TWSTEP = L / (NS * R);
   auto finish = [&](V* v, unsigned p, unsigned j, int u) {
-    const unsigned q = div_small<NS, LR>(j), k = j - q * NS;
+    const unsigned q = div_small<NS, LR>(j), k = j - mul24c<NS>(q);
     if constexpr (NS > 1) {
+      // this butterfly's R - 1 factors are adjacent in the staged table
+      const unsigned kb = opaque_base(mul24c<R - 1>(k));
 #pragma unroll
       for (int t = 1; t < R; ++t) {
-        V w = tw[t * k * TWSTEP];
+        V w = tw[kb + staged_tw_first<L, NS>() + t - 1];
         if (INV) w.y = -w.y;
         v[t] = cmul(v[t], w);
       }
     }
     dft<R, INV, NZ>(v);
-    const unsigned base = q * NS * R + k;
+    const unsigned base = mul24c<NS * R>(q) + k;
     if constexpr (TO_ST) {
 #pragma unroll
       for (int t = 0; t < R; ++t) st(base, t * NS, p, v[t], u * R + t);
     } else {
-      const unsigned wb = opaque_base(base * WSO + p);
+      const unsigned wb = opaque_base(mul24c<WSO>(base) + p);
 #pragma unroll
       for (int t = 0; t < R; ++t) buf[wb + t * NS * WSO] = v[t];
     }
@@ -463,7 +465,7 @@ __device__ __forceinline__ void fft_stage_io(V* __restrict__ buf, const V* __res
 #pragma unroll
           for (int t = 0; t < R; ++t) v[t] = t < NZ ? ld(j, t * LR, p) : czero<V>();
         } else {
-          const unsigned rb = opaque_base(j * WS + p);
+          const unsigned rb = opaque_base(mul24c<WS>(j) + p);
 #pragma unroll
           for (int t = 0; t < R; ++t) v[t] = buf[rb + t * LR * WS];
         }
@@ -478,7 +480,7 @@ __device__ __forceinline__ void fft_stage_io(V* __restrict__ buf, const V* __res
       const unsigned bf = tx + u * T;
       if (NBF % T == 0 || bf < NBF) {
         const unsigned p = bf % W, j = bf / W;
-        const unsigned rb = opaque_base(j * WS + p);
+        const unsigned rb = opaque_base(mul24c<WS>(j) + p);
 #pragma unroll
         for (int t = 0; t < R; ++t) v[u][t] = buf[rb + t * LR * WS];
       }
@@ -520,8 +522,8 @@ __device__ __forceinline__ void for_each_last_slot(F&& f) {
     const unsigned bf = threadIdx.x + u * T;
     if (NBF % T == 0 || bf < NBF) {
       const unsigned p = bf % W, j = bf / W;
-      const unsigned q = div_small<NS, L / R>(j), k = j - q * NS;
-      const unsigned base = q * NS * R + k;
+      const unsigned q = div_small<NS, L / R>(j), k = j - mul24c<NS>(q);
+      const unsigned base = mul24c<NS * R>(q) + k;
 #pragma unroll
       for (int t = 0; t < R; ++t) f(base + t * NS, p, u * R + t);
     }
@@ -562,7 +564,7 @@ __device__ __forceinline__ void fft_io(V* __restrict__ buf, const V* __restrict_
       for (int e = threadIdx.x; e < L * W; e += T) buf[e] = ld(e / W, 0, e % W);
     }
     __syncthreads();
-    fft_lds<W, T, 0, INV>(buf, tw, pl);
+    fft_lds<W, T, INV>(buf, tw, pl);
     if constexpr (!OUT_LDS) {
       int slot = 0;
       for (int e = threadIdx.x; e < L * W; e += T, ++slot) st(e / W, 0, e % W, buf[e], slot);
@@ -573,17 +575,25 @@ __device__ __forceinline__ void fft_io(V* __restrict__ buf, const V* __restrict_
 // Lengths with a compile-time instance; every other supported length uses the run-time plan.
 constexpr int kFastLengths[] = {16, 32, 48, 56, 64, 88, 96, 110, 128, 176, 192, 220, 256, 352, 440, 512};
 
-// Copy this length's twiddle table into LDS (caller synchronises before use).
-template <typename V>
+// This length's twiddles into LDS (caller synchronises before use): the staged table of
+// the compile-time plan (LC > 0), else the plain table w^i, i = 0 .. L - 1.  table + tw_off
+// holds the plain table of the plan's length.
+template <int LC, typename V>
 __device__ __forceinline__ void load_twiddles(V* __restrict__ dst, const V* __restrict__ table, const FftPlan& pl) {
-  // two loads in flight per thread before either is stored (L <= 2 * blockDim.x in one pass)
-  const int L = pl.L, T = blockDim.x;
   const V* src = table + pl.tw_off;
-  for (int i = threadIdx.x; i < L; i += 2 * T) {
-    const int j = i + T < L ? i + T : i;
-    const V a = src[i], b = src[j];
-    dst[i] = a;
-    dst[j] = b;
+  const int T = blockDim.x;
+  if constexpr (LC > 0) {
+    constexpr int N = staged_tw_size<LC>();
+    for (int e = threadIdx.x; e < N; e += T) dst[e] = src[staged_tw_source<LC, 1>((unsigned)e)];
+  } else {
+    // two loads in flight per thread before either is stored (L <= 2 * blockDim.x in one pass)
+    const int L = pl.L;
+    for (int i = threadIdx.x; i < L; i += 2 * T) {
+      const int j = i + T < L ? i + T : i;
+      const V a = src[i], b = src[j];
+      dst[i] = a;
+      dst[j] = b;
+    }
   }
 }
 

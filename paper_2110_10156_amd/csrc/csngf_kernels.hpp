@@ -178,15 +178,18 @@ struct RView {
   }
 };
 
-// byte offset of element (row, col) of a float2 array with a row stride of rs8 bytes
-// (row < 2^24 and rs8 < 2^24, product < 2^31)
-__device__ __forceinline__ uint32_t off2(int row, uint32_t rs8, int col) {
-  return __umul24((unsigned)row, rs8) + 8u * (unsigned)col;
-}
-// the same for an array of complex V with a row stride of rsb bytes
+// byte offset of element (row, col) of an array of complex V with a row stride of rsb bytes
+// (row < 2^24 and rsb < 2^24, offset < 2^31; rsb workgroup-uniform)
 template <typename V>
 __device__ __forceinline__ uint32_t offv(int row, uint32_t rsb, int col) {
-  return __umul24((unsigned)row, rsb) + (uint32_t)sizeof(V) * (unsigned)col;
+  return mad24u((unsigned)row, rsb, (uint32_t)sizeof(V) * (unsigned)col);
+}
+// offv when ok, else kNoOff.  The offset is formed unconditionally and then selected: as a
+// conditional expression around offv the compiler would branch around the multiply.
+template <typename V>
+__device__ __forceinline__ uint32_t offv_if(bool ok, int row, uint32_t rsb, int col) {
+  const uint32_t o = offv<V>(row, rsb, col);
+  return ok ? o : kNoOff;
 }
 
 // ------------------------------------------------------------------------------ x pass
@@ -250,7 +253,7 @@ __global__ __launch_bounds__(kThreadsF) void k_fields_x(
   const int y0 = (logical % nyt) * TY;
   const int z0 = ((logical / nyt) % nzc) * tz;
   const int slot = logical / (nyt * nzc);
-  load_twiddles(tw, twtab, pl);
+  load_twiddles<LC>(tw, twtab, pl);
   const float eps2 = eps * eps;
   const long nv = (long)nx * ny * nz;
   const unsigned tid = threadIdx.x;
@@ -315,7 +318,7 @@ __global__ __launch_bounds__(kThreadsF) void k_fields_x(
           if (ix == nx - 1) { ix = nx - 2; fx[h] = 1.0f; }
           if (iy == ny - 1) { iy = ny - 2; fy[h] = 1.0f; }
           if (iz == nz - 1) { iz = nz - 2; fz[h] = 1.0f; }
-          const unsigned o = (unsigned)((iz * ny + iy) * nx + ix);
+          const unsigned o = mad24u(mad24u((unsigned)iz, ny, (unsigned)iy), nx, (unsigned)ix);
           const unsigned o4 = ok ? 4u * o : kNoOff;
           c[h][0] = src.ld2(o4, 0);          // corners (x, x+1) of the 4 (y, z) edges
           c[h][1] = src.ld2(o4, sy4);
@@ -428,19 +431,20 @@ __global__ __launch_bounds__(kThreadsF) void k_fields_x(
                          !__builtin_isnan(gy) && !__builtin_isnan(gz);
           float n0 = 0.f, n1 = 0.f, n2 = 0.f;
           if (m) {
-            const float inv = 1.0f / sqrtf(gx * gx + gy * gy + gz * gz + eps2);
+            // hardware reciprocal square root (within 1 ulp; its argument is >= eps^2, normal)
+            const float inv = __builtin_amdgcn_rsqf(gx * gx + gy * gy + gz * gz + eps2);
             n0 = gx * inv;
             n1 = gy * inv;
             n2 = gz * inv;
           }
-          const int q = r * nxs + x;
+          const int q = (int)mad24u((unsigned)r, nxs, (unsigned)x);
           ng[q] = n0;
           ng[TY * nxs + q] = n1;
           ng[2 * TY * nxs + q] = n2;
           if (mask_out) {
             const int yy = y0 + r;
-            RView(mask_out + slot * mask_slot_stride, nv).st1(yy < ny ? (unsigned)((z * ny + yy) * nx + x) : kNoOff,
-                                                              m ? 1 : 0);
+            const unsigned mo = mad24u(mad24u((unsigned)z, ny, (unsigned)yy), nx, (unsigned)x);
+            RView(mask_out + slot * mask_slot_stride, nv).st1(yy < ny ? mo : kNoOff, m ? 1 : 0);
           }
         }
       }
@@ -482,7 +486,7 @@ __global__ __launch_bounds__(kThreadsF) void k_fields_x(
         const int x = x0 + x1;
         // x >= nx reads past the row (at most Px floats past ng: the LDS layout pads it) and
         // is replaced by zero below
-        const unsigned b = opaque_base((unsigned)(r * nxs + x0));
+        const unsigned b = opaque_base(mad24u((unsigned)r, nxs, (unsigned)x0));
         const float n0 = ng[b + x1], n1 = ng[TY * nxs + b + x1], n2 = ng[2 * TY * nxs + b + x1];
         const float a1 = p1 ? n2 : n0;
         const float a2 = sq ? (p0 ? n0 : n2) : 1.0f;
@@ -509,10 +513,10 @@ __global__ __launch_bounds__(kThreadsF) void k_fields_x(
         const int e = (int)tid + u * T;
         const bool ok = e < TY * H;
         const int k = ok ? bk[u] : 0, r = ok ? br[u] : 0;
-        const V zk = buf[k * WS + r];
-        const V zc = buf[(k ? Px - k : Px / 2) * WS + r];
+        const V zk = buf[mul24c<WS>((unsigned)k) + r];
+        const V zc = buf[mul24c<WS>((unsigned)(k ? Px - k : Px / 2)) + r];
         const int yy = y0 + r;
-        const uint32_t off = ok && yy >= 1 && yy <= ny - 2 ? offv<V>(row0 + r, hpb, k) : kNoOff;
+        const uint32_t off = offv_if<V>(ok && yy >= 1 && yy <= ny - 2, row0 + r, hpb, k);
         oa.template stv<V>(off, k ? cplx<V>(S(0.5) * (zk.x + zc.x), S(0.5) * (zk.y - zc.y)) : cplx<V>(zk.x, zc.x));
         ob.template stv<V>(off, k ? cplx<V>(S(0.5) * (zk.y + zc.y), S(0.5) * (zc.x - zk.x)) : cplx<V>(zk.y, zc.y));
       }
@@ -548,7 +552,7 @@ __global__ __launch_bounds__(kThreadsP<INV>) void k_pencil(
   const RView dst(out + blockIdx.z * out_sstride + blockIdx.y * out_gstride + kx0,
                   (long long)sizeof(V) * ((long long)n_out * Hp - kx0));
   const uint32_t rsb = (uint32_t)sizeof(V) * (uint32_t)Hp;
-  load_twiddles(tw, twtab, pl);
+  load_twiddles<LC>(tw, twtab, pl);
   // inverse with flags: the group's row flags go to LDS once (rows c >= n_out read 0), so the
   // last stage's stores need no global load each
   uint8_t* rfl = reinterpret_cast<uint8_t*>(smem + align16(sizeof(V) * L) + align16(sizeof(V) * L * W));
@@ -563,7 +567,7 @@ __global__ __launch_bounds__(kThreadsP<INV>) void k_pencil(
   // view (and its flag view) and are dropped; columns >= H are masked by kNoOff
   constexpr int T = kThreadsP<INV>;
   auto load = [&](int i0, int i1, int p) -> V {
-    const uint32_t b = kx0 + p < H ? offv<V>(i0, rsb, p) : kNoOff;
+    const uint32_t b = offv_if<V>(kx0 + p < H, i0, rsb, p);
     return src.template ldv<V, true>(b + (uint32_t)i1 * rsb);
   };
   auto store = [&](int k0, int k1, int p, V v, int) {
@@ -571,7 +575,7 @@ __global__ __launch_bounds__(kThreadsP<INV>) void k_pencil(
     if (c < 0) c += L;
     bool keep = kx0 + p < H;
     if constexpr (INV) keep = keep & (!rowfl | (rfl[c] != 0));   // the flag region exists for the inverse
-    dst.template stv<V>(keep ? offv<V>(c, rsb, p) : kNoOff, v);
+    dst.template stv<V>(offv_if<V>(keep, c, rsb, p), v);
   };
   if (kx0 != 0) {
     fft_io<LC, W, T, INV, false, false, W, HALF>(buf, tw, pl, load, store);
@@ -593,7 +597,7 @@ __global__ __launch_bounds__(kThreadsP<INV>) void k_pencil(
         v = c < half ? cplx<V>(S(0.5) * (v.x + m.x), S(0.5) * (v.y - m.y))
                      : cplx<V>(S(0.5) * (v.y + m.y), S(0.5) * (v.x - m.x));
       }
-      dst.template stv<V>(kx0 + p < H ? offv<V>(c, rsb, p) : kNoOff, v);
+      dst.template stv<V>(offv_if<V>(kx0 + p < H, c, rsb, p), v);
     }
   } else {
     // inverse: the input rows are S_D(ky) for ky < L/2 and S_N(L - ky) above (rows 0 and
@@ -606,7 +610,7 @@ __global__ __launch_bounds__(kThreadsP<INV>) void k_pencil(
           const V s = load(i0, i1, p);
           const int i = i0 + i1;
           const bool mix = p == 0 && i != 0 && i != half;
-          const V m = src.template ldv<V, false>(mix ? offv<V>(L - i, rsb, 0) : kNoOff);
+          const V m = src.template ldv<V, false>(offv_if<V>(mix, L - i, rsb, 0));
           const V g = i < half ? cplx<V>(s.x - m.y, s.y + m.x) : cplx<V>(m.x + s.y, s.x - m.y);
           return mix ? g : s;
         },
@@ -655,7 +659,7 @@ __global__ __launch_bounds__(kThreadsZ) void k_zpass(
     kx0 = tile * W;
     if (kx0 == 0 && (ky == 0 || 2 * ky == Py)) return;   // done by the PACKED launch
   }
-  load_twiddles(tw, twtab, pl);
+  load_twiddles<LC>(tw, twtab, pl);
   if (LC == 0) __syncthreads();
   const long long fstride_x2 = (long long)nz * Py * Hp;
   const long long fstride_sp = (long long)Pz * Py * Hp;
@@ -668,7 +672,7 @@ __global__ __launch_bounds__(kThreadsZ) void k_zpass(
   auto spec_view = [&](int f) { return RView(spec + f * fstride_sp + col0, (long long)sizeof(V) * (fstride_sp - col0)); };
   auto loader = [&](const RView& src) {
     return [&src, kx0, H, zsb](int i0, int i1, int p) -> V {
-      const uint32_t b = kx0 + p < H ? offv<V>(i0, zsb, p) : kNoOff;
+      const uint32_t b = offv_if<V>(kx0 + p < H, i0, zsb, p);
       return src.template ldv<V, true>(b + (uint32_t)i1 * zsb);
     };
   };
@@ -683,7 +687,7 @@ __global__ __launch_bounds__(kThreadsZ) void k_zpass(
       fft_io<LC, W, kThreadsZ, false, false, false, W, HALF>(
           buf, tw, pl, loader(src),
           [&](int k0, int k1, int p, V v, int sl) {
-            const uint32_t b = kx0 + p < H ? offv<V>(k0, zsb, p) : kNoOff;
+            const uint32_t b = offv_if<V>(kx0 + p < H, k0, zsb, p);
             const V sv = a.template ldv<V, false>(b + (uint32_t)k1 * zsb);
             acc[sl].x = fmadd(v.x, sv.x, fmadd(-v.y, sv.y, acc[sl].x));
             acc[sl].y = fmadd(v.x, sv.y, fmadd(v.y, sv.x, acc[sl].y));
@@ -719,7 +723,7 @@ __global__ __launch_bounds__(kThreadsZ) void k_zpass(
         if (e < Pz * W) {
           const int kz = e / W, p = e - kz * W;
           const V v = buf[e];
-          const V sk = a.template ldv<V, false>(kx0 + p < H ? offv<V>(kz, zsb, p) : kNoOff);
+          const V sk = a.template ldv<V, false>(offv_if<V>(kx0 + p < H, kz, zsb, p));
           if (p != 0) {
             acc[u].x = fmadd(v.x, sk.x, fmadd(-v.y, sk.y, acc[u].x));
             acc[u].y = fmadd(v.x, sk.y, fmadd(v.y, sk.x, acc[u].y));
@@ -771,7 +775,7 @@ __global__ __launch_bounds__(kThreadsZ) void k_zpass(
         int c = k0 + k1 - out_off;
         if (c < 0) c += Pz;
         const bool keep = (kx0 + p < H) & (zfl[c] != 0);   // no short-circuit: no branch per element
-        dst.template stv<V>(keep ? offv<V>(c, zsb, p) : kNoOff, v);
+        dst.template stv<V>(offv_if<V>(keep, c, zsb, p), v);
       });
 }
 
@@ -790,7 +794,7 @@ __global__ __launch_bounds__(kThreads) void k_zstore(
   const int kx0 = blockIdx.x * W;
   const int ky = blockIdx.y;
   const int f = blockIdx.z;
-  load_twiddles(tw, twtab, pl);
+  load_twiddles<LC>(tw, twtab, pl);
   if (LC == 0) __syncthreads();
   const long long zs = (long long)Py * Hp;
   const V* src = X2 + (long long)f * nz * zs + (long long)ky * Hp + kx0;
@@ -1167,7 +1171,7 @@ __global__ __launch_bounds__(kThreadsC) void k_final_x(
     if (m) atomicMax(keys + slot, m);
   }
   };
-  load_twiddles(tw, twtab, pl);
+  load_twiddles<LC>(tw, twtab, pl);
   if constexpr (WRITE_MAP) {
     // every row group, one per workgroup (a map entry is written for every displacement)
     run((int)blockIdx.z, (int)blockIdx.y, (int)blockIdx.x * NR);
@@ -1209,7 +1213,7 @@ __global__ __launch_bounds__(kThreadsM) void k_mask_x(const uint8_t* __restrict_
   const int slot = blockIdx.z;
   const int q0 = blockIdx.x * W;   // first row pair of this workgroup
   const int nrow = ny - 2;         // interior rows 1 .. ny - 2
-  load_twiddles(tw, twtab, pl);
+  load_twiddles<LC>(tw, twtab, pl);
   if (LC == 0) __syncthreads();
   const RView m(mask + slot * mask_sstride + (long long)z * ny * nx, (long long)ny * nx);
   auto rows = [&](int i0, int i1, int p) -> double2 {
@@ -1232,8 +1236,8 @@ __global__ __launch_bounds__(kThreadsM) void k_mask_x(const uint8_t* __restrict_
     const int row = (z - 1) * nrow + r;
     const double2 fa = k ? cplx<double2>(0.5 * (zk.x + zc.x), 0.5 * (zk.y - zc.y)) : cplx<double2>(zk.x, zc.x);
     const double2 fb = k ? cplx<double2>(0.5 * (zk.y + zc.y), 0.5 * (zc.x - zk.x)) : cplx<double2>(zk.y, zc.y);
-    dst.stv<double2>(r < nrow ? offv<double2>(row, rsb, k) : kNoOff, fa);
-    dst.stv<double2>(r + 1 < nrow ? offv<double2>(row + 1, rsb, k) : kNoOff, fb);
+    dst.stv<double2>(offv_if<double2>(r < nrow, row, rsb, k), fa);
+    dst.stv<double2>(offv_if<double2>(r + 1 < nrow, row + 1, rsb, k), fb);
   }
 }
 
@@ -1264,7 +1268,7 @@ __global__ __launch_bounds__(kThreadsC) void k_overlap_x(const double2* __restri
     for (int rr = 0; rr < NR; ++rr) fmask |= fl[rr] ? 1u << rr : 0u;
   }
   if (!fmask) return;
-  load_twiddles(tw, twtab, pl);
+  load_twiddles<LC>(tw, twtab, pl);
   if (LC == 0) __syncthreads();
   const int half = Px / 2;
   const RView rows(Y4 + slot * y4_sstride + ((long long)zc * Wy) * Hp, 16LL * Wy * Hp);
@@ -1411,7 +1415,7 @@ __global__ __launch_bounds__(kThreadsP<INV>) void k_debug_fft(const float2* __re
   float2* tw = reinterpret_cast<float2*>(smem);
   float2* buf = reinterpret_cast<float2*>(smem + align16(sizeof(float2) * L));
   const int b0 = blockIdx.x * W;
-  load_twiddles(tw, twtab, pl);
+  load_twiddles<LC>(tw, twtab, pl);
   if (LC == 0) __syncthreads();
   fft_io<LC, W, kThreadsP<INV>, INV, false, false>(
       buf, tw, pl,

@@ -330,6 +330,8 @@ def main():
                     help="oracle sample: rotations timed (median), on all threads and on one (0 = skip)")
     ap.add_argument("--plain-rotations", type=int, default=64,
                     help="rotations timed on the one-rotation-per-launch path (0 = skip)")
+    ap.add_argument("--fp64-rotations", type=int, default=96,
+                    help="rotations timed with the FP64 correlation (CSNGF_FP64); 0 skips")
     ap.add_argument("--usngf-rotations", type=int, default=200,
                     help="rotations timed with the unsquared measure, Eq. (3) (0 = skip)")
     ap.add_argument("--align-runs", type=int, default=5,
@@ -466,6 +468,20 @@ def main():
             usngf = len(ur) / (time.perf_counter() - ts)
         print(f"[bench] unsquared measure {usngf:.1f} rot/s", file=sys.stderr, flush=True)
 
+    fp64 = None
+    if args.fp64_rotations > 0:
+        # the same workload with the transforms in FP64 (CSNGF_FP64): the exact-at-small-overlap mode
+        with bd.Context(A, pair.dims_b, pad=pair.pad, batch=args.batch, fp64=True) as dctx:
+            dr = rots[:args.fp64_rotations]
+            dctx.evaluate(B, dr[:8])
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            dctx.evaluate(B, dr)
+            torch.cuda.synchronize()
+            fp64 = len(dr) / (time.perf_counter() - ts)
+            fp64_slots = dctx.info().batch
+        print(f"[bench] FP64 correlation {fp64:.1f} rot/s ({fp64_slots} slots)", file=sys.stderr, flush=True)
+
     align_stats = None
     if args.align_runs > 0:
         from paper_2110_10156_amd import align as al
@@ -531,6 +547,7 @@ def main():
                        "what": f"one csngf_evaluate call of {len(rots)} rotations, host to host"},
         "plain_rotations_per_s": None if plain is None else round(plain, 2),
         "usngf_rotations_per_s": None if usngf is None else round(usngf, 2),
+        "fp64_rotations_per_s": None if fp64 is None else round(fp64, 2),
         "path_bytes_per_rotation": yard,
         "path_bytes_kept_rows": kept is not None,
         "path_hbm_frac": round(yard * value / (HBM_PEAK_GBS * 1e9), 4),

@@ -211,8 +211,9 @@ def many_pairs(torch, bd, synth, big_pair, n_pairs, n_rot, budget_gib=160.0):
     Sequential: pair after pair, one synchronous evaluation each, default parameters (the
     evaluation calls are timed, context creation is not).
     Concurrent: all contexts alive, each on its own stream, every evaluation in flight at
-    once, graph replay, autotuned (P, slots) with slots capped to an equal share of
-    budget_gib of HBM per context."""
+    once, graph replay, autotuned (P, slots, launch shapes); if the contexts' workspaces
+    together exceed budget_gib of HBM, every context's slots are scaled down alike.
+    Per size: the sequential rate and the autotuned rate of one pair alone (graphs)."""
     dev = torch.device("cuda:0")
     sizes = [synth.MIXED_SHAPES[int(np.random.default_rng(3000 + i).integers(0, len(synth.MIXED_SHAPES)))]
              for i in range(n_pairs)]
@@ -221,20 +222,25 @@ def many_pairs(torch, bd, synth, big_pair, n_pairs, n_rot, budget_gib=160.0):
         p = big_pair if sz == big_pair.dims_a else synth.mixed_pair_of_size(sz)
         vols[sz] = (torch.from_numpy(p.A).to(dev), torch.from_numpy(p.B).to(dev))
     rots = [synth.random_rotations(n_rot, 5000 + i) for i in range(n_pairs)]
-    tuned, share = {}, budget_gib * 2**30 / n_pairs
+    tuned, tuned_rate, mem = {}, {}, {}
     for sz in sorted(set(sizes)):
         A, B = vols[sz]
-        cfg, _ = bd.autotune(A, B, n_probe=64, graphs=True)
+        cfg, rate = bd.autotune(A, B, n_probe=64, graphs=True)
         with bd.Context(A, bd.dims_of(B), pad=cfg["pad"], batch=1) as c1:
-            per_slot = c1.info().workspace_bytes
-        cfg["batch"] = int(max(1, min(cfg["batch"], share // per_slot)))
-        tuned[sz] = cfg
+            mem[sz] = (c1.info().spectra_bytes, c1.info().workspace_bytes)
+        tuned[sz], tuned_rate[sz] = cfg, rate
+    need = sum(mem[sz][0] + tuned[sz]["batch"] * mem[sz][1] for sz in sizes)
+    scale = min(1.0, budget_gib * 2**30 / need)
+    for sz in tuned:
+        tuned[sz]["batch"] = int(max(1, tuned[sz]["batch"] * scale))
     torch.cuda.synchronize()
+    key = lambda s: f"{s[0]}x{s[1]}x{s[2]}"
     out = {"pairs": n_pairs, "rotations_per_pair": n_rot,
-           "sizes": {f"{s[0]}x{s[1]}x{s[2]}": sizes.count(s) for s in sorted(set(sizes))},
-           "concurrent_params": {f"{s[0]}x{s[1]}x{s[2]}": tuned[s] for s in sorted(set(sizes))}}
+           "sizes": {key(s): sizes.count(s) for s in sorted(set(sizes))},
+           "concurrent_params": {key(s): tuned[s] for s in sorted(set(sizes))},
+           "slot_scale": round(scale, 3)}
     # sequential
-    total = 0.0
+    total, per_size = 0.0, {}
     for sz, r in zip(sizes, rots):
         A, B = vols[sz]
         with bd.Context(A, bd.dims_of(B)) as c:
@@ -242,9 +248,28 @@ def many_pairs(torch, bd, synth, big_pair, n_pairs, n_rot, budget_gib=160.0):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             c.evaluate(B, r)
-            total += time.perf_counter() - t0
+            dt = time.perf_counter() - t0
+            total += dt
+            per_size.setdefault(sz, []).append(dt)
     out["sequential_rotations_per_s"] = round(n_pairs * n_rot / total, 1)
     print(f"[bench] many pairs sequential: {n_pairs * n_rot / total:.1f} rot/s", file=sys.stderr, flush=True)
+    # one pair of each size alone with its tuned configuration (graphs, unscaled slots)
+    alone = {}
+    for sz in sorted(set(sizes)):
+        A, B = vols[sz]
+        cfg = dict(tuned[sz])
+        cfg["batch"] = int(round(cfg["batch"] / scale)) if scale < 1.0 else cfg["batch"]
+        with bd.Context(A, bd.dims_of(B), graphs=True, **cfg) as c:
+            r = rots[sizes.index(sz)]
+            c.evaluate(B, r[:c.info().batch])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            c.evaluate(B, r)
+            alone[sz] = n_rot / (time.perf_counter() - t0)
+    out["per_size"] = {key(s): {"sequential_rotations_per_s": round(len(per_size[s]) * n_rot / sum(per_size[s]), 1),
+                                "tuned_alone_rotations_per_s": round(alone[s], 1),
+                                "autotune_probe_rotations_per_s": round(tuned_rate[s], 1)}
+                       for s in sorted(set(sizes))}
     # concurrent
     ctxs = [bd.Context(vols[sz][0], bd.dims_of(vols[sz][1]), graphs=True, **tuned[sz]) for sz in sizes]
     for c, sz, r in zip(ctxs, sizes, rots):            # warm-up: graph recording, first launches

@@ -1141,11 +1141,17 @@ __global__ __launch_bounds__(kThreadsC) void k_final_x(
       int n;
       if constexpr (NCOUNT)   // rows without a flag hold no valid displacement and no counts
         n = (WRITE_MAP || ((fmask >> rr) & 1u)) ? nrows[(long long)yc * Wx + cx] : 0;
-      else
-        n = (lx <= hx) ? drow[rr * X1 + hx + 1] - drow[rr * X1 + lx] : 0;
+      else {
+        // (both reads stay in row rr: an empty range reads column 0 twice)
+        const bool any = lx <= hx;
+        const int d1 = drow[mad24u((unsigned)rr, X1, any ? (unsigned)hx + 1 : 0u)];
+        const int d0 = drow[mad24u((unsigned)rr, X1, any ? (unsigned)lx : 0u)];
+        n = any ? d1 - d0 : 0;
+      }
       const bool valid = n >= thr;
       const float c = valid ? (float)(sv / (S)n) : -INFINITY;
-      const unsigned int canon = (unsigned)((zc * Wy + yc) * Wx + cx);
+      // (zc Wy + yc < 2^24 and Wx < 2^24: a 24-bit multiply-add)
+      const unsigned int canon = mad24u((unsigned)(zc * Wy + yc), Wx, (unsigned)cx);
       if (valid) {
         const unsigned long long key = ((unsigned long long)ordered_bits(c) << 32) | (0xFFFFFFFFu - canon);
         best = key > best ? key : best;

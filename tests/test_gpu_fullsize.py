@@ -2,8 +2,10 @@
 compile-time radix-11 plans), in the launch configuration the benchmark times (automatic
 rotation slots, several launch sequences per call).  One rotation's whole displacement map
 (351 x 351 x 219 = 27 M entries) is compared element by element with the FP64 oracle's map,
-for the squared measure and for the unsquared one (Eq. (3)); further checks use outputs the
-oracle computes one at a time and properties that hold at any size.
+for the squared measure and for the unsquared one (Eq. (3)); every one of the 33 rotations'
+results (32 random and the generating one) is compared with the oracle's, with and without a
+user mask on A; further checks use outputs the oracle computes one at a time and properties
+that hold at any size.
 
 Bar as in test_gpu_parity: N exact, validity identical, |dC| <= 1e-4 on valid
 displacements, argmax identical unless the oracle's best and runner-up are within 2e-4.
@@ -21,7 +23,7 @@ pytestmark = pytest.mark.gpu
 
 CTOL = 1e-4
 TIE = 2e-4
-N_RANDOM = 16   # + the true rotation at index 16: 17 rotations = one full batch and a partial one
+N_RANDOM = 32   # + the true rotation at index 32: 33 rotations = two full batches of 16 and a partial one
 MAP_ROT = 5     # rotation whose full map is pulled back and sampled
 
 
@@ -163,11 +165,10 @@ def _head_mask(shape, seed=17):
 def test_user_mask_on_a_full_map_and_rotations_against_oracle(full):
     """Sec. 3.1, Eq. (4)-(5) at paper scale with a user mask on A (FP64 overlap chain, automatic
     slots, two launch sequences): the whole map of one rotation element by element (N exact,
-    validity identical, 1e-4), and 3 rotations' results against the oracle's maps."""
-    from parity_util import check_against_oracle
+    validity identical, 1e-4), and every rotation's result against the oracle."""
+    from parity_util import check_against_oracle_parallel
     pair = full["pair"]
     mask_a = _head_mask(pair.A.shape)
-    idx = [0, MAP_ROT, N_RANDOM]
     with bd.Context(pair.A, pair.dims_b, pad=pair.pad, mask_a=mask_a) as ctx:
         info = ctx.info()
         _say("mask on A at full size: slots", info.batch, "count_a", info.count_a)
@@ -176,12 +177,8 @@ def test_user_mask_on_a_full_map_and_rotations_against_oracle(full):
     res, _ = O.evaluate(pair.A, pair.B, pair.rotations[MAP_ROT:MAP_ROT + 1], mask_a=mask_a.astype(bool),
                         P_xyz=pair.pad, keep_maps=True)
     _compare_maps(Cg, Ng, res[0].C, res[0].N, "config2-maskA-map")
-    sub = [per[i] for i in idx]
-    sb = bd.Best()
-    k = max(range(len(idx)), key=lambda j: (sub[j].valid, sub[j].score, -j))
-    sb.rot_index, sb.score = k, sub[k].score
-    sb.shift[:] = list(sub[k].shift)
-    check_against_oracle(pair.A, pair.B, pair.rotations[idx], sub, sb, P=pair.pad, mask_a=mask_a.astype(bool))
+    check_against_oracle_parallel(pair.A, pair.B, pair.rotations, per, best, P=pair.pad, mask_a=mask_a.astype(bool))
+    _say("mask on A: all", len(per), "rotations match the oracle")
 
 
 def test_fp64_correlation_at_paper_scale(full, oracle_map):
@@ -196,25 +193,12 @@ def test_fp64_correlation_at_paper_scale(full, oracle_map):
     assert float(np.max(np.abs(Cg[v] - full["C"][v]))) <= 1e-6
 
 
-@pytest.mark.parametrize("r", [0, N_RANDOM])
-def test_per_rotation_results_against_oracle(full, r):
-    """Whole-map oracle (FP64 FFT route) for single rotations of the batch, including the
-    true one and one that sits in the second launch sequence."""
-    pair, per = full["pair"], full["per"]
-    res, _ = O.evaluate(pair.A, pair.B, pair.rotations[r:r + 1], P_xyz=pair.pad, keep_maps=True)
-    o = res[0]
-    g = per[r]
-    assert bool(g.valid) == bool(o.valid)
-    if not o.valid:
-        return
-    assert abs(float(g.score) - o.score) <= CTOL, (r, float(g.score), o.score)
-    Co = o.C
-    vo = np.isfinite(Co)
-    top = np.sort(Co[vo])[::-1][:2]
-    if top.size < 2 or top[0] - top[1] >= TIE:
-        assert tuple(g.shift) == o.shift and g.overlap == o.overlap, (r, tuple(g.shift), o.shift)
-    else:
-        nza, nya, nxa = pair.A.shape
-        sx, sy, sz = g.shift
-        assert Co[sz + nza - 1, sy + nya - 1, sx + nxa - 1] >= o.score - TIE
-    _say("rotation", r, "score", float(g.score), "shift", tuple(g.shift))
+def test_every_rotation_against_oracle(full):
+    """All 33 rotations of the benchmark's launch configuration (two full launch sequences and a
+    partial one) against the oracle's whole FP64 map of each: validity, score within 1e-4,
+    displacement identical unless the oracle's top two are within 2e-4, N exact at the
+    reported displacement, and the overall best (rotation, displacement)."""
+    from parity_util import check_against_oracle_parallel
+    pair = full["pair"]
+    check_against_oracle_parallel(pair.A, pair.B, pair.rotations, full["per"], full["best"], P=pair.pad)
+    _say("all", len(full["per"]), "rotations match the oracle")

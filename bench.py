@@ -213,6 +213,7 @@ def many_pairs(torch, bd, synth, big_pair, n_pairs, n_rot, budget_gib=160.0):
     Concurrent: all contexts alive, each on its own stream, every evaluation in flight at
     once, graph replay, autotuned (P, slots, launch shapes); if the contexts' workspaces
     together exceed budget_gib of HBM, every context's slots are scaled down alike.
+    Sequential, tuned: the concurrent mode's contexts, one pair after another.
     Per size: the sequential rate and the autotuned rate of one pair alone (graphs)."""
     dev = torch.device("cuda:0")
     sizes = [synth.MIXED_SHAPES[int(np.random.default_rng(3000 + i).integers(0, len(synth.MIXED_SHAPES)))]
@@ -281,10 +282,18 @@ def many_pairs(torch, bd, synth, big_pair, n_pairs, n_rot, budget_gib=160.0):
     for c in ctxs:
         c.wait()
     dt = time.perf_counter() - t0
-    for c in ctxs:
-        c.close()
     out["concurrent_rotations_per_s"] = round(n_pairs * n_rot / dt, 1)
     print(f"[bench] many pairs concurrent: {n_pairs * n_rot / dt:.1f} rot/s", file=sys.stderr, flush=True)
+    # the same contexts (tuned, graphs) one pair after another
+    t0 = time.perf_counter()
+    for c, sz, r in zip(ctxs, sizes, rots):
+        c.evaluate(vols[sz][1], r)
+    dt = time.perf_counter() - t0
+    for c in ctxs:
+        c.close()
+    out["sequential_tuned_rotations_per_s"] = round(n_pairs * n_rot / dt, 1)
+    print(f"[bench] many pairs sequential, tuned + graphs: {n_pairs * n_rot / dt:.1f} rot/s", file=sys.stderr,
+          flush=True)
     return out
 
 

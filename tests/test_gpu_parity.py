@@ -177,6 +177,36 @@ def test_random_small_pairs_full_maps(case):
         assert per[0].score == Cg.flat[flat] and per[0].overlap == Ng.flat[flat]
 
 
+@pytest.mark.parametrize("sa,sb,pz", [((20, 18, 40), (22, 17, 38), 88), ((24, 20, 30), (21, 23, 50), 88),
+                                      ((24, 20, 40), (21, 23, 50), 110), ((16, 16, 30), (16, 16, 30), 176)])
+def test_compile_time_z_plans_with_radix_11_first(sa, sb, pz):
+    """z lengths whose compile-time plan starts with radix 11 (88, 110, 176, like the
+    paper-scale 220), with B's interior z extent at most half the length (first stage pruned to
+    6 inputs) and above it (the second case: 48 > 44, all 11 inputs), ragged x and y tiles; one
+    rotated map and the per-rotation result against the oracle."""
+    rng = np.random.default_rng(pz + sa[0])
+    from scipy.ndimage import gaussian_filter
+    shape_a, shape_b = sa[::-1], sb[::-1]    # (z, y, x) arrays of x, y, z extents
+    A = gaussian_filter(rng.random(shape_a), 1.0).astype(np.float32)
+    B = gaussian_filter(rng.random(shape_b), 1.0).astype(np.float32)
+    R = _rand_rot(rng, 35)
+    need = [sa[i] + sb[i] - 1 for i in range(3)]
+    assert need[2] <= pz
+    pad = (0, 0, pz)
+    with bd.Context(A, bd.dims_of(B), pad=pad) as ctx:
+        P = tuple(ctx.info().pad)
+        assert P[2] == pz
+        Cg, Ng = ctx.evaluate_map(B, R)
+        per, best = ctx.evaluate(B, np.stack([R, np.eye(3)]))
+    _say("radix-11 z plan", sa, sb, P)
+    Co, No, _ = _oracle_maps(A, B, R, None, 0.5, P)
+    _compare_maps(Cg, Ng, Co, No, f"z{pz}")
+    if np.isfinite(Cg).any():
+        flat = int(np.argmax(np.where(np.isfinite(Cg), Cg, -np.inf)))
+        iz, iy, ix = np.unravel_index(flat, Cg.shape)
+        assert tuple(per[0].shift) == (ix - (sa[0] - 1), iy - (sa[1] - 1), iz - (sa[2] - 1))
+
+
 def test_large_xy_extent_full_maps():
     """A 256 x 256 cross-section: FFT length 512 along x and y (the largest supported; run-time
     plans), slice prefix sums above 16 bits, and the field stage's widest rows."""

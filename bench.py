@@ -65,6 +65,52 @@ def kernel_bytes(nA, nB, P, rotations_per_launch=1.0, kept=None):
     }
 
 
+# FP32 vector peak without packed FP32 (which this code does not use): 256 CUs x 4 SIMDs x 16
+# lanes x 2 flop (fma) x 2.4 GHz
+VALU_FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+
+
+def plan_radices(L):
+    """The FFT engine's factorisation of L: odd radices first (11, 7, 5, 3), then 8, 4, 2."""
+    n, rs = L, []
+    for q in (11, 7, 5, 3, 8, 4, 2):
+        while n % q == 0:
+            rs.append(q)
+            n //= q
+    return rs
+
+
+def dft_flops(R, pruned):
+    """Real flops of one radix-R butterfly as the engine computes it (fma = 2); pruned: the
+    upper half of the inputs is zero (first stage of a zero-padded transform)."""
+    if R == 2:
+        return 0 if pruned else 4
+    if R == 4:
+        return 8 if pruned else 16
+    if R == 8:
+        return 40 if pruned else 56
+    h = (R - 1) // 2    # odd R: pairs x_m with x_(R-m)
+    return (6 if pruned else 10) * h + 8 * h * h
+
+
+def transform_flops(L, pruned_first):
+    """Flops of one length-L complex transform: butterflies plus twiddle products (6 flops
+    each) at every stage after the first."""
+    f, ns = 0, 1
+    for s, R in enumerate(plan_radices(L)):
+        f += (L // R) * (dft_flops(R, pruned_first and s == 0) + (6 * (R - 1) if ns > 1 else 0))
+        ns *= R
+    return f
+
+
+def zpass_flops(nB, P, nf=6):
+    """Algorithmic flops per rotation of the z pass: for every (ky, kx) pencil, nf pruned
+    forward transforms, nf complex multiply-accumulates per bin, one full inverse."""
+    Px, Py, Pz = P
+    pruned = 2 * (nB[2] - 2) <= Pz
+    return Py * (Px // 2) * (nf * (transform_flops(Pz, pruned) + 8 * Pz) + transform_flops(Pz, False))
+
+
 def survey_yardstick(nA, nB, P):
     """The fixed per-rotation byte model of the method as the paper states it (Sec. 3.1: 7
     forward and 2 inverse zero-padded real 3-D FFTs per rotation with A's 7 spectra cached and
@@ -442,7 +488,7 @@ def main():
     elapsed = t1 - t0
     value = args.steps * len(rots) / elapsed
 
-    roofline = roofline_fields = None
+    roofline = roofline_fields = roofline_valu = None
     kept = None
     seq_rot = len(rots) / math.ceil(len(rots) / slots)   # mean rotations per launch sequence
     if stats:
@@ -476,6 +522,18 @@ def main():
                                                   * (pair.dims_a[1] + pair.dims_b[1] - 1)}
         if stats.get("fields_x", (0, 0))[0] > 0:
             roofline_fields = roof("fields_x")
+        if stats.get("z_mac_inverse", (0, 0))[0] > 0:
+            # the z pass is bound by vector-ALU issue (counter summary): its arithmetic against
+            # the FP32 vector peak without packed math
+            launches, ms = stats["z_mac_inverse"]
+            per_launch_rot = len(rots) * args.steps / launches
+            fl = zpass_flops(pair.dims_b, tuple(info.pad)) * per_launch_rot
+            tf = fl / (ms / launches / 1e3) / 1e12
+            roofline_valu = {"bound": "alu", "achieved": round(tf, 2), "peak": round(VALU_FP32_PEAK_TFLOPS, 2),
+                             "unit": "TFLOP/s", "frac": round(tf / VALU_FP32_PEAK_TFLOPS, 4),
+                             "kernel": "z_mac_inverse", "alg_flops_per_launch": fl,
+                             "peak_what": "FP32 vector fma, packed FP32 not used: 256 CUs x 4 SIMDs x 16 lanes x "
+                                          "2 flop x 2.4 GHz"}
         print(f"[bench] kernel ms/rotation: {roofline['kernels_ms_per_rotation']}", file=sys.stderr, flush=True)
 
     plain = None
@@ -594,6 +652,7 @@ def main():
         "best": {"rot_index": best.rot_index, "shift": list(best.shift), "score": best.score},
         "roofline": roofline,
         "roofline_field_stage": roofline_fields,
+        "roofline_z_pass_valu": roofline_valu,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -109,7 +109,11 @@ class GpuEvaluator:
         return tA, tB
 
     def score(self, Ak, Bk, Rs):
-        with self.bd.Context(Ak, self.bd.dims_of(Bk), gamma=self.gamma, eps=self.eps, measure=self.measure) as ctx:
+        # a level with few candidates (the last re-scores 1) needs no more rotation slots than
+        # it has rotations; otherwise the library sizes the slots
+        slots = len(Rs) if len(Rs) < 16 else 0
+        with self.bd.Context(Ak, self.bd.dims_of(Bk), gamma=self.gamma, eps=self.eps, measure=self.measure,
+                             batch=slots) as ctx:
             per, _ = ctx.evaluate(Bk, Rs)
         return ([p.score if p.valid else -np.inf for p in per], [tuple(p.shift) for p in per])
 

@@ -54,14 +54,15 @@ class AlignResult:
 
 
 def candidates(starts, u, a, rng):
-    """The starting points themselves (re-scored, Sec. 3.2) followed by a random perturbations."""
+    """The starting points themselves (re-scored, Sec. 3.2) followed by a random perturbations,
+    each of a starting point drawn uniformly (drawn as arrays: a level has thousands)."""
     starts = [tuple(float(v) for v in s) for s in starts]
-    out = list(starts)
-    for _ in range(int(a)):
-        base = starts[int(rng.integers(0, len(starts)))]
-        r = rng.uniform(-u, u, size=3)
-        out.append(tuple(base[i] + float(r[i]) for i in range(3)))
-    return out
+    a = int(a)
+    if a <= 0:
+        return list(starts)
+    idx = rng.integers(0, len(starts), size=a)
+    pert = np.asarray(starts, dtype=np.float64)[idx] + rng.uniform(-u, u, size=(a, 3))
+    return starts + [tuple(row) for row in pert.tolist()]
 
 
 def top_p(scores, p):
@@ -112,8 +113,9 @@ class GpuEvaluator:
         # a level with few candidates (the last re-scores 1) needs no more rotation slots than
         # it has rotations; otherwise the library sizes the slots
         slots = len(Rs) if len(Rs) < 16 else 0
+        # (graph replay: a level runs tens of identical launch sequences)
         with self.bd.Context(Ak, self.bd.dims_of(Bk), gamma=self.gamma, eps=self.eps, measure=self.measure,
-                             batch=slots) as ctx:
+                             batch=slots, graphs=True) as ctx:
             per, _ = ctx.evaluate(Bk, Rs)
         return ([p.score if p.valid else -np.inf for p in per], [tuple(p.shift) for p in per])
 
@@ -133,7 +135,7 @@ def align(A, B, schedule=PAPER_SCHEDULE, seed=0, evaluator=None):
         d, sigma, u, a = schedule["d"][k], schedule["sigma"][k], schedule["u"][k], schedule["a"][k]
         Ak, Bk = ev.level(A, B, sigma, d)
         thetas = candidates(starts, u, a, rng)
-        Rs = np.stack([synth.euler_xyz_matrix(*t) for t in thetas])
+        Rs = synth.euler_xyz_matrices(thetas)
         scores, shifts = ev.score(Ak, Bk, Rs)
         p_next = schedule["p"][k + 1] if k + 1 < m else 1
         keep = top_p(scores, p_next)

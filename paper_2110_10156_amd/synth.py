@@ -28,7 +28,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 __all__ = [
-    "quat_to_matrix", "axis_angle_matrix", "euler_xyz_matrix", "random_rotations",
+    "quat_to_matrix", "axis_angle_matrix", "euler_xyz_matrix", "euler_xyz_matrices", "random_rotations",
     "intensity_map_f", "VolumePair", "config0", "config1", "config2", "cube_pair",
     "mixed_pair", "mixed_pair_of_size", "MIXED_SHAPES",
 ]
@@ -64,6 +64,22 @@ def euler_xyz_matrix(ax_deg: float, ay_deg: float, az_deg: float) -> np.ndarray:
     rx = axis_angle_matrix([1, 0, 0], math.radians(ax_deg))
     ry = axis_angle_matrix([0, 1, 0], math.radians(ay_deg))
     rz = axis_angle_matrix([0, 0, 1], math.radians(az_deg))
+    return rx @ ry @ rz
+
+
+def euler_xyz_matrices(angles_deg) -> np.ndarray:
+    """euler_xyz_matrix for every row (theta_x, theta_y, theta_z) of an (n, 3) array of degrees,
+    as one (n, 3, 3) array (the rotations about the three axes built in closed form)."""
+    t = np.radians(np.asarray(angles_deg, dtype=np.float64).reshape(-1, 3))
+    c, s = np.cos(t), np.sin(t)
+    n = t.shape[0]
+    one, zero = np.ones(n), np.zeros(n)
+    rx = np.stack([np.stack([one, zero, zero], -1), np.stack([zero, c[:, 0], -s[:, 0]], -1),
+                   np.stack([zero, s[:, 0], c[:, 0]], -1)], -2)
+    ry = np.stack([np.stack([c[:, 1], zero, s[:, 1]], -1), np.stack([zero, one, zero], -1),
+                   np.stack([-s[:, 1], zero, c[:, 1]], -1)], -2)
+    rz = np.stack([np.stack([c[:, 2], -s[:, 2], zero], -1), np.stack([s[:, 2], c[:, 2], zero], -1),
+                   np.stack([zero, zero, one], -1)], -2)
     return rx @ ry @ rz
 
 

@@ -42,3 +42,13 @@ def test_config1_truth_appended():
     assert p.A.shape == (64, 96, 96) and p.rotations.shape == (5, 3, 3)
     assert p.true_index == 4 and np.array_equal(p.rotations[4], p.true_rotation)
     assert all(-15 <= v <= 15 for v in p.true_shift)
+
+
+def test_euler_matrices_vectorised_equals_single():
+    rng = np.random.default_rng(9)
+    ang = rng.uniform(-200.0, 200.0, size=(50, 3))
+    many = synth.euler_xyz_matrices(ang)
+    one = np.stack([synth.euler_xyz_matrix(*a) for a in ang])
+    assert many.shape == (50, 3, 3)
+    assert np.max(np.abs(many - one)) < 1e-14
+    assert np.allclose(many @ np.transpose(many, (0, 2, 1)), np.eye(3), atol=1e-14)

@@ -30,8 +30,12 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "rotations/s at 3.4 Mvoxel (full displacement map); p50/p99 alignment latency"
 
 
-def kernel_bytes(nA, nB, P, rotations_per_launch=1.0, kept=None):
+def kernel_bytes(nA, nB, P, rotations_per_launch=1.0, kept=None, runs=True):
     """Algorithmic HBM bytes per rotation of each kernel family (complex64 = 8 B).
+
+    runs: no user mask on either side, so the moving masks are runs of x per grid row found
+    from the rotation (8 B per row) and the field stage writes no mask; otherwise the field
+    stage writes the eroded mask (1 B per voxel) and the overlap table reads it.
 
     Pruned pencils: only nonzero input rows are read, H = Px/2 bins per row (the real DC and
     Nyquist bins share one complex value).  A's six conjugate spectra are read once per
@@ -55,9 +59,10 @@ def kernel_bytes(nA, nB, P, rotations_per_launch=1.0, kept=None):
     y4 = kr * H * 8                     # after the y inverse (kept rows)
     sat = 4 * (nxB + 1) * (nyB + 1) * (nzB + 1)
     plane = 2 if nxB * nyB < 65536 else 4   # bytes per slice prefix sum (uint16 / uint32)
+    masks = 2 * 8 * nyB * nzB if runs else vox      # runs out and in, or the mask bytes in
     return {
-        "fields_x": 4 * vox + x1 + vox,              # B once, X1, eroded mask
-        "overlap_sat": vox + 2 * plane * vox + sat,  # mask in; slice prefixes out and back; table out
+        "fields_x": 4 * vox + x1 + (0 if runs else vox),   # B once, X1 (and the eroded mask)
+        "overlap_sat": masks + 2 * plane * vox + sat,      # masks; slice prefixes out and back; table out
         "y_forward": x1 + x2,
         "z_mac_inverse": x2 + spec / rotations_per_launch + y3,
         "y_inverse": y3 + y4,

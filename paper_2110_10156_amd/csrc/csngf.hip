@@ -695,26 +695,42 @@ int run_batch_t(csngf_ctx* c, const float* dB, const uint8_t* dmB, const int* ro
   V* buf1 = reinterpret_cast<V*>(c->d_buf1);
   V* buf2 = reinterpret_cast<V*>(c->d_buf2);
   const V* spec = reinterpret_cast<const V*>(c->d_spec);
-  // (the per-slot argmax keys are cleared by k_bounds on the side stream, before the join)
-  rc = launch_fields(c, true, dB, dmB, c->nB, rotq, buf1, c->buf1_slot, c->d_mask, c->mask_slot, nullptr, slots);
-  if (rc) return rc;
-  // overlap table on the side stream, concurrent with the y forward pass
-  HIPCHK(hipEventRecord(c->ev_fork, c->stream));
-  HIPCHK(hipStreamWaitEvent(c->side, c->ev_fork, 0));
-  {
+  // Overlap table on the side stream (it also clears the per-slot argmax keys, before the join).
+  // Without a user mask on B or A the moving masks are runs found from the rotations alone, so
+  // the table is built beside the field stage; otherwise the field stage writes the masks and
+  // the table is built from them beside the y forward pass.  The fork comes after the previous
+  // sequence's last reader of the masks, table, flags and work list on this stream.
+  const bool runs = dmB == nullptr && !c->masked;
+  auto overlap_table = [&]() -> int {
+    HIPCHK(hipEventRecord(c->ev_fork, c->stream));
+    HIPCHK(hipStreamWaitEvent(c->side, c->ev_fork, 0));
     const int nx = c->nB[0], ny = c->nB[1], nz = c->nB[2];
     hipStream_t st = c->side;
-    ev = prof_begin(c, st);
+    hipEvent_t e = prof_begin(c, st);
+    int2* d_runs = reinterpret_cast<int2*>(c->d_mask);   // the mask slots hold the runs instead
+    const long long runs_slot = c->mask_slot / (long long)sizeof(int2);
+    if (runs)
+      hipLaunchKernelGGL(k_mask_runs, dim3((ny * nz + kThreads - 1) / kThreads, slots), dim3(kThreads), 0, st, rotq,
+                         nx, ny, nz, d_runs, runs_slot);
     const dim3 gz(((nx + 1) * (ny + 1) + kThreads - 1) / kThreads, slots);
+    const dim3 gp((nx + 63) / 64, nz, slots);
     if ((long long)nx * ny < 65536) {   // 2-D prefix sums fit 16 bits
       uint16_t* pl16 = reinterpret_cast<uint16_t*>(c->d_plane);
-      hipLaunchKernelGGL(k_sat_planes<uint16_t>, dim3(nz, slots), dim3(kSatThreads), 0, st, c->d_mask, pl16, nx, ny,
-                         c->mask_slot, 2 * c->plane_slot);
+      if (runs)
+        hipLaunchKernelGGL(k_sat_planes_runs<uint16_t>, gp, dim3(64), 0, st, d_runs, pl16, nx, ny, runs_slot,
+                           2 * c->plane_slot);
+      else
+        hipLaunchKernelGGL(k_sat_planes<uint16_t>, dim3(nz, slots), dim3(kSatThreads), 0, st, c->d_mask, pl16, nx,
+                           ny, c->mask_slot, 2 * c->plane_slot);
       hipLaunchKernelGGL(k_sat_z<uint16_t>, gz, dim3(kThreads), 0, st, pl16, c->d_sat, nx, ny, nz, 2 * c->plane_slot,
                          c->sat_slot);
     } else {
-      hipLaunchKernelGGL(k_sat_planes<uint32_t>, dim3(nz, slots), dim3(kSatThreads), 0, st, c->d_mask, c->d_plane, nx,
-                         ny, c->mask_slot, c->plane_slot);
+      if (runs)
+        hipLaunchKernelGGL(k_sat_planes_runs<uint32_t>, gp, dim3(64), 0, st, d_runs, c->d_plane, nx, ny, runs_slot,
+                           c->plane_slot);
+      else
+        hipLaunchKernelGGL(k_sat_planes<uint32_t>, dim3(nz, slots), dim3(kSatThreads), 0, st, c->d_mask, c->d_plane,
+                           nx, ny, c->mask_slot, c->plane_slot);
       hipLaunchKernelGGL(k_sat_z<uint32_t>, gz, dim3(kThreads), 0, st, c->d_plane, c->d_sat, nx, ny, nz,
                          c->plane_slot, c->sat_slot);
     }
@@ -728,10 +744,16 @@ int run_batch_t(csngf_ctx* c, const float* dB, const uint8_t* dmB, const int* ro
       hipLaunchKernelGGL(k_worklist, dim3((items + kThreads - 1) / kThreads), dim3(kThreads), 0, st, c->d_flags,
                          c->flag_slot, c->Wd[1], c->Wd[2], 2 * kRowsC, slots, c->d_work + 64, c->d_work);
     }
-    prof_end(c, KT_SAT, ev, st);
+    prof_end(c, KT_SAT, e, st);
     LAUNCHCHK("k_sat");
     HIPCHK(hipEventRecord(c->ev_join, st));
-  }
+    return CSNGF_OK;
+  };
+  if (runs && (rc = overlap_table())) return rc;
+  rc = launch_fields(c, true, dB, dmB, c->nB, rotq, buf1, c->buf1_slot, runs ? nullptr : c->d_mask, c->mask_slot,
+                     nullptr, slots);
+  if (rc) return rc;
+  if (!runs && (rc = overlap_table())) return rc;
   // y forward: X1 [slot][f][z][y] -> X2 [slot][f][z][ky]
   // (X1 holds the interior rows and slices only: the fields vanish on the border planes)
   rc = launch_pencil(c, false, buf1, buf2, c->nB[1] - 2, c->P[1], 0, c->ply,
@@ -1108,7 +1130,8 @@ int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims
     const long long nvB = (long long)nB[0] * nB[1] * nB[2];
     c->buf1_slot = std::max((long long)c->nf * nB[2] * nB[1], (long long)c->Wd[2] * P[1]) * Hp;
     c->buf2_slot = std::max((long long)c->nf * nB[2] * P[1], (long long)c->Wd[2] * c->Wd[1]) * Hp;
-    c->mask_slot = (nvB + 255) / 256 * 256;
+    // the eroded masks, or their runs (one int2 per row) when they follow from the rotations
+    c->mask_slot = (std::max(nvB, 8LL * nB[1] * nB[2]) + 255) / 256 * 256;
     c->sat_slot = ((long long)(nB[0] + 1) * (nB[1] + 1) * (nB[2] + 1) + 63) / 64 * 64;
     c->flag_slot = ((long long)c->Wd[2] * (1 + c->Wd[1]) + 255) / 256 * 256;
     const int plane_bytes = (long long)nB[0] * nB[1] < 65536 ? 2 : 4;   // per voxel, as the SAT kernels use
@@ -1509,7 +1532,7 @@ extern "C" int csngf_footprint(csngf_dims dA, csngf_dims dB, const csngf_params*
   const long long buf1 = std::max((long long)nf * nB[2] * nB[1], (long long)Wd[2] * P[1]) * Hp;
   const long long buf2 = std::max((long long)nf * nB[2] * P[1], (long long)Wd[2] * Wd[1]) * Hp;
   const int plane_bytes = (long long)nB[0] * nB[1] < 65536 ? 2 : 4;
-  const long long per = el * (buf1 + buf2) + (nvB + 255) / 256 * 256 +
+  const long long per = el * (buf1 + buf2) + (std::max(nvB, 8LL * nB[1] * nB[2]) + 255) / 256 * 256 +
                         4 * (((long long)(nB[0] + 1) * (nB[1] + 1) * (nB[2] + 1) + 63) / 64 * 64) +
                         4 * (((nvB * plane_bytes + 3) / 4 + 63) / 64 * 64) +
                         ((long long)Wd[2] * (1 + Wd[1]) + 255) / 256 * 256 +

@@ -827,6 +827,91 @@ __global__ __launch_bounds__(kThreads) void k_zstore(
   }
 }
 
+// ------------------------------------------------------------------------------ moving mask runs
+// Without a user mask on B the eroded mask of B^ depends only on the rotation, and on each grid
+// row (y, z) it is one run of x.  A sample at grid point (x, y, z) is valid when its Q16 source
+// coordinate p_i 2^17 = sum_j k_ij (2 x_j - (n_j - 1)) + (n_i - 1) 2^16 lies in [0, (n_i - 1) 2^17]
+// on every axis i: the field stage's integer test.  Along a row p_i = a_i x + b_i (a_i = 2 k_i0),
+// so the valid samples form the run [lo, hi] that the three pairs of inequalities leave, found
+// with exact integer floor and ceiling divisions (no overflow: |a_i x + b_i| < 2^29).  A grid
+// point is in the eroded mask when it is interior and the samples at it and at its six
+// neighbours are valid (Sec. 3.1 masks; the central-difference stencil): the run of row (y, z)
+// shrunk by one at each end, intersected with the runs of rows (y +- 1, z) and (y, z +- 1).  For
+// finite B this is bit for bit the set of voxels whose fields the field stage keeps, so the
+// overlap table can be built from the rotations alone, beside the field stage.
+__device__ __forceinline__ long long floor_div(long long a, long long b) {   // b > 0
+  const long long q = a / b;
+  return (a % b != 0 && a < 0) ? q - 1 : q;
+}
+
+// the run of valid samples on row (y, z) of B's grid, empty (lo > hi) off the grid
+__device__ __forceinline__ int2 sample_run(const int* __restrict__ kq, int nx, int ny, int nz, int y, int z) {
+  if ((unsigned)y >= (unsigned)ny || (unsigned)z >= (unsigned)nz) return make_int2(1, 0);
+  const int n[3] = {nx, ny, nz};
+  const long long dy = 2 * y - (ny - 1), dz = 2 * z - (nz - 1);
+  long long lo = 0, hi = nx - 1;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const long long a = 2LL * kq[3 * i];
+    const long long b = -(long long)kq[3 * i] * (nx - 1) + (long long)kq[3 * i + 1] * dy +
+                        (long long)(n[i] - 1) * 65536 + (long long)kq[3 * i + 2] * dz;
+    const long long L = (long long)(n[i] - 1) << 17;
+    if (a == 0) {
+      if (b < 0 || b > L) return make_int2(1, 0);
+    } else if (a > 0) {   // -b <= a x <= L - b
+      lo = max(lo, -floor_div(b, a));
+      hi = min(hi, floor_div(L - b, a));
+    } else {              // b - L <= |a| x <= b
+      lo = max(lo, -floor_div(L - b, -a));
+      hi = min(hi, floor_div(b, -a));
+    }
+  }
+  return lo <= hi ? make_int2((int)lo, (int)hi) : make_int2(1, 0);
+}
+
+// runs[slot][z][y] = eroded-mask run of row (y, z) (empty: x > y); grid (ceil(ny nz / kThreads), slots)
+__global__ __launch_bounds__(kThreads) void k_mask_runs(const int* __restrict__ rotq, int nx, int ny, int nz,
+                                                        int2* __restrict__ runs, long long runs_sstride) {
+  const int slot = blockIdx.y;
+  const int t = (int)(blockIdx.x * kThreads + threadIdx.x);
+  if (t >= ny * nz) return;
+  const int z = t / ny, y = t - z * ny;
+  const int* kq = rotq + 9 * slot;
+  int lo = 1, hi = 0;
+  if (y >= 1 && y <= ny - 2 && z >= 1 && z <= nz - 2) {
+    const int2 c = sample_run(kq, nx, ny, nz, y, z);
+    lo = max(1, c.x + 1);
+    hi = min(nx - 2, c.y - 1);
+    const int2 r[4] = {sample_run(kq, nx, ny, nz, y - 1, z), sample_run(kq, nx, ny, nz, y + 1, z),
+                       sample_run(kq, nx, ny, nz, y, z - 1), sample_run(kq, nx, ny, nz, y, z + 1)};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      lo = max(lo, r[k].x);
+      hi = min(hi, r[k].y);
+    }
+  }
+  runs[slot * runs_sstride + t] = make_int2(lo, hi);
+}
+
+// Step 1 of the overlap table from the runs: plane[slot][z][y][x] = sum over rows y' <= y of the
+// run's points with x' <= x.  One wave per 64 columns of a slice, walking down its rows.
+template <typename PT>
+__global__ __launch_bounds__(64) void k_sat_planes_runs(const int2* __restrict__ runs, PT* __restrict__ plane,
+                                                        int nx, int ny, long long runs_sstride,
+                                                        long long plane_sstride) {
+  const int z = blockIdx.y, slot = blockIdx.z;
+  const int x = (int)(blockIdx.x * 64 + threadIdx.x);
+  if (x >= nx) return;
+  const int2* r = runs + slot * runs_sstride + (long long)z * ny;
+  PT* out = plane + slot * plane_sstride + (long long)z * ny * nx + x;
+  uint32_t col = 0;
+  for (int y = 0; y < ny; ++y) {
+    const int2 v = r[y];
+    col += (uint32_t)max(0, min(x - v.x + 1, v.y - v.x + 1));   // 0 for an empty run
+    out[(long long)y * nx] = (PT)col;
+  }
+}
+
 // ------------------------------------------------------------------------------ overlap SAT
 // sat[slot][(nz+1)][(ny+1)][(nx+1)], zero on index 0 of every axis:
 // sat[z+1][y+1][x+1] = sum of mask over [0..z] x [0..y] x [0..x].

@@ -35,6 +35,17 @@ def test_byte_model_kept_rows():
     assert abs(kb["z_mac_inverse"] - (x2 + 6 * 220 * 352 * 176 * 8 / 16 + 109 * 352 * 176 * 8)) < 1
 
 
+def test_byte_model_mask_runs():
+    # without user masks the moving masks are runs of x per row (8 B), and the field stage
+    # writes no mask; with a mask the field stage writes one byte per voxel and the table reads it
+    dims, P = (176, 176, 110), (352, 352, 220)
+    vox, x1 = 176 * 176 * 110, 6 * 108 * 174 * 176 * 8
+    r = bench.kernel_bytes(dims, dims, P, 16.0)
+    m = bench.kernel_bytes(dims, dims, P, 16.0, runs=False)
+    assert r["fields_x"] == 4 * vox + x1 and m["fields_x"] == 5 * vox + x1
+    assert m["overlap_sat"] - r["overlap_sat"] == vox - 2 * 8 * 176 * 110
+
+
 def test_more_than_one_gpu_exits_with_a_message():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)

@@ -2,7 +2,8 @@
 //
 // Data flow for one rotation slot (H = Px/2 stored half-spectrum bins along x, row pitch Hp):
 //   k_fields_x   B -> resample -> NGF -> mask -> 6 products -> x R2C    X1 [6][nz-2][ny-2][Hp]
-//   k_sat_*      eroded mask of B^ -> zero-bordered 3-D summed-area table (exact overlaps)
+//   k_mask_runs, k_sat_*   eroded mask of B^ (runs of x per row from the rotation, or the
+//                field stage's mask bytes) -> zero-bordered 3-D summed-area table (exact overlaps)
 //   k_pencil<F>  y forward, ny-2 nonzero rows -> Py                      X2 [6][nz-2][Py][Hp]
 //   k_zpass      per field: z forward (nz-2 nonzero -> Pz), multiply by A's conjugate spectrum,
 //                sum over fields; then z inverse of the sum              Y3 [Wz][Py][Hp]

@@ -834,29 +834,29 @@ __global__ __launch_bounds__(kThreads) void k_zstore(
 // coordinate p_i 2^17 = sum_j k_ij (2 x_j - (n_j - 1)) + (n_i - 1) 2^16 lies in [0, (n_i - 1) 2^17]
 // on every axis i: the field stage's integer test.  Along a row p_i = a_i x + b_i (a_i = 2 k_i0),
 // so the valid samples form the run [lo, hi] that the three pairs of inequalities leave, found
-// with exact integer floor and ceiling divisions (no overflow: |a_i x + b_i| < 2^29).  A grid
+// with exact integer floor and ceiling divisions (no overflow: |a_i x + b_i| < 2^30).  A grid
 // point is in the eroded mask when it is interior and the samples at it and at its six
 // neighbours are valid (Sec. 3.1 masks; the central-difference stencil): the run of row (y, z)
 // shrunk by one at each end, intersected with the runs of rows (y +- 1, z) and (y, z +- 1).  For
 // finite B this is bit for bit the set of voxels whose fields the field stage keeps, so the
 // overlap table can be built from the rotations alone, beside the field stage.
-__device__ __forceinline__ long long floor_div(long long a, long long b) {   // b > 0
-  const long long q = a / b;
+__device__ __forceinline__ int floor_div(int a, int b) {   // b > 0
+  const int q = a / b;
   return (a % b != 0 && a < 0) ? q - 1 : q;
 }
 
-// the run of valid samples on row (y, z) of B's grid, empty (lo > hi) off the grid
+// the run of valid samples on row (y, z) of B's grid, empty (lo > hi) off the grid.  32-bit
+// arithmetic suffices: |k| <= 2^17 (|R_ij| <= 2) and n <= 512 keep |b|, L - b below 2^30.
 __device__ __forceinline__ int2 sample_run(const int* __restrict__ kq, int nx, int ny, int nz, int y, int z) {
   if ((unsigned)y >= (unsigned)ny || (unsigned)z >= (unsigned)nz) return make_int2(1, 0);
   const int n[3] = {nx, ny, nz};
-  const long long dy = 2 * y - (ny - 1), dz = 2 * z - (nz - 1);
-  long long lo = 0, hi = nx - 1;
+  const int dy = 2 * y - (ny - 1), dz = 2 * z - (nz - 1);
+  int lo = 0, hi = nx - 1;
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    const long long a = 2LL * kq[3 * i];
-    const long long b = -(long long)kq[3 * i] * (nx - 1) + (long long)kq[3 * i + 1] * dy +
-                        (long long)(n[i] - 1) * 65536 + (long long)kq[3 * i + 2] * dz;
-    const long long L = (long long)(n[i] - 1) << 17;
+    const int a = 2 * kq[3 * i];
+    const int b = -kq[3 * i] * (nx - 1) + kq[3 * i + 1] * dy + (n[i] - 1) * 65536 + kq[3 * i + 2] * dz;
+    const int L = (n[i] - 1) << 17;
     if (a == 0) {
       if (b < 0 || b > L) return make_int2(1, 0);
     } else if (a > 0) {   // -b <= a x <= L - b
@@ -867,7 +867,7 @@ __device__ __forceinline__ int2 sample_run(const int* __restrict__ kq, int nx, i
       hi = min(hi, floor_div(b, -a));
     }
   }
-  return lo <= hi ? make_int2((int)lo, (int)hi) : make_int2(1, 0);
+  return lo <= hi ? make_int2(lo, hi) : make_int2(1, 0);
 }
 
 // runs[slot][z][y] = eroded-mask run of row (y, z) (empty: x > y); grid (ceil(ny nz / kThreads), slots)
@@ -906,6 +906,7 @@ __global__ __launch_bounds__(64) void k_sat_planes_runs(const int2* __restrict__
   const int2* r = runs + slot * runs_sstride + (long long)z * ny;
   PT* out = plane + slot * plane_sstride + (long long)z * ny * nx + x;
   uint32_t col = 0;
+#pragma unroll 8
   for (int y = 0; y < ny; ++y) {
     const int2 v = r[y];
     col += (uint32_t)max(0, min(x - v.x + 1, v.y - v.x + 1));   // 0 for an empty run

@@ -139,3 +139,49 @@ def test_option_sweep_full_maps(case):
         assert r == int(np.argmax(ob)), (r, ob)
     else:
         assert ob[r] >= ob.max() - TIE, (r, ob)
+
+
+GENERAL = [
+    np.array([[2.0, 0.0, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, -1.0]]),    # zero x-coefficients off x
+    0.6 * synth.axis_angle_matrix(np.array([0.2, 0.9, -0.4]), math.radians(35.0)),
+    np.clip(synth.axis_angle_matrix(np.array([1.0, 0.3, 0.2]), math.radians(20.0)) @ np.diag([1.9, 0.7, 1.3])
+            @ synth.axis_angle_matrix(np.array([-0.3, 0.5, 1.0]), math.radians(50.0)), -2.0, 2.0),
+    np.array([[1.0, 2.0, 0.0], [0.0, 1.0, 0.0], [-2.0, 0.0, 1.0]]),    # extreme entries, mask on B
+]
+
+
+@pytest.mark.parametrize("case", range(len(GENERAL)))
+def test_general_linear_maps_full_maps(case):
+    """The entry points take any finite matrix with |M_ij| <= 2 (Q16 entries up to 2^17): the
+    eroded masks' integer bounds and the resample must hold at those extremes, scaled, sheared,
+    reflected and with zero coefficients, on the run-based table (no mask) and the byte-mask
+    table (mask on B)."""
+    from scipy.ndimage import gaussian_filter
+    rng = np.random.default_rng(1200 + case)
+    sa = (26, 22, 30) if case % 2 else (30, 24, 28)
+    sb = (24, 25, 29)
+    A = gaussian_filter(rng.random(sa), 1.0).astype(np.float32)
+    B = gaussian_filter(rng.random(sb), 1.0).astype(np.float32)
+    mb = (rng.random(sb) > 0.03).astype(np.uint8) if case == 3 else None
+    M = GENERAL[case]
+    _say("general", case, np.round(M, 3).tolist(), "mask on B" if mb is not None else "")
+    with bd.Context(A, bd.dims_of(B), gamma=0.25) as ctx:
+        P = tuple(ctx.info().pad)
+        Cg, Ng = ctx.evaluate_map(B, M, mask_b=mb)
+        per, best = ctx.evaluate(B, np.stack([M, M]), mask_b=mb)
+    fa = O.fixed_fields(A)
+    fb = O.moving_fields(B, O.quantize_rotation(M), None if mb is None else mb.astype(bool))
+    S, N = O.correlation_maps_fft(fa, fb, P)
+    Co, _ = O.normalise(S, N, int(fa.mask.sum()), int(fb.mask.sum()), 0.25)
+    assert np.array_equal(Ng, N), f"general{case}: overlap counts differ"
+    vg, vo = np.isfinite(Cg), np.isfinite(Co)
+    assert np.array_equal(vg, vo), f"general{case}: validity differs"
+    _say("general", case, "moving mask voxels", int(fb.mask.sum()), "valid", int(vo.sum()))
+    if vo.any():
+        err = float(np.max(np.abs(Cg[vo].astype(np.float64) - Co[vo])))
+        _say("general", case, "max|dC| =", err)
+        assert err <= CTOL
+        gg = int(np.argmax(np.where(vg, Cg, -np.inf)))
+        assert per[0].valid and per[0].score == Cg.flat[gg] and best.rot_index == 0
+    else:
+        assert not per[0].valid and best.rot_index == -1

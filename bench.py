@@ -116,7 +116,7 @@ def zpass_flops(nB, P, nf=6):
     return Py * (Px // 2) * (nf * (transform_flops(Pz, pruned) + 8 * Pz) + transform_flops(Pz, False))
 
 
-def survey_yardstick(nA, nB, P):
+def paper_yardstick(nA, nB, P):
     """The fixed per-rotation byte model of the method as the paper states it (Sec. 3.1: 7
     forward and 2 inverse zero-padded real 3-D FFTs per rotation with A's 7 spectra cached and
     read once per rotation), as three pruned complex64 pencil passes each: x writes and y
@@ -619,7 +619,7 @@ def main():
 
     lat_ms = np.array(lat) * 1e3
     yard = sum(kb.values())
-    survey_yard = survey_yardstick(pair.dims_a, pair.dims_b, tuple(info.pad))
+    paper_yard = paper_yardstick(pair.dims_a, pair.dims_b, tuple(info.pad))
     out = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -648,8 +648,8 @@ def main():
         "path_bytes_per_rotation": yard,
         "path_bytes_kept_rows": kept is not None,
         "path_hbm_frac": round(yard * value / (HBM_PEAK_GBS * 1e9), 4),
-        "yardstick_bytes_per_rotation": survey_yard,
-        "yardstick_frac": round(survey_yard * value / (HBM_PEAK_GBS * 1e9), 4),
+        "yardstick_bytes_per_rotation": paper_yard,
+        "yardstick_frac": round(paper_yard * value / (HBM_PEAK_GBS * 1e9), 4),
         "yardstick_what": "fixed byte model of the paper's 7 forward + 2 inverse FFTs with A's 7 spectra read per "
                           "rotation; this design skips the mask transforms, shares A's spectra per launch and "
                           "prunes inverse rows, so this fraction can exceed what its own kernels move",

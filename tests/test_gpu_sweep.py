@@ -11,6 +11,7 @@ cases use gamma >= 0.25 (where N is a sizeable share of a mask); gamma = 0 and 0
 the FP64 correlation, which meets the bar at every overlap.
 """
 import math
+import os
 import sys
 
 import numpy as np
@@ -24,7 +25,7 @@ pytestmark = pytest.mark.gpu
 
 CTOL = 1e-4
 TIE = 2e-4
-NCASES = 48
+NCASES = int(os.environ.get("CSNGF_SWEEP_CASES", "48"))   # more cases on request
 
 
 def _say(*a):

@@ -74,7 +74,11 @@ constexpr int kRowsX = 8;    // rows per workgroup in the field stage
 #ifndef CSNGF_HU
 #define CSNGF_HU 1
 #endif
+#ifndef CSNGF_GBW
+#define CSNGF_GBW 16
+#endif
 constexpr int kGatherGroup = CSNGF_HU;
+constexpr int kGatherBW = CSNGF_GBW;   // columns per block of the field stage's sample-to-thread map
 #ifndef CSNGF_ROWSC
 #define CSNGF_ROWSC 4
 #endif
@@ -230,12 +234,18 @@ __global__ __launch_bounds__(kThreadsF) void k_fields_x(
   // the length is compiled in (the host checks nx against Px before launching)
   constexpr int NXM = LC > 0 ? (HALF ? LC / 2 : LC) : kMaxLen;
   constexpr int PXM = LC > 0 ? LC : kMaxLen;
-  constexpr int ME = (HR * NXM + T - 1) / T;          // halo-plane samples per thread
+  // halo-plane samples go to the threads in blocks of kGatherBW columns x HR rows, so a wave
+  // gathers a compact patch of the plane (16 x 4 samples) whose rotated source footprint in B
+  // spans few cache lines; the LDS plane stays row-major
+  constexpr int BW = kGatherBW;
+  constexpr int NXP = (NXM + BW - 1) / BW * BW;
+  constexpr int ME = (HR * NXP + T - 1) / T;          // halo-plane samples per thread
   constexpr int MN = (TY * NXM + T - 1) / T;          // slice voxels per thread
   constexpr int MU = (TY * (PXM / 2) + T - 1) / T;    // half-spectrum bins per thread
   extern __shared__ __align__(16) unsigned char smem[];
   const int Px = pl.L;
   const int plane = HR * nx;
+  const int plane_el = (nx + BW - 1) / BW * BW * HR;   // sample slots, padding columns included
   using S = scalar_t<V>;
   V* tw = reinterpret_cast<V*>(smem);
   V* buf = reinterpret_cast<V*>(smem + align16(sizeof(V) * Px));
@@ -268,13 +278,16 @@ __global__ __launch_bounds__(kThreadsF) void k_fields_x(
   // grid get a coordinate far below 0, so the box test rejects them.
   // fixed: the voxel's offset within a plane, -1 outside the grid.
   const int* kq = MOVING ? rotq + 9 * slot : nullptr;
-  int cx[ME], cy[ME], cz[ME];
+  int cx[ME], cy[ME], cz[ME], pe[ME];   // pe: the sample's LDS index in the plane, -1 for none
 #pragma unroll
   for (int u = 0; u < ME; ++u) {
     const int e = (int)tid + u * T;
-    const int x = e % nx, r = e / nx;
+    const int b = e / (BW * HR), w = e - b * (BW * HR);
+    const int r = w / BW, x = b * BW + (w - r * BW);
     const int yy = y0 + r - 1;
-    const bool in = e < plane && yy >= 0 && yy < ny;
+    const bool slot_ok = e < plane_el && x < nx;
+    pe[u] = slot_ok ? r * nx + x : -1;
+    const bool in = slot_ok && yy >= 0 && yy < ny;
     if (MOVING) {
       const int dx = 2 * x - (nx - 1), dy = 2 * yy - (ny - 1);
       cx[u] = in ? kq[0] * dx + kq[1] * dy + (nx - 1) * 65536 : -(1 << 30);
@@ -298,7 +311,7 @@ __global__ __launch_bounds__(kThreadsF) void k_fields_x(
     constexpr int HU = kGatherGroup;
 #pragma unroll
     for (int u0 = 0; u0 < ME; u0 += HU) {
-      if (u0 * T >= plane) break;
+      if (u0 * T >= plane_el) break;
       float v[HU];
       if constexpr (MOVING) {
         float2 c[HU][4];
@@ -360,8 +373,8 @@ __global__ __launch_bounds__(kThreadsF) void k_fields_x(
       }
 #pragma unroll
       for (int h = 0; h < HU; ++h) {
-        const int e = (int)tid + (u0 + h) * T;
-        if (u0 + h < ME && e < plane) pv[e] = v[h];
+        const int u = u0 + h < ME ? u0 + h : ME - 1;
+        if (u0 + h < ME && pe[u] >= 0) pv[pe[u]] = v[h];
       }
     }
   };
@@ -393,6 +406,7 @@ __global__ __launch_bounds__(kThreadsF) void k_fields_x(
     // registers
 #pragma unroll
     for (int u = 0; u < ME; ++u) {
+      pe[u] = (int)opaque_idx((unsigned)pe[u]);
       cx[u] = (int)opaque_idx((unsigned)cx[u]);
       if (MOVING) {
         cy[u] = (int)opaque_idx((unsigned)cy[u]);

@@ -125,7 +125,8 @@ typedef struct {
   int32_t map_dims[3];     /* W = n_A + n_B - 1 per axis (x, y, z) */
   int32_t reserved;
   int64_t count_a;         /* |M_A| after erosion */
-  int64_t spectra_bytes;   /* device bytes held for A's conjugate spectra */
+  int64_t spectra_bytes;   /* device bytes held per context: A's conjugate spectra and the
+                              moving volume's brick copy (5^3 values per 4^3 cells) */
   int64_t workspace_bytes; /* device bytes held for rotation workspaces */
 } csngf_info;
 
@@ -219,8 +220,9 @@ int csngf_smooth_downsample_noalloc(const float* vol, csngf_dims d, float sigma,
                                     csngf_dims* out_dims, void* stream);
 
 /* Device memory a context would hold, without allocating anything (admission control of a
- * server): *spectra_bytes for A's resident spectra, *slot_bytes per rotation slot of
- * workspace (a context holds batch slots), and the FFT size pad_out[3] that would be used.
+ * server): *spectra_bytes per context (A's resident spectra and B's brick copy),
+ * *slot_bytes per rotation slot of workspace (a context holds batch slots), and the FFT size
+ * pad_out[3] that would be used.
  * Any output may be NULL. */
 int csngf_footprint(csngf_dims dA, csngf_dims dB, const csngf_params* p, int64_t* spectra_bytes,
                     int64_t* slot_bytes, int32_t* pad_out);

@@ -238,6 +238,8 @@ struct csngf_ctx {
   int* d_rot = nullptr;
   int rot_cap = 0;
   float* d_B = nullptr;
+  float* d_Bb = nullptr;        // B in bricks of 4^3 cells (the moving side's gathers)
+  long long brick_bytes = 0;
   uint8_t* d_mB = nullptr;
   int* d_flag = nullptr;
   RotResultDev* h_res = nullptr;
@@ -359,6 +361,7 @@ void release(csngf_ctx* c) {
   dfree(c->d_res);
   dfree(c->d_rot);
   dfree(c->d_B);
+  dfree(c->d_Bb);
   dfree(c->d_mB);
   dfree(c->d_flag);
   dfree(c->d_rot_stage);
@@ -920,6 +923,19 @@ int ensure_rot_capacity(csngf_ctx* c, int n) {
   return CSNGF_OK;
 }
 
+// B's copy in bricks (k_brick): values per volume, and the launch
+long long brick_floats(const int* n3) {
+  return (long long)kBrickVals * brick_count(n3[0]) * brick_count(n3[1]) * brick_count(n3[2]);
+}
+
+int launch_brick(hipStream_t s, const float* vol, const int* n3, float* out) {
+  const long long total = brick_floats(n3);
+  hipLaunchKernelGGL(k_brick, dim3((unsigned)((total + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, vol, n3[0],
+                     n3[1], n3[2], out, total);
+  LAUNCHCHK("k_brick");
+  return CSNGF_OK;
+}
+
 // Stage the moving volume (and mask) on the device; device-pointer inputs are checked for
 // non-finite values by a kernel whose flag is read after the call's final synchronisation.
 int stage_moving(csngf_ctx* c, const float* B, const uint8_t* maskB, const float** dB, const uint8_t** dmB) {
@@ -930,7 +946,8 @@ int stage_moving(csngf_ctx* c, const float* B, const uint8_t* maskB, const float
     HIPCHK(hipMemsetAsync(c->d_flag, 0, sizeof(int), c->stream));
     hipLaunchKernelGGL(k_check_finite, dim3(1024), dim3(256), 0, c->stream, B, (long long)nv, c->d_flag);
     LAUNCHCHK("k_check_finite");
-    return CSNGF_OK;
+    *dB = c->d_Bb;   // the field stage gathers from the brick copy
+    return launch_brick(c->stream, B, c->nB, c->d_Bb);
   }
   if (!all_finite(B, nv)) return fail(CSNGF_E_INVALID_ARG, "moving volume B has a non-finite value");
   if (!c->d_B) {
@@ -938,7 +955,9 @@ int stage_moving(csngf_ctx* c, const float* B, const uint8_t* maskB, const float
     if (rc) return rc;
   }
   HIPCHK(hipMemcpyAsync(c->d_B, B, sizeof(float) * nv, hipMemcpyHostToDevice, c->stream));
-  *dB = c->d_B;
+  int brc = launch_brick(c->stream, c->d_B, c->nB, c->d_Bb);
+  if (brc) return brc;
+  *dB = c->d_Bb;   // the field stage gathers from the brick copy
   *dmB = nullptr;
   if (maskB) {
     if (!c->d_mB) {
@@ -1164,6 +1183,8 @@ int csngf_create(const float* A, csngf_dims dA, const uint8_t* maskA, csngf_dims
         hipEventCreateWithFlags(&c->ev_zpack, hipEventDisableTiming) != hipSuccess)
       return bail(hip_fail(hipGetLastError(), "side stream"));
     if ((rc = dalloc(&c->d_mask, (size_t)c->mask_slot * batch))) return bail(rc);
+    c->brick_bytes = (long long)sizeof(float) * brick_floats(nB);
+    if ((rc = dalloc(&c->d_Bb, (size_t)c->brick_bytes))) return bail(rc);
     if ((rc = dalloc(&c->d_sat, 4 * (size_t)c->sat_slot * batch))) return bail(rc);
     if ((rc = dalloc(&c->d_flags, (size_t)c->flag_slot * batch))) return bail(rc);
     if ((rc = dalloc(&c->d_keys, sizeof(unsigned long long) * batch))) return bail(rc);
@@ -1207,7 +1228,7 @@ int csngf_get_info(const csngf_ctx* c, csngf_info* o) {
   }
   o->batch = c->batch;
   o->count_a = c->count_a;
-  o->spectra_bytes = c->spec_bytes;
+  o->spectra_bytes = c->spec_bytes + c->brick_bytes;
   o->workspace_bytes = c->workspace_bytes;
   return CSNGF_OK;
 }
@@ -1537,7 +1558,7 @@ extern "C" int csngf_footprint(csngf_dims dA, csngf_dims dB, const csngf_params*
                         4 * (((nvB * plane_bytes + 3) / 4 + 63) / 64 * 64) +
                         ((long long)Wd[2] * (1 + Wd[1]) + 255) / 256 * 256 +
                         4LL * Wd[2] * ((Wd[1] + 2 * kRowsC - 1) / (2 * kRowsC));
-  if (spectra_bytes) *spectra_bytes = el * nf * P[2] * P[1] * Hp;
+  if (spectra_bytes) *spectra_bytes = el * nf * P[2] * P[1] * Hp + (long long)sizeof(float) * brick_floats(nB);
   if (slot_bytes) *slot_bytes = per;
   if (pad_out)
     for (int i = 0; i < 3; ++i) pad_out[i] = P[i];
@@ -1753,7 +1774,13 @@ int csngf_debug_fields(const float* vol, const uint8_t* vmask, csngf_dims d, con
     if ((rc = dalloc(&dmask, nv))) return done(rc);
     owned.push_back(dmask);
   }
-  rc = launch_fields(&tmp, R9 != nullptr, dvol, dvm, n3, drot, x1, 0, dmask, 0, dprod, 1);
+  float* gvol = dvol;   // the moving side gathers from a brick copy
+  if (R9) {
+    if ((rc = dalloc(&gvol, sizeof(float) * brick_floats(n3)))) return done(rc);
+    owned.push_back(gvol);
+    if ((rc = launch_brick(nullptr, dvol, n3, gvol))) return done(rc);
+  }
+  rc = launch_fields(&tmp, R9 != nullptr, gvol, dvm, n3, drot, x1, 0, dmask, 0, dprod, 1);
   if (rc) return done(rc);
   if (hipDeviceSynchronize() != hipSuccess) return done(hip_fail(hipGetLastError(), "k_fields_x"));
   if (!dev) {

@@ -197,6 +197,28 @@ __device__ __forceinline__ uint32_t offv_if(bool ok, int row, uint32_t rsb, int 
   return ok ? o : kNoOff;
 }
 
+// ------------------------------------------------------------------------------ B in bricks
+// The moving side gathers B through a copy in bricks of 4 x 4 x 4 trilinear cells with their
+// upper corners: 5 x 5 x 5 values (x fastest), brick (bx, by, bz) holding B at
+// (4 bx + lx, 4 by + ly, 4 bz + lz), lx, ly, lz = 0..4, clamped to the grid.  Every cell's 8
+// corners then lie in one 500-byte brick, as (x, x+1) pairs 0, 5, 25 and 30 values apart, and
+// a wave's gathers over a rotated patch touch few cache lines.  nbx = ceil((nx - 1) / 4)
+// bricks per axis cover the nx - 1 cells.
+constexpr int kBrickVals = 125;
+__host__ __device__ constexpr int brick_count(int n) { return (n + 2) / 4; }   // ceil((n - 1) / 4)
+
+__global__ __launch_bounds__(kThreads) void k_brick(const float* __restrict__ B, int nx, int ny, int nz,
+                                                    float* __restrict__ out, long long total) {
+  const long long t = (long long)blockIdx.x * kThreads + threadIdx.x;
+  if (t >= total) return;
+  const int nbx = brick_count(nx), nby = brick_count(ny);
+  const int b = (int)(t / kBrickVals), l = (int)(t - (long long)b * kBrickVals);
+  const int lz = l / 25, ly = (l - 25 * lz) / 5, lx = l - 25 * lz - 5 * ly;
+  const int bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
+  const int x = min(4 * bx + lx, nx - 1), y = min(4 * by + ly, ny - 1), z = min(4 * bz + lz, nz - 1);
+  out[t] = B[((long long)z * ny + y) * nx + x];
+}
+
 // ------------------------------------------------------------------------------ x pass
 // One workgroup: rows y0 .. y0+kRowsX-1 of slices z0 .. z0+tz-1 of one rotation slot,
 // marching along z with a ring of 3 sampled halo planes (rows y0-1 .. y0+kRowsX) in LDS, so
@@ -270,7 +292,9 @@ __global__ __launch_bounds__(kThreadsF) void k_fields_x(
   const unsigned tid = threadIdx.x;
   const float qnan = __builtin_nanf("");
 
-  const RView src(vol, 4LL * nv);   // the volume (its mask and the mask output: where used)
+  // the volume: on the moving side its copy in bricks, on the fixed side as laid out
+  const int nbx = brick_count(nx), nby = brick_count(ny);
+  const RView src(vol, MOVING ? 4LL * kBrickVals * nbx * nby * brick_count(nz) : 4LL * nv);
 
   // ---- per-thread decode of the halo-plane samples
   // moving: source coordinate p 2^17 = k (2 x - (n - 1)) + (n - 1) 2^16 per axis (Q16 matrix k),
@@ -332,16 +356,20 @@ __global__ __launch_bounds__(kThreadsF) void k_fields_x(
           if (ix == nx - 1) { ix = nx - 2; fx[h] = 1.0f; }
           if (iy == ny - 1) { iy = ny - 2; fy[h] = 1.0f; }
           if (iz == nz - 1) { iz = nz - 2; fz[h] = 1.0f; }
-          const unsigned o = mad24u(mad24u((unsigned)iz, ny, (unsigned)iy), nx, (unsigned)ix);
-          const unsigned o4 = ok ? 4u * o : kNoOff;
+          // the cell's brick and its place in it
+          const unsigned brick = mad24u(mad24u((unsigned)iz >> 2, nby, (unsigned)iy >> 2), nbx, (unsigned)ix >> 2);
+          const unsigned ob = mad24u(brick, kBrickVals,
+                                     mad24u(mad24u((unsigned)iz & 3u, 5, (unsigned)iy & 3u), 5, (unsigned)ix & 3u));
+          const unsigned o4 = ok ? 4u * ob : kNoOff;
           c[h][0] = src.ld2(o4, 0);          // corners (x, x+1) of the 4 (y, z) edges
-          c[h][1] = src.ld2(o4, sy4);
-          c[h][2] = src.ld2(o4, sz4);
-          c[h][3] = src.ld2(o4, sz4 + sy4);
+          c[h][1] = src.ld2(o4, 4 * 5);
+          c[h][2] = src.ld2(o4, 4 * 25);
+          c[h][3] = src.ld2(o4, 4 * 30);
           good[h] = ok;
           if (umask) {
             // all 8 corners inside the mask: the smallest of the 8 bytes is nonzero
             const RView srcm(umask, nv);
+            const unsigned o = mad24u(mad24u((unsigned)iz, ny, (unsigned)iy), nx, (unsigned)ix);
             const unsigned om = ok ? o : kNoOff;
             unsigned mn = min(srcm.ld1(om, 0), srcm.ld1(om + 1, 0));
             mn = min(mn, min(srcm.ld1(om, sy4 / 4), srcm.ld1(om + 1, sy4 / 4)));

@@ -152,6 +152,23 @@ def test_automatic_fft_size_prefers_fixed_length_plans():
     assert bd.footprint((100, 100, 100), (100, 100, 100), pad=(200, 200, 200))[2] == (200, 200, 200)
 
 
+def test_footprint_per_context_and_per_slot_bytes():
+    """The per-context figure is A's six conjugate spectra ([6][Pz][Py][Hp] complex64) plus B's
+    brick copy (5^3 floats per brick of 4^3 cells, ceil((n - 1) / 4) bricks per axis); the
+    per-slot figure grows with the rotation workspaces and is the same for FP32 and FP64 apart
+    from the transform buffers."""
+    spec, slot, P = bd.footprint((176, 176, 110), (176, 176, 110))
+    assert P == (352, 352, 220)
+    bricks = 44 * 44 * 28
+    assert spec == 6 * 220 * 352 * 176 * 8 + 4 * 125 * bricks
+    # X1/Y3 and X2/Y4 buffers dominate a slot: at least (6 * 108 * 352 + 6 * 108 * 174) * 176 bins
+    assert slot >= 8 * 6 * 108 * (352 + 174) * 176
+    # a 3-voxel axis still gets one brick; rows hold Px/2 bins padded to the 16-bin tile
+    spec3, _, P3 = bd.footprint((3, 3, 3), (3, 3, 3))
+    hp = -(-(P3[0] // 2) // 16) * 16
+    assert spec3 == 6 * P3[2] * P3[1] * hp * 8 + 4 * 125
+
+
 def test_noalloc_pyramid_rejects_bad_and_oversized_arguments():
     """The allocation-free pyramid entry point validates before touching a device: NULL
     pointers, bad sigma or factor, and inputs whose intermediates exceed the fixed scratch."""

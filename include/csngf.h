@@ -228,10 +228,10 @@ int csngf_footprint(csngf_dims dA, csngf_dims dB, const csngf_params* p, int64_t
                     int64_t* slot_bytes, int32_t* pad_out);
 
 /* Autotuner: for the shapes of A and B and the base params (eps, gamma, flags), time the
- * candidate configurations - FFT size per axis (the smallest supported length and, if that
- * has no compile-time plan, the smallest one that has, within 1.5x) and rotation slots in
- * flight (the automatic choice, half and double), then, holding the best of those, z slices
- * per field-stage workgroup (4, 8, 16) and then final-pass workgroups (2048 .. 16384) - on
+ * candidate configurations - FFT size per axis (the smallest supported length and the next
+ * length with a compile-time plan within 1.5x, every combination, with the automatic slot
+ * count), then at the best size the rotation slots in flight (half and double), then z
+ * slices per field-stage workgroup (4, 8, 16) and then final-pass workgroups (2048 .. 16384) - on
  * n_probe deterministic random rotations, and return the fastest in *best (pad, batch,
  * slices and final_groups set) and its rate in rotations/s (*best_rate may be NULL).  Creates
  * and destroys contexts; results do not depend on the choice (any FFT size >= n_A + n_B - 1

@@ -92,14 +92,20 @@ def corner_distance(A_shape_zyx, B_shape_zyx, R_true, shift_true, R_found, shift
 
 
 class GpuEvaluator:
-    """Scores candidate rotations of one pyramid level with libcsngf (device-resident volumes)."""
+    """Scores candidate rotations of one pyramid level with libcsngf (device-resident volumes).
 
-    def __init__(self, measure="squared", gamma=0.5, eps=1e-5, device="cuda:0"):
+    tune: run the library's autotuner once per pair of level shapes (FFT size, rotation slots,
+    launch shapes; a few hundred milliseconds per shape, cached for later alignments) and
+    evaluate with its choice; the scores do not depend on it."""
+
+    def __init__(self, measure="squared", gamma=0.5, eps=1e-5, device="cuda:0", tune=False):
         import torch
         from . import binding
         self.torch, self.bd = torch, binding
         self.measure, self.gamma, self.eps = measure, gamma, eps
         self.device = torch.device(device)
+        self.tune = tune
+        self.tuned = {}   # (A level shape, B level shape) -> Context keywords
 
     def level(self, A, B, sigma, d):
         tA = A if not isinstance(A, np.ndarray) else self.torch.from_numpy(np.ascontiguousarray(A)).to(self.device)
@@ -111,11 +117,17 @@ class GpuEvaluator:
 
     def score(self, Ak, Bk, Rs):
         # a level with few candidates (the last re-scores 1) needs no more rotation slots than
-        # it has rotations; otherwise the library sizes the slots
-        slots = len(Rs) if len(Rs) < 16 else 0
+        # it has rotations; otherwise the library sizes the slots, or the tuned choice does
+        kw = {"batch": len(Rs) if len(Rs) < 16 else 0}
+        if self.tune and len(Rs) >= 16:
+            key = (tuple(Ak.shape), tuple(Bk.shape))
+            if key not in self.tuned:
+                self.tuned[key] = self.bd.autotune(Ak, Bk, n_probe=64, measure=self.measure, gamma=self.gamma,
+                                                   eps=self.eps, graphs=True)[0]
+            kw = dict(self.tuned[key])
         # (graph replay: a level runs tens of identical launch sequences)
         with self.bd.Context(Ak, self.bd.dims_of(Bk), gamma=self.gamma, eps=self.eps, measure=self.measure,
-                             batch=slots, graphs=True) as ctx:
+                             graphs=True, **kw) as ctx:
             per, _ = ctx.evaluate(Bk, Rs)
         return ([p.score if p.valid else -np.inf for p in per], [tuple(p.shift) for p in per])
 

@@ -1603,8 +1603,10 @@ extern "C" int csngf_autotune(const float* A, csngf_dims dA, const float* B, csn
     const int s0 = smallest_supported_at_least(need);
     if (s0 < 0) return fail(CSNGF_E_UNSUPPORTED, "no supported FFT size >= n_A + n_B - 1");
     cand[i].push_back(s0);
+    // and the next length with a compile-time plan within 1.5x: a longer length of cheaper
+    // radices (say 128 = 8 4 4 for 110 = 11 5 2) can be the faster transform
     for (int L = s0 + 1; L <= kMaxLen && L <= need + need / 2; ++L)
-      if (fast_length(L) && !fast_length(s0)) {
+      if (fast_length(L)) {
         cand[i].push_back(L);
         break;
       }
@@ -1628,6 +1630,7 @@ extern "C" int csngf_autotune(const float* A, csngf_dims dA, const float* B, csn
     csngf_destroy(ctx);
     return rate;
   };
+  // FFT sizes with the automatic slot count, then half and double the slots at the best size
   for (int px : cand[0])
     for (int py : cand[1])
       for (int pz : cand[2]) {
@@ -1639,15 +1642,19 @@ extern "C" int csngf_autotune(const float* A, csngf_dims dA, const float* B, csn
         int b0 = 0;
         const double r0 = probe(q, &b0);
         if (r0 > best_r) { best_r = r0; best_p = q; best_p.batch = b0; }
-        for (int b : {b0 / 2, b0 * 2}) {
-          if (b < 1 || b > 64 || b == b0) continue;
-          q.batch = b;
-          int bu = 0;
-          const double r = probe(q, &bu);
-          if (r > best_r) { best_r = r; best_p = q; }
-        }
       }
   if (best_r <= 0) return fail(CSNGF_E_DEVICE, "no candidate configuration could be evaluated");
+  {
+    const csngf_params base_b = best_p;
+    for (int b : {base_b.batch / 2, base_b.batch * 2}) {
+      if (b < 1 || b > 64) continue;
+      csngf_params q = base_b;
+      q.batch = b;
+      int bu = 0;
+      const double r = probe(q, &bu);
+      if (r > best_r) { best_r = r; best_p = q; }
+    }
+  }
   // launch shapes, one knob at a time from the best FFT size and slot count
   {
     const csngf_params base_p = best_p;

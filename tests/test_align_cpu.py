@@ -83,3 +83,46 @@ def test_oracle_driven_search_recovers_a_shift_and_small_rotation():
     dE = align.corner_distance(pair.A.shape, B.shape, R_true, tuple(t), res.R, res.shift)
     assert dE < 3.0, (res.euler_deg, res.shift, dE)
     assert len(res.levels) == 2 and res.levels[0].candidates == 61 and res.levels[1].candidates == 23
+
+
+def test_gpu_evaluator_tunes_once_per_level_shape(monkeypatch):
+    """GpuEvaluator(tune=True) asks the autotuner once per pair of level shapes and creates
+    every context of that shape with its choice; levels with few candidates keep one slot per
+    candidate; tune=False passes only the slot choice.  (Library calls are stand-ins here.)"""
+    import types
+    calls, made = [], []
+
+    class Ctx:
+        def __init__(self, A, dims_b, **kw):
+            made.append(kw)
+
+        def __enter__(self):
+            return self
+
+        def __exit__(self, *a):
+            return False
+
+        def evaluate(self, B, Rs):
+            p = types.SimpleNamespace(valid=True, score=0.5, shift=(0, 0, 0))
+            return [p] * len(Rs), None
+
+    def autotune(A, B, **kw):
+        calls.append((tuple(A.shape), tuple(B.shape)))
+        return {"pad": (96, 96, 64), "batch": 32, "slices": 4, "final_groups": 4096}, 1.0
+
+    ev = align.GpuEvaluator.__new__(align.GpuEvaluator)
+    ev.bd = types.SimpleNamespace(Context=Ctx, autotune=autotune, dims_of=lambda v: tuple(v.shape))
+    ev.measure, ev.gamma, ev.eps, ev.tune, ev.tuned = "squared", 0.5, 1e-5, True, {}
+    a, b = np.zeros((28, 44, 44)), np.zeros((28, 44, 44))
+    R = np.tile(np.eye(3), (20, 1, 1))
+    ev.score(a, b, R)
+    ev.score(a, b, R)
+    ev.score(a, b, R[:3])                      # few candidates: no tuning, one slot each
+    ev.score(np.zeros((55, 88, 88)), np.zeros((55, 88, 88)), R)
+    assert calls == [((28, 44, 44), (28, 44, 44)), ((55, 88, 88), (55, 88, 88))]
+    assert made[0]["pad"] == (96, 96, 64) and made[0]["batch"] == 32 and made[1] == made[0]
+    assert made[2]["batch"] == 3 and "pad" not in made[2]
+    assert all(m["graphs"] for m in made)
+    ev.tune, ev.tuned, made[:] = False, {}, []
+    ev.score(a, b, R)
+    assert made == [{"gamma": 0.5, "eps": 1e-5, "measure": "squared", "graphs": True, "batch": 0}]

@@ -42,7 +42,7 @@ constexpr int kTileW = 16;     // adjacent x-bins per pencil tile in the z pass 
 #define CSNGF_TF 512
 #endif
 #ifndef CSNGF_TPF
-#define CSNGF_TPF 256
+#define CSNGF_TPF 512   // y forward: 0.087 -> 0.084 ms per rotation against 256 (more waves in flight)
 #endif
 #ifndef CSNGF_TPI
 #define CSNGF_TPI 512
